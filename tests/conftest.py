@@ -1,0 +1,20 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer CPU-only oracle checks")
+
+
+@pytest.fixture(scope="session")
+def gpu_lib():
+    """The loaded HIP library; GPU tests fail loudly if it is not built."""
+    from paper_2309_08235_amd import priest
+    return priest.lib()
