@@ -1,0 +1,186 @@
+"""Benchmark of the PRIEST planner on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step = one full plan (Alg. 1) of the paper-scale 2D workload: N = 1000
+samples, 20 CEM iterations of 100 projection iterations each, M = 50
+circular obstacles (30 static, 20 constant-velocity), K = 100 steps, FP32,
+every sub-step (draw, project, residual, cost, top-k twice, refit,
+Cholesky) on the GPU.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: the metric is projected samples x iterations per
+second (N * n_proj_iters * n_cem per plan), plus plans/s and per-plan
+latency percentiles, the roofline position of the projection kernel and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def projection_flops(dims: int, nv: int, K: int, M: int) -> float:
+    """Algorithmic FLOPs of one projection iteration for one sample (lower
+    bound: obstacle pairs counted at their no-contact cost).
+
+      forward rows p, v, a      : 3 dims nv K FMA        -> 6 dims nv K
+      obstacle pair (t, j)      : centre at t (dims FMA), offset (dims),
+                                  scaled squared distance (2 dims + 1), test (1)
+      velocity / acceleration   : 2 K (2 dims + 2)
+      right-hand side W^T delta : 3 dims nv K FMA        -> 6 dims nv K
+      multiplier + KKT product  : dims (2 nv + 2 nv^2 + 3 nv)
+    """
+    pair = 2 * dims + dims + 2 * dims + 1 + 1
+    return (12 * dims * nv * K + pair * K * M + 2 * K * (2 * dims + 2)
+            + dims * (5 * nv + 2 * nv * nv))
+
+
+def cpu_baseline(wl, n_sample: int):
+    """The FP64 oracle on `n_sample` samples of the same workload (one
+    projection of n_proj_iters iterations), in projected samples x iters/s."""
+    import oracle as O
+    from paper_2309_08235_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    bc, obs = W.scene(wl, 0)
+    prob = O.Problem(wl.dims, wl.n_coeff, wl.n_steps, wl.horizon, wl.n_obs, wl.rho, wl.v_max,
+                     wl.a_max, wl.bc_mask)
+    xi = W.samples(wl, 5, n=n_sample)
+    t0 = time.perf_counter()
+    O.project(prob, bc, obs, xi, wl.n_proj_iters)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * wl.n_proj_iters / dt, "unit": "projected samples*iters/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_sample} samples x {wl.n_proj_iters} projection iterations of the "
+                      f"{wl.name} scene (one CEM iteration's projection), FP64 NumPy, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--cpu-sample", type=int, default=150)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): every problem and "
+              "sample shard is independent, so N GPUs would run N disjoint copies", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_08235_amd import priest as P
+    from paper_2309_08235_amd import workloads as W
+
+    wl = W.C2
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    prob = P.Problem.from_workload(wl)
+    bc_h, obs_h = W.scene(wl, 0)
+    bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
+    obs = torch.tensor(obs_h, dtype=torch.float32, device=dev)
+    mu0 = torch.tensor(W.initial_mean(wl), dtype=torch.float32, device=dev)
+    cov0 = torch.tensor(W.initial_cov(wl), dtype=torch.float32, device=dev)
+    mu, cov = mu0.clone(), cov0.clone()
+    cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
+                n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
+                cov_jitter=wl.cov_jitter)
+    out = prob.plan_outputs(cem, full=False)
+    ws = prob.workspace(cem)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        mu.copy_(mu0)
+        cov.copy_(cov0)
+        prob.plan(bc, obs, cem, mu, cov, seed=1234 + i, stream_id=0, out=out, workspace=ws)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step(args.warmup + i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])          # ms per plan
+    status = int(out["status"][0].item())
+    best = float(out["best_cost"][0].item())
+    assert status == 0 and np.isfinite(best), (status, best)
+
+    per_plan = wl.n_samples * wl.n_proj_iters * wl.n_cem
+    value = per_plan * args.steps / wall
+
+    # projection kernel alone: same shape, same stream, events around R launches
+    xi = torch.tensor(W.samples(wl, 5), dtype=torch.float32, device=dev)
+    xo = torch.empty_like(xi)
+    r = torch.empty(wl.n_samples, device=dev)
+    c1 = torch.empty(wl.n_samples, device=dev)
+    for _ in range(3):
+        P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ka.record(stream)
+    for _ in range(args.kernel_reps):
+        P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+    kb.record(stream)
+    torch.cuda.synchronize()
+    k_ms = ka.elapsed_time(kb) / args.kernel_reps
+    flops = projection_flops(wl.dims, wl.n_coeff, wl.n_steps, wl.n_obs) * wl.n_samples * wl.n_proj_iters
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "project_kernel<2,11>", "kernel_ms": round(k_ms, 4),
+                "flops_per_launch": flops}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_sample)
+
+    line = {
+        "metric": "projected samples*iters/s",
+        "value": round(value, 1),
+        "unit": "samples*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "dims": wl.dims, "n_samples": wl.n_samples,
+                   "n_obs": wl.n_obs, "n_steps": wl.n_steps, "n_coeff": wl.n_coeff,
+                   "n_proj_iters": wl.n_proj_iters, "n_cem": wl.n_cem, "n_proj": wl.n_proj,
+                   "n_elite": wl.n_elite, "parallelism": "single-gpu"},
+        "plans_per_sec": round(args.steps / wall, 3),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * priest.h - C ABI of the MI355X (gfx950) PRIEST planner library, libpriest.so.
+ *
+ * PRIEST (Rastgar et al., "PRIEST: Projection Guided Sampling-Based
+ * Optimization For Autonomous Navigation") plans a trajectory by sampling
+ * polynomial coefficient vectors xi from a Gaussian, pushing every sample
+ * toward the feasible set with a batched projection optimizer, and refitting
+ * the Gaussian to the lowest-cost projected samples (Alg. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers (HIP global memory) unless a comment
+ *    says "host".  The caller allocates and owns them; the library owns only
+ *    the opaque problem handle and what it allocates inside it.
+ *  - Every call that takes a `stream` (a hipStream_t passed as void*, NULL =
+ *    the default stream) is asynchronous on that stream: outputs are valid
+ *    once the caller synchronises it.  priest_init_problem synchronises once.
+ *  - float32 arrays, row-major.  A sample xi has D = dims * n_coeff entries
+ *    laid out [dims][n_coeff]: the coefficients of x(t), then y(t), then z(t)
+ *    (Sec. II-A, compact form below eq. (3)).
+ *  - Scenes:
+ *      bc  [dims][6]  per axis (p0, v0, a0, pf, vf, af): boundary values of
+ *                     position, velocity, acceleration at t0 and tf
+ *                     (eq. (1b)); rows not selected by bc_mask are ignored.
+ *      obs [n_obs][8] (cx, cy, cz, vx, vy, vz, a, b): obstacle centre at t=0,
+ *                     constant velocity, semi-axes (a, a, b) of eq. (1e);
+ *                     in 2D cz, vz and b are ignored (circles of radius a).
+ *  - Return value: PRIEST_OK or a negative status; no exception or abort
+ *    crosses the ABI.  priest_last_error() returns a thread-local message
+ *    describing the last failure on the calling thread.
+ *  - Input validation happens on the host before anything is launched: on
+ *    error nothing has been enqueued and outputs are untouched.
+ */
+#ifndef PRIEST_H_
+#define PRIEST_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRIEST_OK 0
+#define PRIEST_ERR_INVALID (-1)   /* bad sizes, null required pointer, non-finite scalar */
+#define PRIEST_ERR_SINGULAR (-2)  /* boundary rows rank-deficient: KKT matrix singular */
+#define PRIEST_ERR_NOMEM (-3)     /* device allocation failed / workspace too small / admission refused */
+#define PRIEST_ERR_DEVICE (-4)    /* a HIP runtime call failed */
+#define PRIEST_ERR_NONFINITE (-5) /* NaN/Inf met on the device (reported through a status word) */
+
+/* Boundary rows (eq. (3b)): bit i selects row i of
+ * [P_0; Pdot_0; Pddot_0; P_-1; Pdot_-1; Pddot_-1] for every axis. */
+#define PRIEST_BC_P0 1u
+#define PRIEST_BC_V0 2u
+#define PRIEST_BC_A0 4u
+#define PRIEST_BC_PF 8u
+#define PRIEST_BC_VF 16u
+#define PRIEST_BC_AF 32u
+/* The four rows of the paper's block of A. */
+#define PRIEST_BC_DEFAULT (PRIEST_BC_P0 | PRIEST_BC_V0 | PRIEST_BC_A0 | PRIEST_BC_PF)
+
+#define PRIEST_FP32 0        /* every product in FP32 */
+#define PRIEST_BF16_MIXED 1  /* BF16 operands for the right-hand-side assembly F^T(e - F xi),
+                                FP32 accumulation, last n_refine_fp32 iterations in FP32 */
+
+#define PRIEST_MAX_COEFF 16
+#define PRIEST_MAX_STEPS 256
+#define PRIEST_MAX_OBS 1024
+#define PRIEST_MAX_SAMPLES 65536
+
+typedef struct priest_problem priest_problem; /* opaque, owned by the library */
+
+/* Shape of a planning problem (Sec. II-A eqs. (1)-(3); Appendix eq. (12)). */
+typedef struct priest_problem_desc {
+  int32_t dims;          /* 2 or 3 */
+  int32_t n_coeff;       /* coefficients per axis, 2..16 (polynomial degree n_coeff-1) */
+  int32_t n_steps;       /* planning steps K on t_k = k T/(K-1), 2..256 */
+  int32_t n_obs;         /* exact obstacle count (enters I + rho F^T F), 0..1024 */
+  double horizon;        /* T > 0, seconds */
+  double rho;            /* augmented-Lagrangian weight rho >= 0 (eq. (14)) */
+  double v_max;          /* > 0; +inf disables the velocity bound (eq. (1c)) */
+  double a_max;          /* > 0; +inf disables the acceleration bound */
+  uint32_t bc_mask;      /* PRIEST_BC_* rows; at most n_coeff rows, full rank */
+  int32_t precision;     /* PRIEST_FP32 or PRIEST_BF16_MIXED */
+  int32_t n_refine_fp32; /* PRIEST_BF16_MIXED: trailing iterations run in FP32 */
+  int32_t reserved;      /* must be 0 */
+} priest_problem_desc;
+
+/* Sampling-loop settings (Alg. 1, eqs. (9a)-(9c)). */
+typedef struct priest_cem_params {
+  int32_t n_samples;    /* N_b: samples per CEM iteration, 1..PRIEST_MAX_SAMPLES */
+  int32_t n_cem;        /* CEM iterations */
+  int32_t n_proj_iters; /* projection iterations per CEM iteration */
+  int32_t n_proj;       /* N_proj: size of the lowest-residual set, 1..n_samples */
+  int32_t n_elite;      /* N_elite: size of the elite set, 1..n_proj */
+  int32_t reserved;     /* must be 0 */
+  float sigma;          /* learning rate of eqs. (9a)/(9b), in [0, 1] */
+  float gamma;          /* temperature of eq. (9c), > 0 */
+  float cov_jitter;     /* eps = cov_jitter * tr(Sigma)/D added before Cholesky, >= 0 */
+  float reserved_f;     /* must be 0 */
+} priest_cem_params;
+
+/* Outputs of priest_plan; every pointer but best_xi/best_cost may be NULL.
+ * Per-sample outputs describe the LAST CEM iteration. */
+typedef struct priest_plan_out {
+  float* best_xi;      /* [D]: projected sample with the lowest c_aug of the final elite set */
+  float* best_cost;    /* [1]: its c_aug = c1 + r */
+  int32_t* elite_idx;  /* [n_elite]: elite sample indices, ascending c_aug */
+  int32_t* proj_idx;   /* [n_proj]: lowest-residual sample indices, ascending r */
+  float* xi;           /* [N][D]: the drawn samples */
+  float* xi_bar;       /* [N][D]: projected samples */
+  float* resid;        /* [N]: r = ||F xi_bar - e(xi_bar)|| */
+  float* c1;           /* [N]: smoothness cost sum_k ||a_k||^2 */
+  int32_t* status;     /* [1]: PRIEST_OK, or PRIEST_ERR_NONFINITE if a covariance factorisation failed */
+} priest_plan_out;
+
+/* Builds the problem: Bernstein basis P, Pdot, Pddot (eq. (2)), boundary block
+ * A (eq. (3b)), and the fixed KKT inverse of eq. (7b), factored once in FP64
+ * on the GPU (Sec. III-A, "Scalability": M is computed only once).
+ * `out` receives a handle to free with priest_free_problem.  Synchronises
+ * `stream`.  Errors: INVALID (bad desc), SINGULAR (rank-deficient boundary
+ * rows), NOMEM, DEVICE. */
+int32_t priest_init_problem(const priest_problem_desc* desc, void* stream, priest_problem** out);
+
+/* Releases a problem handle (NULL is accepted).  The caller must make sure no
+ * work using it is still running. */
+int32_t priest_free_problem(priest_problem* p);
+
+/* Number of coefficients per sample, D = dims * n_coeff (host call). */
+int32_t priest_problem_dim(const priest_problem* p);
+
+/* Projection optimizer (Sec. III-A eqs. (4)-(7); Appendix eqs. (14)-(15)):
+ * pushes each of the N samples xi_in [N][D] toward the feasible set with
+ * n_iter alternating-minimisation iterations, starting from xi_bar = xi,
+ * lambda = 0.  Writes xi_out [N][D].  resid [N] (r of Alg. 1) and c1 [N]
+ * (smoothness cost) of the returned iterate may be NULL.  bc/obs: one scene
+ * (layouts above).  xi_in and xi_out may alias.  Errors: INVALID. */
+int32_t priest_project(priest_problem* p, const float* bc, const float* obs,
+                       const float* xi_in, int32_t N, int32_t n_iter,
+                       float* xi_out, float* resid, float* c1, void* stream);
+
+/* Bytes of device workspace priest_plan / priest_plan_batch need for
+ * n_problems problems with settings `c` (host call). */
+int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_params* c,
+                                   int32_t n_problems, size_t* bytes);
+
+/* Alg. 1 for one problem: n_cem iterations of
+ *   draw N samples from N(mu, Sigma) -> project -> residual r -> N_proj
+ *   lowest r -> c_aug = c1 + r -> N_elite lowest c_aug -> refit (eqs. (9a)-(9c)).
+ * mu [D] and cov [D][D] are read and overwritten with the refitted
+ * distribution (the warm start of the next call).
+ * Draws: if `noise` ([n_cem][N][D] standard normals) is non-NULL it is used;
+ * otherwise Philox4x32-10 with key `seed`, counter (sample, d/4, iteration,
+ * stream_id), followed by Box-Muller.
+ * workspace: device buffer of at least priest_plan_workspace_size bytes.
+ * Errors: INVALID, NOMEM (workspace too small). */
+int32_t priest_plan(priest_problem* p, const float* bc, const float* obs,
+                    const priest_cem_params* c, float* mu, float* cov,
+                    uint64_t seed, uint32_t stream_id, const float* noise,
+                    const priest_plan_out* out, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/* Alg. 1 for n_problems independent problems of the same shape, every CEM
+ * step batched over all problems in one launch (the 3D batched workload).
+ * Arrays are stacked per problem: bc [P][dims][6], obs [P][n_obs][8],
+ * mu [P][D], cov [P][D][D], noise [P][n_cem][N][D] (nullable),
+ * out->best_xi [P][D], best_cost [P], elite_idx [P][n_elite], proj_idx [P][n_proj],
+ * xi / xi_bar [P][N][D], resid / c1 [P][N], status [P].
+ * Problem q draws with stream id stream_base + q.
+ * use_graph != 0 captures the whole CEM loop into a hipGraph the first time
+ * a given argument set is seen and replays it afterwards.  Errors as priest_plan. */
+int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc,
+                          const float* obs, const priest_cem_params* c, float* mu,
+                          float* cov, uint64_t seed, uint32_t stream_base,
+                          const float* noise, const priest_plan_out* out, void* workspace,
+                          size_t workspace_bytes, int32_t use_graph, void* stream);
+
+/* Debug/parity hook for the closed-form alpha/beta/d step (Appendix eqs.
+ * (15a)-(15c), (13)): for samples xi [N][D] writes the per-row push-outs
+ * e(xi) - F xi, laid out [N][n_obs + 2][K][dims] (obstacle blocks, then the
+ * velocity block, then the acceleration block).  Meant for small N. */
+int32_t priest_debug_offsets(priest_problem* p, const float* bc, const float* obs,
+                             const float* xi, int32_t N, float* offsets, void* stream);
+
+/* Debug/parity hook for the draws: writes z [N][D] standard normals of CEM
+ * iteration `iter` for (seed, stream_id), exactly as priest_plan draws them. */
+int32_t priest_debug_normals(uint64_t seed, uint32_t stream_id, int32_t iter, int32_t N,
+                             int32_t D, float* z, void* stream);
+
+/* Copies the problem's FP32 constants to host memory for inspection:
+ * which = 0: KKT block M11 [n_coeff][n_coeff]; 1: Pi = M11 Q [n_coeff][n_coeff];
+ * 2: M12 [n_coeff][6] (column i multiplies boundary value i of an axis);
+ * 3: basis rows [K][3][n_coeff] (P, Pdot, Pddot).  `host_out` must hold
+ * `count` floats (host).  Synchronous. */
+int32_t priest_debug_constants(const priest_problem* p, int32_t which, float* host_out,
+                               int32_t count);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* priest_last_error(void);
+
+/* Library ABI version (increments on incompatible change). */
+int32_t priest_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRIEST_H_ */

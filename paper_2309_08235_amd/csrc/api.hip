@@ -1,0 +1,552 @@
+// C ABI of libpriest.so: validation, problem construction and launch
+// sequencing.  All arithmetic of the planner runs in the kernels of
+// project.hip (projection), cem.hip (selection / refit / Cholesky) and
+// kkt.hip (one-time FP64 KKT factorisation); this file builds the Bernstein
+// basis and Q on the host in FP64 and orders the launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "priest_internal.h"
+
+using namespace priest;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(PRIEST_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+__global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Bernstein polynomial B_{i,n}(tau); zero outside 0 <= i <= n.
+double bern(int i, int n, double tau) {
+  if (i < 0 || i > n || n < 0) return 0.0;
+  return binom(n, i) * std::pow(tau, i) * std::pow(1.0 - tau, n - i);
+}
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+size_t align256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
+
+}  // namespace
+
+struct priest_problem {
+  priest_problem_desc desc{};
+  int D = 0, E = 0;
+  int rowsel[6] = {0, 0, 0, 0, 0, 0};
+  float* dW = nullptr;     // [K][3][nv]
+  float* dM11 = nullptr;   // [nv][nv]
+  float* dPi = nullptr;    // [nv][nv]
+  float* dM12 = nullptr;   // [nv][6]
+  double* d64 = nullptr;   // scratch for the FP64 factorisation
+  std::vector<float> hW, hM11, hPi, hM12;
+  std::mutex graph_mu;
+  std::vector<GraphEntry> graphs;
+  int device = 0;
+  size_t lds_limit = 0;
+};
+
+namespace {
+
+int32_t validate_desc(const priest_problem_desc* d) {
+  if (!d) return fail(PRIEST_ERR_INVALID, "desc is NULL");
+  if (d->dims != 2 && d->dims != 3) return fail(PRIEST_ERR_INVALID, "dims must be 2 or 3");
+  if (d->n_coeff < 2 || d->n_coeff > PRIEST_MAX_COEFF)
+    return fail(PRIEST_ERR_INVALID, "n_coeff must be in [2, %d]", PRIEST_MAX_COEFF);
+  if (d->n_steps < 2 || d->n_steps > PRIEST_MAX_STEPS)
+    return fail(PRIEST_ERR_INVALID, "n_steps must be in [2, %d]", PRIEST_MAX_STEPS);
+  if (d->n_obs < 0 || d->n_obs > PRIEST_MAX_OBS)
+    return fail(PRIEST_ERR_INVALID, "n_obs must be in [0, %d]", PRIEST_MAX_OBS);
+  if (!(std::isfinite(d->horizon) && d->horizon > 0))
+    return fail(PRIEST_ERR_INVALID, "horizon must be finite and > 0");
+  if (!(std::isfinite(d->rho) && d->rho >= 0)) return fail(PRIEST_ERR_INVALID, "rho must be finite and >= 0");
+  if (!(d->v_max > 0) || std::isnan(d->v_max)) return fail(PRIEST_ERR_INVALID, "v_max must be > 0");
+  if (!(d->a_max > 0) || std::isnan(d->a_max)) return fail(PRIEST_ERR_INVALID, "a_max must be > 0");
+  if (d->bc_mask & ~63u) return fail(PRIEST_ERR_INVALID, "bc_mask has unknown bits");
+  if (d->precision != PRIEST_FP32 && d->precision != PRIEST_BF16_MIXED)
+    return fail(PRIEST_ERR_INVALID, "unknown precision");
+  if (d->n_refine_fp32 < 0) return fail(PRIEST_ERR_INVALID, "n_refine_fp32 must be >= 0");
+  if (d->reserved != 0) return fail(PRIEST_ERR_INVALID, "reserved must be 0");
+  int E = 0;
+  for (int i = 0; i < 6; ++i) E += (d->bc_mask >> i) & 1;
+  if (E > d->n_coeff)
+    return fail(PRIEST_ERR_SINGULAR, "%d boundary rows exceed %d coefficients per axis", E, d->n_coeff);
+  return PRIEST_OK;
+}
+
+int32_t validate_cem(const priest_cem_params* c) {
+  if (!c) return fail(PRIEST_ERR_INVALID, "cem params are NULL");
+  if (c->n_samples < 1 || c->n_samples > 8192)
+    return fail(PRIEST_ERR_INVALID, "n_samples must be in [1, 8192] for planning");
+  if (c->n_cem < 1) return fail(PRIEST_ERR_INVALID, "n_cem must be >= 1");
+  if (c->n_proj_iters < 0) return fail(PRIEST_ERR_INVALID, "n_proj_iters must be >= 0");
+  if (c->n_proj < 1 || c->n_proj > c->n_samples)
+    return fail(PRIEST_ERR_INVALID, "n_proj must be in [1, n_samples]");
+  if (c->n_elite < 1 || c->n_elite > c->n_proj)
+    return fail(PRIEST_ERR_INVALID, "n_elite must be in [1, n_proj]");
+  if (!(std::isfinite(c->sigma) && c->sigma >= 0 && c->sigma <= 1))
+    return fail(PRIEST_ERR_INVALID, "sigma must be in [0, 1]");
+  if (!(std::isfinite(c->gamma) && c->gamma > 0)) return fail(PRIEST_ERR_INVALID, "gamma must be > 0");
+  if (!(std::isfinite(c->cov_jitter) && c->cov_jitter >= 0))
+    return fail(PRIEST_ERR_INVALID, "cov_jitter must be finite and >= 0");
+  if (c->reserved != 0 || c->reserved_f != 0.0f) return fail(PRIEST_ERR_INVALID, "reserved must be 0");
+  return PRIEST_OK;
+}
+
+ProjArgs base_args(const priest_problem* p) {
+  ProjArgs a{};
+  const auto& d = p->desc;
+  a.dims = d.dims;
+  a.nv = d.n_coeff;
+  a.K = d.n_steps;
+  a.M = d.n_obs;
+  a.rho = static_cast<float>(d.rho);
+  a.dt = static_cast<float>(d.horizon / (d.n_steps - 1));
+  a.vmax = static_cast<float>(d.v_max);
+  a.amax = static_cast<float>(d.a_max);
+  a.W = p->dW;
+  a.M11 = p->dM11;
+  a.Pi = p->dPi;
+  a.M12 = p->dM12;
+  return a;
+}
+
+int32_t check_lds(const priest_problem* p, const ProjArgs& a) {
+  const size_t need = project_lds_bytes(a);
+  if (need > p->lds_limit)
+    return fail(PRIEST_ERR_INVALID, "problem shape needs %zu B of LDS per block (limit %zu)", need,
+                p->lds_limit);
+  return PRIEST_OK;
+}
+
+struct PlanLayout {
+  size_t xb, resid, c1, L, status, per_problem;
+};
+
+PlanLayout plan_layout(int D, int N) {
+  PlanLayout l{};
+  size_t o = 0;
+  l.xb = o;     o += align256(sizeof(float) * static_cast<size_t>(N) * D);
+  l.resid = o;  o += align256(sizeof(float) * N);
+  l.c1 = o;     o += align256(sizeof(float) * N);
+  l.L = o;      o += align256(sizeof(float) * D * D);
+  l.status = o; o += align256(sizeof(int32_t));
+  l.per_problem = o;
+  return l;
+}
+
+// Enqueues n_cem CEM iterations for n_problems problems of shape p.
+int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float* obs,
+                     const priest_cem_params* c, float* mu, float* cov, uint64_t seed,
+                     uint32_t stream_base, const float* noise, const priest_plan_out* out,
+                     char* ws, hipStream_t s) {
+  const int D = p->D, N = c->n_samples;
+  const PlanLayout pl = plan_layout(D, N);
+  // per-problem workspace blocks are laid out [problem][...]: strides in floats
+  const int64_t wstride = static_cast<int64_t>(pl.per_problem / sizeof(float));
+  float* wxb = reinterpret_cast<float*>(ws + pl.xb);
+  float* wr = reinterpret_cast<float*>(ws + pl.resid);
+  float* wc = reinterpret_cast<float*>(ws + pl.c1);
+  float* wL = reinterpret_cast<float*>(ws + pl.L);
+
+  if (out->status) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((P + 255) / 256), dim3(256), 0, s, out->status, P,
+                       PRIEST_OK);
+    HIP_TRY(hipGetLastError());
+  }
+  CemArgs ca{};
+  ca.D = D;
+  ca.N = N;
+  ca.n_proj = c->n_proj;
+  ca.n_elite = c->n_elite;
+  ca.sigma = c->sigma;
+  ca.gamma = c->gamma;
+  ca.cov_jitter = c->cov_jitter;
+  ca.xb = wxb;
+  ca.xb_stride = wstride;
+  ca.resid = wr;
+  ca.c1 = wc;
+  ca.n_stride = wstride;
+  ca.mu = mu;
+  ca.mu_stride = D;
+  ca.cov = cov;
+  ca.cov_stride = static_cast<int64_t>(D) * D;
+  ca.L = wL;
+  ca.L_stride = wstride;
+  ca.best_xi = out->best_xi;
+  ca.best_stride = D;
+  ca.best_cost = out->best_cost;
+  ca.elite_idx = out->elite_idx;
+  ca.proj_idx = out->proj_idx;
+  ca.status = out->status;
+  ca.chol_only = 1;
+  HIP_TRY(launch_cem(ca, P, s));
+  ca.chol_only = 0;
+
+  ProjArgs a = base_args(p);
+  a.N = N;
+  project_pick_tile(a.dims, a.nv, a.K, a.M, N, P, &a.S, &a.G);
+  a.blocks_per_problem = (N + a.S - 1) / a.S;
+  a.n_iter = c->n_proj_iters;
+  a.mode = noise ? kFromNoise : kFromPhilox;
+  a.seed = seed;
+  a.stream_base = stream_base;
+  a.bc = bc;
+  a.bc_stride = static_cast<int64_t>(a.dims) * 6;
+  a.obs = obs;
+  a.obs_stride = static_cast<int64_t>(a.M) * 8;
+  a.mu = mu;
+  a.mu_stride = D;
+  a.L = wL;
+  a.L_stride = wstride;
+  a.noise_stride = static_cast<int64_t>(c->n_cem) * N * D;
+  a.xi_out = wxb;
+  a.xi_out_stride = wstride;
+  a.resid = wr;
+  a.c1 = wc;
+  a.n_stride = wstride;
+  {
+    const int32_t st = check_lds(p, a);
+    if (st != PRIEST_OK) return st;
+  }
+  for (int l = 0; l < c->n_cem; ++l) {
+    a.iter = l;
+    a.noise = noise ? noise + static_cast<int64_t>(l) * N * D : nullptr;
+    const bool last = (l == c->n_cem - 1);
+    a.xi_src = last ? out->xi : nullptr;
+    a.xi_src_stride = static_cast<int64_t>(N) * D;
+    a.resid2 = last ? out->resid : nullptr;
+    a.c12 = last ? out->c1 : nullptr;
+    a.xi_out2 = last ? out->xi_bar : nullptr;
+    HIP_TRY(launch_project(a, P, s));
+    HIP_TRY(launch_cem(ca, P, s));
+  }
+  return PRIEST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* priest_last_error(void) { return g_err.c_str(); }
+
+int32_t priest_version(void) { return 1; }
+
+int32_t priest_init_problem(const priest_problem_desc* desc, void* stream, priest_problem** out) {
+  if (!out) return fail(PRIEST_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  const int32_t st = validate_desc(desc);
+  if (st != PRIEST_OK) return st;
+  const auto& d = *desc;
+  const int nv = d.n_coeff, K = d.n_steps, n = nv - 1;
+  const double T = d.horizon;
+  std::unique_ptr<priest_problem> p(new priest_problem());
+  p->desc = d;
+  p->D = d.dims * nv;
+  int E = 0;
+  for (int i = 0; i < 6; ++i)
+    if ((d.bc_mask >> i) & 1) p->rowsel[E++] = i;
+  p->E = E;
+  HIP_TRY(hipGetDevice(&p->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, p->device));
+  p->lds_limit = prop.sharedMemPerBlock;
+
+  // Bernstein rows (FP64): P, Pdot, Pddot at t_k = k T/(K-1)
+  std::vector<double> P(K * nv), Pd(K * nv), Pdd(K * nv);
+  for (int k = 0; k < K; ++k) {
+    const double tau = static_cast<double>(k) / (K - 1);
+    for (int i = 0; i < nv; ++i) {
+      P[k * nv + i] = bern(i, n, tau);
+      Pd[k * nv + i] = n * (bern(i - 1, n - 1, tau) - bern(i, n - 1, tau)) / T;
+      Pdd[k * nv + i] = (n >= 2) ? n * (n - 1) *
+                                       (bern(i - 2, n - 2, tau) - 2.0 * bern(i - 1, n - 2, tau) +
+                                        bern(i, n - 2, tau)) / (T * T)
+                                 : 0.0;
+    }
+  }
+  // Q = I + rho (n_obs P^T P + Pdot^T Pdot + Pddot^T Pddot)
+  std::vector<double> Q(nv * nv, 0.0);
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < K; ++k)
+        s += d.n_obs * P[k * nv + i] * P[k * nv + j] + Pd[k * nv + i] * Pd[k * nv + j] +
+             Pdd[k * nv + i] * Pdd[k * nv + j];
+      Q[i * nv + j] = (i == j ? 1.0 : 0.0) + d.rho * s;
+    }
+  // boundary block A_ax: rows P_0, Pdot_0, Pddot_0, P_-1, Pdot_-1, Pddot_-1
+  std::vector<double> A(std::max(E, 1) * nv, 0.0);
+  for (int r = 0; r < E; ++r) {
+    const int which = p->rowsel[r];
+    const std::vector<double>& src = (which % 3 == 0) ? P : (which % 3 == 1) ? Pd : Pdd;
+    const int k = (which < 3) ? 0 : K - 1;
+    for (int i = 0; i < nv; ++i) A[r * nv + i] = src[k * nv + i];
+  }
+  p->hW.resize(static_cast<size_t>(K) * 3 * nv);
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < nv; ++i) {
+      p->hW[(k * 3 + 0) * nv + i] = static_cast<float>(P[k * nv + i]);
+      p->hW[(k * 3 + 1) * nv + i] = static_cast<float>(Pd[k * nv + i]);
+      p->hW[(k * 3 + 2) * nv + i] = static_cast<float>(Pdd[k * nv + i]);
+    }
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *dQ = nullptr, *dA = nullptr;
+  int* dsel = nullptr;
+  int* dflag = nullptr;
+  auto cleanup = [&]() {
+    if (dQ) (void)hipFree(dQ);
+    if (dA) (void)hipFree(dA);
+    if (dsel) (void)hipFree(dsel);
+    if (dflag) (void)hipFree(dflag);
+  };
+  auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
+  if (!alloc(reinterpret_cast<void**>(&p->dW), sizeof(float) * p->hW.size()) ||
+      !alloc(reinterpret_cast<void**>(&p->dM11), sizeof(float) * nv * nv) ||
+      !alloc(reinterpret_cast<void**>(&p->dPi), sizeof(float) * nv * nv) ||
+      !alloc(reinterpret_cast<void**>(&p->dM12), sizeof(float) * nv * 6) ||
+      !alloc(reinterpret_cast<void**>(&p->d64), sizeof(double) * (2 * nv * nv + nv * 6)) ||
+      !alloc(reinterpret_cast<void**>(&dQ), sizeof(double) * nv * nv) ||
+      !alloc(reinterpret_cast<void**>(&dA), sizeof(double) * A.size()) ||
+      !alloc(reinterpret_cast<void**>(&dsel), sizeof(int) * 6) ||
+      !alloc(reinterpret_cast<void**>(&dflag), sizeof(int))) {
+    cleanup();
+    priest_free_problem(p.release());
+    return fail(PRIEST_ERR_NOMEM, "device allocation failed");
+  }
+  int flag = -99;
+  hipError_t e = hipMemcpyAsync(p->dW, p->hW.data(), sizeof(float) * p->hW.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dQ, Q.data(), sizeof(double) * nv * nv, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dA, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dsel, p->rowsel, sizeof(int) * 6, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_kkt(dQ, dA, nv, E, dsel, p->d64, p->dM11, p->dPi, p->dM12, dflag, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  p->hM11.resize(nv * nv);
+  p->hPi.resize(nv * nv);
+  p->hM12.resize(nv * 6);
+  if (e == hipSuccess) e = hipMemcpy(p->hM11.data(), p->dM11, sizeof(float) * nv * nv, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(p->hPi.data(), p->dPi, sizeof(float) * nv * nv, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(p->hM12.data(), p->dM12, sizeof(float) * nv * 6, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) {
+    priest_free_problem(p.release());
+    return fail(PRIEST_ERR_DEVICE, "problem setup failed: %s", hipGetErrorString(e));
+  }
+  if (flag != PRIEST_OK) {
+    priest_free_problem(p.release());
+    return fail(PRIEST_ERR_SINGULAR, "KKT matrix is singular (boundary rows %u linearly dependent)",
+                d.bc_mask);
+  }
+  *out = p.release();
+  return PRIEST_OK;
+}
+
+int32_t priest_free_problem(priest_problem* p) {
+  if (!p) return PRIEST_OK;
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (p->dW) (void)hipFree(p->dW);
+  if (p->dM11) (void)hipFree(p->dM11);
+  if (p->dPi) (void)hipFree(p->dPi);
+  if (p->dM12) (void)hipFree(p->dM12);
+  if (p->d64) (void)hipFree(p->d64);
+  delete p;
+  return PRIEST_OK;
+}
+
+int32_t priest_problem_dim(const priest_problem* p) { return p ? p->D : 0; }
+
+int32_t priest_project(priest_problem* p, const float* bc, const float* obs, const float* xi_in,
+                       int32_t N, int32_t n_iter, float* xi_out, float* resid, float* c1,
+                       void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);
+  if (n_iter < 0) return fail(PRIEST_ERR_INVALID, "n_iter must be >= 0");
+  if (!bc || !xi_in || !xi_out) return fail(PRIEST_ERR_INVALID, "bc, xi_in and xi_out are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  if (N == 0) return PRIEST_OK;
+  ProjArgs a = base_args(p);
+  a.N = N;
+  project_pick_tile(a.dims, a.nv, a.K, a.M, N, 1, &a.S, &a.G);
+  a.blocks_per_problem = (N + a.S - 1) / a.S;
+  a.n_iter = n_iter;
+  a.mode = kFromInput;
+  a.bc = bc;
+  a.obs = obs;
+  a.xi_in = xi_in;
+  a.xi_out = xi_out;
+  a.resid = resid;
+  a.c1 = c1;
+  const int32_t st = check_lds(p, a);
+  if (st != PRIEST_OK) return st;
+  HIP_TRY(launch_project(a, 1, static_cast<hipStream_t>(stream)));
+  return PRIEST_OK;
+}
+
+int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_params* c,
+                                   int32_t n_problems, size_t* bytes) {
+  if (!p || !bytes) return fail(PRIEST_ERR_INVALID, "problem and bytes are required");
+  const int32_t st = validate_cem(c);
+  if (st != PRIEST_OK) return st;
+  if (n_problems < 1) return fail(PRIEST_ERR_INVALID, "n_problems must be >= 1");
+  *bytes = plan_layout(p->D, c->n_samples).per_problem * static_cast<size_t>(n_problems);
+  return PRIEST_OK;
+}
+
+static int32_t plan_common(priest_problem* p, int32_t P, const float* bc, const float* obs,
+                           const priest_cem_params* c, float* mu, float* cov, uint64_t seed,
+                           uint32_t stream_base, const float* noise, const priest_plan_out* out,
+                           void* workspace, size_t workspace_bytes, int32_t use_graph,
+                           void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  int32_t st = validate_cem(c);
+  if (st != PRIEST_OK) return st;
+  if (P < 1) return fail(PRIEST_ERR_INVALID, "n_problems must be >= 1");
+  if (!bc || !mu || !cov || !out || !out->best_xi || !out->best_cost || !workspace)
+    return fail(PRIEST_ERR_INVALID, "bc, mu, cov, out->best_xi, out->best_cost and workspace are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  size_t need = 0;
+  priest_plan_workspace_size(p, c, P, &need);
+  if (workspace_bytes < need)
+    return fail(PRIEST_ERR_NOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+  if (cem_lds_bytes(c->n_samples, p->D, c->n_elite) > p->lds_limit)
+    return fail(PRIEST_ERR_INVALID, "n_samples too large for the selection kernel");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!use_graph)
+    return enqueue_plan(p, P, bc, obs, c, mu, cov, seed, stream_base, noise, out,
+                        static_cast<char*>(workspace), s);
+  if (!s) return fail(PRIEST_ERR_INVALID, "graph capture needs a non-default stream");
+  std::vector<uint64_t> key = {
+      static_cast<uint64_t>(P), reinterpret_cast<uint64_t>(bc), reinterpret_cast<uint64_t>(obs),
+      reinterpret_cast<uint64_t>(mu), reinterpret_cast<uint64_t>(cov), seed, stream_base,
+      reinterpret_cast<uint64_t>(noise), reinterpret_cast<uint64_t>(workspace),
+      reinterpret_cast<uint64_t>(s), reinterpret_cast<uint64_t>(out->best_xi),
+      reinterpret_cast<uint64_t>(out->best_cost), reinterpret_cast<uint64_t>(out->elite_idx),
+      reinterpret_cast<uint64_t>(out->proj_idx), reinterpret_cast<uint64_t>(out->xi),
+      reinterpret_cast<uint64_t>(out->xi_bar), reinterpret_cast<uint64_t>(out->resid),
+      reinterpret_cast<uint64_t>(out->c1), reinterpret_cast<uint64_t>(out->status)};
+  const uint32_t* cw = reinterpret_cast<const uint32_t*>(c);
+  for (size_t i = 0; i < sizeof(priest_cem_params) / 4; ++i) key.push_back(cw[i]);
+  std::lock_guard<std::mutex> lk(p->graph_mu);
+  for (auto& g : p->graphs)
+    if (g.key == key) {
+      HIP_TRY(hipGraphLaunch(g.exec, s));
+      return PRIEST_OK;
+    }
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  st = enqueue_plan(p, P, bc, obs, c, mu, cov, seed, stream_base, noise, out,
+                    static_cast<char*>(workspace), s);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(s, &graph);
+  if (st != PRIEST_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ce != hipSuccess) return fail(PRIEST_ERR_DEVICE, "stream capture failed: %s", hipGetErrorString(ce));
+  GraphEntry g;
+  g.key = key;
+  const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(PRIEST_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+  if (p->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back(g);
+  HIP_TRY(hipGraphLaunch(g.exec, s));
+  return PRIEST_OK;
+}
+
+int32_t priest_plan(priest_problem* p, const float* bc, const float* obs,
+                    const priest_cem_params* c, float* mu, float* cov, uint64_t seed,
+                    uint32_t stream_id, const float* noise, const priest_plan_out* out,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  return plan_common(p, 1, bc, obs, c, mu, cov, seed, stream_id, noise, out, workspace,
+                     workspace_bytes, 0, stream);
+}
+
+int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc,
+                          const float* obs, const priest_cem_params* c, float* mu, float* cov,
+                          uint64_t seed, uint32_t stream_base, const float* noise,
+                          const priest_plan_out* out, void* workspace, size_t workspace_bytes,
+                          int32_t use_graph, void* stream) {
+  return plan_common(p, n_problems, bc, obs, c, mu, cov, seed, stream_base, noise, out, workspace,
+                     workspace_bytes, use_graph, stream);
+}
+
+int32_t priest_debug_offsets(priest_problem* p, const float* bc, const float* obs,
+                             const float* xi, int32_t N, float* offsets, void* stream) {
+  if (!p || !xi || !offsets) return fail(PRIEST_ERR_INVALID, "problem, xi and offsets are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  if (N < 0 || N > 4096) return fail(PRIEST_ERR_INVALID, "N must be in [0, 4096]");
+  (void)bc;
+  if (N == 0) return PRIEST_OK;
+  ProjArgs a = base_args(p);
+  a.N = N;
+  a.obs = obs;
+  HIP_TRY(launch_debug_offsets(a, xi, offsets, static_cast<hipStream_t>(stream)));
+  return PRIEST_OK;
+}
+
+int32_t priest_debug_normals(uint64_t seed, uint32_t stream_id, int32_t iter, int32_t N, int32_t D,
+                             float* z, void* stream) {
+  if (!z || N < 0 || D < 1 || iter < 0) return fail(PRIEST_ERR_INVALID, "bad arguments");
+  if (N == 0) return PRIEST_OK;
+  HIP_TRY(launch_debug_normals(seed, stream_id, iter, N, D, z, static_cast<hipStream_t>(stream)));
+  return PRIEST_OK;
+}
+
+int32_t priest_debug_constants(const priest_problem* p, int32_t which, float* host_out,
+                               int32_t count) {
+  if (!p || !host_out) return fail(PRIEST_ERR_INVALID, "problem and host_out are required");
+  const std::vector<float>* src = nullptr;
+  switch (which) {
+    case 0: src = &p->hM11; break;
+    case 1: src = &p->hPi; break;
+    case 2: src = &p->hM12; break;
+    case 3: src = &p->hW; break;
+    default: return fail(PRIEST_ERR_INVALID, "unknown constant %d", which);
+  }
+  if (count != static_cast<int32_t>(src->size()))
+    return fail(PRIEST_ERR_INVALID, "constant %d has %zu entries, count is %d", which, src->size(), count);
+  std::memcpy(host_out, src->data(), sizeof(float) * src->size());
+  return PRIEST_OK;
+}
+
+}  // extern "C"

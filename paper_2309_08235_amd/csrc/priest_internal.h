@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP translation units of libpriest.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/priest.h"
+
+namespace priest {
+
+constexpr int kMaxNV = PRIEST_MAX_COEFF;
+constexpr int kProjectThreads = 256;
+constexpr int kCemThreads = 1024;
+
+// Sample sources of the projection kernel.
+enum SampleMode : int32_t {
+  kFromInput = 0,   // xi read from xi_in
+  kFromPhilox = 1,  // xi = mu + L z, z from Philox4x32-10 + Box-Muller
+  kFromNoise = 2,   // xi = mu + L z, z read from `noise`
+};
+
+// Arguments of the fused projection kernel.  One launch covers
+// n_problems * blocks_per_problem blocks; block b works on problem
+// b / blocks_per_problem, samples [tile*S, tile*S + S) of it.
+struct ProjArgs {
+  int32_t dims, nv, K, M, N;
+  int32_t S;                   // samples per block
+  int32_t n_iter;              // projection iterations
+  int32_t blocks_per_problem;
+  int32_t G;                   // time-groups of the right-hand-side reduction
+  int32_t mode;                // SampleMode
+  int32_t iter;                // CEM iteration (Philox counter word 2)
+  uint32_t stream_base;        // Philox counter word 3 = stream_base + problem
+  uint64_t seed;               // Philox key
+  float rho, dt, vmax, amax;   // vmax/amax may be +inf
+  // problem constants (shared by all problems of the launch)
+  const float* W;    // [K][3][nv] rows of P, Pdot, Pddot
+  const float* M11;  // [nv][nv]
+  const float* Pi;   // [nv][nv]  M11 Q
+  const float* M12;  // [nv][6]
+  // per-problem inputs (stride in floats between consecutive problems)
+  const float* bc;  int64_t bc_stride;
+  const float* obs; int64_t obs_stride;
+  const float* xi_in; int64_t xi_in_stride;
+  const float* mu; int64_t mu_stride;
+  const float* L; int64_t L_stride;
+  const float* noise; int64_t noise_stride;
+  // outputs
+  float* xi_out; int64_t xi_out_stride;    // [N][D] per problem, required
+  float* resid; float* c1; int64_t n_stride;  // [N] per problem, nullable
+  float* xi_src; int64_t xi_src_stride;    // drawn samples, nullable
+  // optional second copies (caller outputs, dense [problem][N] / [problem][N][D])
+  float* resid2; float* c12; float* xi_out2;
+};
+
+// Arguments of the selection / refit / Cholesky kernel (one block per problem).
+struct CemArgs {
+  int32_t D, N, n_proj, n_elite;
+  int32_t chol_only;     // 1: only L = chol(cov + eps I)
+  float sigma, gamma, cov_jitter;
+  const float* xb;  int64_t xb_stride;     // projected samples [N][D]
+  const float* resid; const float* c1; int64_t n_stride;
+  float* mu; int64_t mu_stride;            // in/out
+  float* cov; int64_t cov_stride;          // in/out
+  float* L; int64_t L_stride;              // out: chol(cov' + eps I)
+  float* best_xi; int64_t best_stride;     // [D]
+  float* best_cost;                        // [1] per problem
+  int32_t* elite_idx; int32_t* proj_idx;   // nullable
+  int32_t* status;                         // nullable, [1] per problem
+};
+
+// host-side launchers (defined in the .hip files)
+size_t project_lds_bytes(const ProjArgs& a);
+int project_pick_tile(int dims, int nv, int K, int M, int N, int n_problems, int* S, int* G);
+hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s);
+size_t cem_lds_bytes(int N, int D, int n_elite);
+hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s);
+hipError_t launch_kkt(const double* Q, const double* A, int nv, int E, const int* rowsel,
+                      double* out64, float* M11, float* Pi, float* M12, int* flag,
+                      hipStream_t s);
+hipError_t launch_debug_offsets(const ProjArgs& a, const float* xi, float* out, hipStream_t s);
+hipError_t launch_debug_normals(uint64_t seed, uint32_t stream_id, int iter, int N, int D,
+                                float* z, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the Philox S-P network
+// with multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key increments
+// 0x9E3779B9 / 0xBB67AE85.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+// (x >> 9 + 1/2) * 2^-23: an open-interval uniform that FP32 holds exactly.
+__device__ __forceinline__ float open_uniform(uint32_t x) {
+  return (static_cast<float>(x >> 9) + 0.5f) * 1.1920928955078125e-07f;
+}
+
+// Four standard normals of counter (i, q, iter, stream) by Box-Muller on
+// word pairs (0,1) and (2,3).
+__device__ __forceinline__ void philox_normals4(uint64_t seed, uint32_t i, uint32_t q,
+                                                uint32_t iter, uint32_t stream, float z[4]) {
+  const U4 w = philox10(U4{i, q, iter, stream}, static_cast<uint32_t>(seed),
+                        static_cast<uint32_t>(seed >> 32));
+  const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const float u1 = open_uniform(words[2 * p]);
+    const float u2 = open_uniform(words[2 * p + 1]);
+    const float rad = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    z[2 * p] = rad * cs;
+    z[2 * p + 1] = rad * sn;
+  }
+}
+
+}  // namespace priest

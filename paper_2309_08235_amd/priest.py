@@ -1,0 +1,311 @@
+"""Thin ctypes binding of libpriest.so (include/priest.h).
+
+Functions keep the C names and only marshal arguments: torch tensors become
+device pointers, the current torch stream becomes the hipStream_t, and a
+non-zero status becomes a :class:`PriestError`.  Every step of the planner
+runs in the library's HIP kernels; if the library is not built the first
+call raises instead of falling back to anything else.
+
+:class:`Problem` is a convenience wrapper that allocates outputs with torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpriest.so")
+
+PRIEST_OK = 0
+PRIEST_ERR_INVALID = -1
+PRIEST_ERR_SINGULAR = -2
+PRIEST_ERR_NOMEM = -3
+PRIEST_ERR_DEVICE = -4
+PRIEST_ERR_NONFINITE = -5
+
+BC_P0, BC_V0, BC_A0, BC_PF, BC_VF, BC_AF = 1, 2, 4, 8, 16, 32
+BC_DEFAULT = BC_P0 | BC_V0 | BC_A0 | BC_PF
+BC_REST = BC_DEFAULT | BC_VF | BC_AF
+FP32, BF16_MIXED = 0, 1
+
+EXPORTS = (
+    "priest_init_problem", "priest_free_problem", "priest_problem_dim", "priest_project",
+    "priest_plan_workspace_size", "priest_plan", "priest_plan_batch", "priest_debug_offsets",
+    "priest_debug_normals", "priest_debug_constants", "priest_last_error", "priest_version",
+)
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("n_coeff", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_obs", ctypes.c_int32),
+                ("horizon", ctypes.c_double), ("rho", ctypes.c_double),
+                ("v_max", ctypes.c_double), ("a_max", ctypes.c_double),
+                ("bc_mask", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("n_refine_fp32", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CemParams(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("n_cem", ctypes.c_int32),
+                ("n_proj_iters", ctypes.c_int32), ("n_proj", ctypes.c_int32),
+                ("n_elite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("gamma", ctypes.c_float),
+                ("cov_jitter", ctypes.c_float), ("reserved_f", ctypes.c_float)]
+
+
+class PlanOut(ctypes.Structure):
+    _fields_ = [("best_xi", ctypes.c_void_p), ("best_cost", ctypes.c_void_p),
+                ("elite_idx", ctypes.c_void_p), ("proj_idx", ctypes.c_void_p),
+                ("xi", ctypes.c_void_p), ("xi_bar", ctypes.c_void_p),
+                ("resid", ctypes.c_void_p), ("c1", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+class PriestError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"priest status {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_SIGS = {
+    "priest_init_problem": (_I, [ctypes.POINTER(ProblemDesc), _P, ctypes.POINTER(_P)]),
+    "priest_free_problem": (_I, [_P]),
+    "priest_problem_dim": (_I, [_P]),
+    "priest_project": (_I, [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P]),
+    "priest_plan_workspace_size": (_I, [_P, ctypes.POINTER(CemParams), _I,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "priest_plan": (_I, [_P, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
+                         ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P, ctypes.c_size_t, _P]),
+    "priest_plan_batch": (_I, [_P, _I, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
+                               ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P, ctypes.c_size_t,
+                               _I, _P]),
+    "priest_debug_offsets": (_I, [_P, _P, _P, _P, _I, _P, _P]),
+    "priest_debug_normals": (_I, [ctypes.c_uint64, ctypes.c_uint32, _I, _I, _I, _P, _P]),
+    "priest_debug_constants": (_I, [_P, _I, _P, _I]),
+    "priest_last_error": (ctypes.c_char_p, []),
+    "priest_version": (_I, []),
+}
+
+
+def lib():
+    """Loads libpriest.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2309_08235_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = handle
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != PRIEST_OK:
+        raise PriestError(rc, lib().priest_last_error().decode())
+
+
+def _ptr(t, dtype=torch.float32):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# C-named functions
+# ---------------------------------------------------------------------------
+def priest_init_problem(desc: ProblemDesc, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().priest_init_problem(ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def priest_free_problem(handle):
+    _check(lib().priest_free_problem(handle))
+
+
+def priest_problem_dim(handle) -> int:
+    return lib().priest_problem_dim(handle)
+
+
+def priest_project(handle, bc, obs, xi_in, n_iter, xi_out, resid=None, c1=None, stream=None):
+    _check(lib().priest_project(handle, _ptr(bc), _ptr(obs), _ptr(xi_in), xi_in.shape[0], n_iter,
+                                _ptr(xi_out), _ptr(resid), _ptr(c1), _stream(stream)))
+
+
+def priest_plan_workspace_size(handle, params: CemParams, n_problems: int = 1) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().priest_plan_workspace_size(handle, ctypes.byref(params), n_problems, ctypes.byref(n)))
+    return n.value
+
+
+def _plan_out(out: dict) -> PlanOut:
+    po = PlanOut()
+    for name, dtype in (("best_xi", torch.float32), ("best_cost", torch.float32),
+                        ("elite_idx", torch.int32), ("proj_idx", torch.int32),
+                        ("xi", torch.float32), ("xi_bar", torch.float32),
+                        ("resid", torch.float32), ("c1", torch.float32), ("status", torch.int32)):
+        setattr(po, name, _ptr(out.get(name), dtype))
+    return po
+
+
+def priest_plan(handle, bc, obs, params: CemParams, mu, cov, seed, stream_id, noise, out: dict,
+                workspace, stream=None):
+    po = _plan_out(out)
+    _check(lib().priest_plan(handle, _ptr(bc), _ptr(obs), ctypes.byref(params), _ptr(mu), _ptr(cov),
+                             seed, stream_id, _ptr(noise), ctypes.byref(po),
+                             _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def priest_plan_batch(handle, n_problems, bc, obs, params: CemParams, mu, cov, seed, stream_base,
+                      noise, out: dict, workspace, use_graph=False, stream=None):
+    po = _plan_out(out)
+    _check(lib().priest_plan_batch(handle, n_problems, _ptr(bc), _ptr(obs), ctypes.byref(params),
+                                   _ptr(mu), _ptr(cov), seed, stream_base, _ptr(noise),
+                                   ctypes.byref(po), _ptr(workspace, torch.uint8),
+                                   workspace.numel(), int(bool(use_graph)), _stream(stream)))
+
+
+def priest_debug_offsets(handle, bc, obs, xi, offsets, stream=None):
+    _check(lib().priest_debug_offsets(handle, _ptr(bc), _ptr(obs), _ptr(xi), xi.shape[0],
+                                      _ptr(offsets), _stream(stream)))
+
+
+def priest_debug_normals(seed, stream_id, it, z, stream=None):
+    _check(lib().priest_debug_normals(seed, stream_id, it, z.shape[0], z.shape[1], _ptr(z),
+                                      _stream(stream)))
+
+
+def priest_debug_constants(handle, which: int, count: int):
+    buf = (ctypes.c_float * count)()
+    _check(lib().priest_debug_constants(handle, which, buf, count))
+    return list(buf)
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+@dataclass
+class Cem:
+    n_samples: int
+    n_cem: int
+    n_proj_iters: int
+    n_proj: int
+    n_elite: int
+    sigma: float = 0.5
+    gamma: float = 1.0
+    cov_jitter: float = 1e-5
+
+    def c(self) -> CemParams:
+        return CemParams(self.n_samples, self.n_cem, self.n_proj_iters, self.n_proj,
+                         self.n_elite, 0, self.sigma, self.gamma, self.cov_jitter, 0.0)
+
+
+class Problem:
+    """Owns a priest_problem handle; methods take/return torch tensors on the GPU."""
+
+    def __init__(self, dims, n_coeff, n_steps, horizon, n_obs, rho=1.0, v_max=math.inf,
+                 a_max=math.inf, bc_mask=BC_DEFAULT, precision=FP32, n_refine_fp32=10,
+                 stream=None):
+        self.desc = ProblemDesc(dims, n_coeff, n_steps, n_obs, horizon, rho, v_max, a_max,
+                                bc_mask, precision, n_refine_fp32, 0)
+        self.dims, self.n_coeff, self.n_steps, self.n_obs = dims, n_coeff, n_steps, n_obs
+        self.D = dims * n_coeff
+        self.handle = priest_init_problem(self.desc, stream)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        d = dict(dims=wl.dims, n_coeff=wl.n_coeff, n_steps=wl.n_steps, horizon=wl.horizon,
+                 n_obs=wl.n_obs, rho=wl.rho, v_max=wl.v_max, a_max=wl.a_max, bc_mask=wl.bc_mask)
+        d.update(kw)
+        return cls(**d)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            priest_free_problem(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def project(self, bc, obs, xi, n_iter, stream=None):
+        N = xi.shape[0]
+        dev = xi.device
+        xo = torch.empty_like(xi)
+        r = torch.empty(N, device=dev, dtype=torch.float32)
+        c1 = torch.empty(N, device=dev, dtype=torch.float32)
+        priest_project(self.handle, bc, obs, xi, n_iter, xo, r, c1, stream)
+        return xo, r, c1
+
+    def offsets(self, bc, obs, xi, stream=None):
+        out = torch.empty((xi.shape[0], self.n_obs + 2, self.n_steps, self.dims),
+                          device=xi.device, dtype=torch.float32)
+        priest_debug_offsets(self.handle, bc, obs, xi, out, stream)
+        return out
+
+    def constants(self):
+        nv, K = self.n_coeff, self.n_steps
+        import numpy as np
+        return {
+            "M11": np.array(priest_debug_constants(self.handle, 0, nv * nv)).reshape(nv, nv),
+            "Pi": np.array(priest_debug_constants(self.handle, 1, nv * nv)).reshape(nv, nv),
+            "M12": np.array(priest_debug_constants(self.handle, 2, nv * 6)).reshape(nv, 6),
+            "W": np.array(priest_debug_constants(self.handle, 3, K * 3 * nv)).reshape(K, 3, nv),
+        }
+
+    def plan_outputs(self, cem: Cem, n_problems=1, full=True, device="cuda"):
+        P, N, D = n_problems, cem.n_samples, self.D
+        f = dict(device=device, dtype=torch.float32)
+        i = dict(device=device, dtype=torch.int32)
+        out = {"best_xi": torch.empty((P, D), **f), "best_cost": torch.empty(P, **f),
+               "elite_idx": torch.empty((P, cem.n_elite), **i),
+               "proj_idx": torch.empty((P, cem.n_proj), **i), "status": torch.empty(P, **i)}
+        if full:
+            out.update({"xi": torch.empty((P, N, D), **f), "xi_bar": torch.empty((P, N, D), **f),
+                        "resid": torch.empty((P, N), **f), "c1": torch.empty((P, N), **f)})
+        return out
+
+    def workspace(self, cem: Cem, n_problems=1, device="cuda"):
+        n = priest_plan_workspace_size(self.handle, cem.c(), n_problems)
+        return torch.empty(n, dtype=torch.uint8, device=device)
+
+    def plan(self, bc, obs, cem: Cem, mu, cov, seed=0, stream_id=0, noise=None, out=None,
+             workspace=None, stream=None):
+        """Runs Alg. 1 in place on (mu, cov); returns the output dict."""
+        out = out if out is not None else self.plan_outputs(cem)
+        ws = workspace if workspace is not None else self.workspace(cem)
+        priest_plan(self.handle, bc, obs, cem.c(), mu, cov, seed, stream_id, noise, out, ws, stream)
+        return out
+
+    def plan_batch(self, n_problems, bc, obs, cem: Cem, mu, cov, seed=0, stream_base=0,
+                   noise=None, out=None, workspace=None, use_graph=False, stream=None):
+        out = out if out is not None else self.plan_outputs(cem, n_problems)
+        ws = workspace if workspace is not None else self.workspace(cem, n_problems)
+        priest_plan_batch(self.handle, n_problems, bc, obs, cem.c(), mu, cov, seed, stream_base,
+                          noise, out, ws, use_graph, stream)
+        return out
