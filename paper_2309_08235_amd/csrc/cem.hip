@@ -1,42 +1,48 @@
 // Selection, refit and covariance factorisation of the sampling loop (Alg. 1,
-// eqs. (9a)-(9c)) on gfx950: one 1024-thread block per problem.
+// eqs. (9a)-(9c)) on gfx950: one 512-thread block per problem.
 //
 //   1. ConstraintEliteSet: the n_proj samples with the lowest residual r,
-//      ordered by (r, index) - a bitonic sort of 64-bit keys in LDS;
+//      ordered by (r, index) - a stable block radix sort of the order-
+//      preserving bit patterns of r (ties keep index order);
 //   2. EliteSet: the n_elite lowest c_aug = c1 + r among them, ties kept in
-//      the order of step 1;
+//      the order of step 1 (second stable radix sort, on positions);
 //   3. weights c_m = exp(-(c_aug_m - delta)/gamma), delta = min c_aug;
 //   4. mu' = (1-sigma) mu + sigma sum w xi_bar / sum w,
 //      Sigma' = (1-sigma) Sigma + sigma sum w (xi_bar - mu')(xi_bar - mu')^T / sum w;
-//   5. L = chol(Sigma' + eps I), eps = cov_jitter tr(Sigma')/D, for the next draw.
+//   5. L = chol(Sigma' + eps I), eps = cov_jitter tr(Sigma')/D, for the next
+//      draw: one wave, lane i holds row i in registers.
 // Every sum runs in a fixed order, so results are bitwise reproducible.
 #include "priest_internal.h"
+
+#include <hipcub/block/block_radix_sort.hpp>
+
+// Phase markers (no-ops unless a profiling build defines them).
+#ifndef PRIEST_CEM_MARK
+#define PRIEST_CEM_MARK(i)
+#endif
 
 namespace priest {
 namespace {
 
-__host__ __device__ inline int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
+constexpr int kStageFloats = 4096;  // elite rows staged in LDS per chunk
+constexpr int kOwn = 3;             // covariance entries per thread (D <= 48)
 
 __host__ __device__ inline size_t align16(size_t n) { return (n + 15) & ~static_cast<size_t>(15); }
 
 struct CemLayout {
-  size_t keys, proj, elite, w, red, mu, A, total;
+  size_t proj, elite, w, red, mu, A, stage, total;
 };
 
-__host__ __device__ inline CemLayout cem_layout(int N, int D, int n_proj, int n_elite) {
+__host__ __device__ inline CemLayout cem_layout(int D, int n_proj, int n_elite) {
   CemLayout l{};
   size_t o = 0;
-  l.keys = o;  o += align16(sizeof(uint64_t) * pow2_at_least(N > 1 ? N : 2));
   l.proj = o;  o += align16(sizeof(int) * (n_proj > 0 ? n_proj : 1));
   l.elite = o; o += align16(sizeof(int) * (n_elite > 0 ? n_elite : 1));
   l.w = o;     o += align16(sizeof(float) * (n_elite > 0 ? n_elite : 1));
-  l.red = o;   o += align16(sizeof(float) * kCemThreads);
+  l.red = o;   o += align16(sizeof(float) * 64);
   l.mu = o;    o += align16(sizeof(float) * D);
   l.A = o;     o += align16(sizeof(float) * D * D);
+  l.stage = o; o += align16(sizeof(float) * kStageFloats);
   l.total = o;
   return l;
 }
@@ -49,68 +55,80 @@ __device__ __forceinline__ uint32_t ordered_bits(float v) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__device__ void bitonic_sort(uint64_t* k, int n) {
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool asc = (lo & size) == 0;
-        const uint64_t x = k[lo], y = k[hi];
-        if ((x > y) == asc) { k[lo] = y; k[hi] = x; }
-      }
-      __syncthreads();
-    }
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Lower Cholesky of the D x D matrix A (LDS) by one wave, rows padded to DM
+// with the identity; lane i keeps row i in registers and column j is
+// broadcast lane by lane.  Writes L back into A (lower triangle).  Returns
+// false if a pivot is not positive and finite (it is replaced by 1).
+template <int DM>
+__device__ bool cholesky_wave(float* A, int D, int lane) {
+  float row[DM];
+#pragma unroll
+  for (int c = 0; c < DM; ++c)
+    row[c] = (lane < D && c < D) ? A[lane * D + c] : (lane == c ? 1.0f : 0.0f);
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < DM; ++j) {
+    const float piv = bcast(row[j], j);
+    const bool b = !(piv > 0.0f) || !(piv < 3.0e38f);
+    bad = bad || b;
+    const float ljj = b ? 1.0f : sqrtf(piv);
+    const float lij = (lane > j) ? row[j] / ljj : ((lane == j) ? ljj : row[j]);
+    row[j] = lij;
+#pragma unroll
+    for (int c = j + 1; c < DM; ++c) row[c] = fmaf(-lij, bcast(lij, c), row[c]);
+  }
+  if (lane < D) {
+#pragma unroll
+    for (int c = 0; c < DM; ++c)
+      if (c <= lane && c < D) A[lane * D + c] = row[c];
+  }
+  return !bad;
+}
+
+
+// Stable selection of the k smallest keys among n (n <= T * IPT): writes the
+// values of ranks 0..k-1 to out[] in ascending (key, input position) order.
+template <int IPT>
+__device__ void select_sorted(const uint32_t* keys_in, const int* vals_in, int n, int k,
+                              int* out, void* temp) {
+  using Sort = hipcub::BlockRadixSort<uint32_t, kCemThreads, IPT, int>;
+  uint32_t key[IPT];
+  int val[IPT];
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int e = threadIdx.x * IPT + i;
+    key[i] = (e < n) ? keys_in[e] : 0xffffffffu;
+    val[i] = (e < n) ? vals_in[e] : -1;
+  }
+  Sort(*reinterpret_cast<typename Sort::TempStorage*>(temp)).Sort(key, val);
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int rnk = threadIdx.x * IPT + i;
+    if (rnk < k) out[rnk] = val[i];
   }
 }
 
-// Deterministic block sum of v over threads (fixed tree).
-__device__ float block_sum(float v, float* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const float r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// In-place lower Cholesky of the D x D matrix A in LDS (right-looking).
-// Returns false if a pivot is not positive and finite.
-__device__ bool cholesky_lds(float* A, int D, float* red) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < D; ++j) {
-    if (threadIdx.x == 0) {
-      const float ajj = A[j * D + j];
-      if (!(ajj > 0.0f) || !(ajj < 3.0e38f)) { bad = 1; A[j * D + j] = 1.0f; }
-      else A[j * D + j] = sqrtf(ajj);
-    }
-    __syncthreads();
-    const float ljj = A[j * D + j];
-    for (int i = j + 1 + threadIdx.x; i < D; i += blockDim.x) A[i * D + j] /= ljj;
-    __syncthreads();
-    const int m = D - j - 1;
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e / m, c = j + 1 + e % m;
-      if (c <= i) A[i * D + c] = fmaf(-A[i * D + j], A[c * D + j], A[i * D + c]);
-    }
-    __syncthreads();
-  }
-  (void)red;
-  return bad == 0;
-}
-
+template <int IPT, int DM>
 __global__ __launch_bounds__(kCemThreads) void cem_kernel(CemArgs a) {
+  using Sort = hipcub::BlockRadixSort<uint32_t, kCemThreads, IPT, int>;
+  __shared__ typename Sort::TempStorage sort_tmp;
+  __shared__ uint32_t skey[kCemThreads * IPT];
+  __shared__ int sval[kCemThreads * IPT];
   extern __shared__ float4 sm4[];
   char* sm = reinterpret_cast<char*>(sm4);
   const int prob = blockIdx.x;
   const int D = a.D, N = a.N, tid = threadIdx.x, T = blockDim.x;
-  const CemLayout l = cem_layout(N, D, a.n_proj, a.n_elite);
-  uint64_t* keys = reinterpret_cast<uint64_t*>(sm + l.keys);
+  const CemLayout l = cem_layout(D, a.n_proj, a.n_elite);
   int* proj = reinterpret_cast<int*>(sm + l.proj);
   int* elite = reinterpret_cast<int*>(sm + l.elite);
   float* w = reinterpret_cast<float*>(sm + l.w);
@@ -120,74 +138,116 @@ __global__ __launch_bounds__(kCemThreads) void cem_kernel(CemArgs a) {
   float* mu = a.mu + prob * a.mu_stride;
   float* cov = a.cov + prob * a.cov_stride;
   float* L = a.L + prob * a.L_stride;
+  PRIEST_CEM_MARK(0);
 
   if (!a.chol_only) {
     const float* r = a.resid + prob * a.n_stride;
     const float* c1 = a.c1 + prob * a.n_stride;
     const float* xb = a.xb + prob * a.xb_stride;
     // 1. lowest residuals
-    const int n1 = pow2_at_least(N > 1 ? N : 2);
-    for (int i = tid; i < n1; i += T)
-      keys[i] = (i < N) ? ((static_cast<uint64_t>(ordered_bits(r[i])) << 32) | static_cast<uint32_t>(i))
-                        : ~0ull;
+    for (int i = tid; i < N; i += T) {
+      skey[i] = ordered_bits(r[i]);
+      sval[i] = i;
+    }
     __syncthreads();
-    bitonic_sort(keys, n1);
-    for (int i = tid; i < a.n_proj; i += T) {
-      proj[i] = static_cast<int>(keys[i] & 0xffffffffu);
+    select_sorted<IPT>(skey, sval, N, a.n_proj, proj, &sort_tmp);
+    __syncthreads();
+    PRIEST_CEM_MARK(1);
+    for (int i = tid; i < a.n_proj; i += T)
       if (a.proj_idx) a.proj_idx[prob * a.n_proj + i] = proj[i];
-    }
-    __syncthreads();
     // 2. lowest c_aug within them; ties keep the order of step 1
-    const int n2 = pow2_at_least(a.n_proj > 1 ? a.n_proj : 2);
-    for (int i = tid; i < n2; i += T) {
-      if (i < a.n_proj) {
-        const int s = proj[i];
-        keys[i] = (static_cast<uint64_t>(ordered_bits(c1[s] + r[s])) << 32) | static_cast<uint32_t>(i);
-      } else {
-        keys[i] = ~0ull;
-      }
+    for (int i = tid; i < a.n_proj; i += T) {
+      const int s = proj[i];
+      skey[i] = ordered_bits(c1[s] + r[s]);
+      sval[i] = i;
     }
     __syncthreads();
-    bitonic_sort(keys, n2);
+    select_sorted<IPT>(skey, sval, a.n_proj, a.n_elite, elite, &sort_tmp);
+    __syncthreads();
     for (int m = tid; m < a.n_elite; m += T) {
-      elite[m] = proj[keys[m] & 0xffffffffu];
+      elite[m] = proj[elite[m]];
       if (a.elite_idx) a.elite_idx[prob * a.n_elite + m] = elite[m];
     }
     __syncthreads();
-    // 3. weights
+    PRIEST_CEM_MARK(2);
+    // 3. weights; fixed-order sum by the first wave
     const int e0 = elite[0];
     const float delta = c1[e0] + r[e0];
-    float part = 0.0f;
     for (int m = tid; m < a.n_elite; m += T) {
       const int s = elite[m];
-      const float wm = expf(-((c1[s] + r[s]) - delta) / a.gamma);
-      w[m] = wm;
+      w[m] = expf(-((c1[s] + r[s]) - delta) / a.gamma);
     }
     __syncthreads();
-    // fixed-order partial sums: thread t sums m = t, t+T, ...
-    for (int m = tid; m < a.n_elite; m += T) part += w[m];
-    const float sw = block_sum(part, red);
-    const float inv_sw = 1.0f / sw;
-    // 4a. mean
-    for (int d = tid; d < D; d += T) {
-      float s = 0.0f;
-      for (int m = 0; m < a.n_elite; ++m) s = fmaf(w[m], xb[static_cast<int64_t>(elite[m]) * D + d], s);
-      muN[d] = (1.0f - a.sigma) * mu[d] + a.sigma * (s * inv_sw);
+    if (tid < 64) {
+      float part = 0.0f;
+      for (int m = tid; m < a.n_elite; m += 64) part += w[m];
+      part = wave_sum(part);
+      if (tid == 0) red[0] = part;
     }
     __syncthreads();
-    // 4b. covariance about the new mean (lower triangle, then mirrored)
-    for (int e = tid; e < D * D; e += T) {
-      const int i = e / D, j = e - i * D;
-      if (j > i) continue;
-      float s = 0.0f;
-      const float mi = muN[i], mj = muN[j];
-      for (int m = 0; m < a.n_elite; ++m) {
-        const float* x = xb + static_cast<int64_t>(elite[m]) * D;
-        s = fmaf(w[m] * (x[i] - mi), x[j] - mj, s);
+    const float inv_sw = 1.0f / red[0];
+    PRIEST_CEM_MARK(3);
+    // 4. mean and covariance from elite rows staged in LDS, CH rows at a time
+    float* stage = reinterpret_cast<float*>(sm + l.stage);
+    const int CH = kStageFloats / D;
+    float macc = 0.0f;
+    for (int m0 = 0; m0 < a.n_elite; m0 += CH) {
+      const int nm = min(CH, a.n_elite - m0);
+      for (int i = tid; i < nm * D; i += T) {
+        const int m = i / D;
+        stage[i] = xb[static_cast<int64_t>(elite[m0 + m]) * D + (i - m * D)];
       }
-      const float v = (1.0f - a.sigma) * cov[e] + a.sigma * (s * inv_sw);
-      A[i * D + j] = v;
-      A[j * D + i] = v;
+      __syncthreads();
+      if (tid < D) {
+#pragma unroll 8
+        for (int m = 0; m < nm; ++m) macc = fmaf(w[m0 + m], stage[m * D + tid], macc);
+      }
+      __syncthreads();
+    }
+    if (tid < D) muN[tid] = (1.0f - a.sigma) * mu[tid] + a.sigma * (macc * inv_sw);
+    __syncthreads();
+    PRIEST_CEM_MARK(4);
+    // covariance about the new mean: thread tid owns lower-triangle entries
+    // e = tid + k T, k < kOwn
+    const int ntri = D * (D + 1) / 2;
+    int ti[kOwn], tj[kOwn];
+    float cacc[kOwn] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < kOwn; ++k) {
+      const int e = tid + k * T;
+      int i = 0;
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      ti[k] = i;
+      tj[k] = e - i * (i + 1) / 2;
+    }
+    for (int m0 = 0; m0 < a.n_elite; m0 += CH) {
+      const int nm = min(CH, a.n_elite - m0);
+      for (int i = tid; i < nm * D; i += T) {
+        const int m = i / D;
+        stage[i] = xb[static_cast<int64_t>(elite[m0 + m]) * D + (i - m * D)];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kOwn; ++k) {
+        if (tid + k * T < ntri) {
+          const float mi = muN[ti[k]], mj = muN[tj[k]];
+          float acc = cacc[k];
+#pragma unroll 8
+          for (int m = 0; m < nm; ++m)
+            acc = fmaf(w[m0 + m] * (stage[m * D + ti[k]] - mi), stage[m * D + tj[k]] - mj, acc);
+          cacc[k] = acc;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kOwn; ++k) {
+      if (tid + k * T < ntri) {
+        const int i = ti[k], j = tj[k];
+        const float v = (1.0f - a.sigma) * cov[i * D + j] + a.sigma * (cacc[k] * inv_sw);
+        A[i * D + j] = v;
+        A[j * D + i] = v;
+      }
     }
     __syncthreads();
     for (int e = tid; e < D * D; e += T) cov[e] = A[e];
@@ -197,37 +257,54 @@ __global__ __launch_bounds__(kCemThreads) void cem_kernel(CemArgs a) {
     }
     if (tid == 0) a.best_cost[prob] = delta;
     __syncthreads();
+    PRIEST_CEM_MARK(5);
   } else {
     for (int e = tid; e < D * D; e += T) A[e] = cov[e];
     __syncthreads();
   }
-  // 5. factor Sigma' + eps I
-  float tr = 0.0f;
-  for (int d = tid; d < D; d += T) tr += A[d * D + d];
-  const float eps = a.cov_jitter * block_sum(tr, red) / static_cast<float>(D);
-  for (int d = tid; d < D; d += T) A[d * D + d] += eps;
+  // 5. factor Sigma' + eps I (first wave)
+  if (tid < 64) {
+    float tr = 0.0f;
+    for (int d = tid; d < D; d += 64) tr += A[d * D + d];
+    tr = wave_sum(tr);
+    const float eps = a.cov_jitter * tr / static_cast<float>(D);
+    for (int d = tid; d < D; d += 64) A[d * D + d] += eps;
+    const bool ok = cholesky_wave<DM>(A, D, tid);
+    if (tid == 0 && a.status) {
+      bool fin = ok;
+      if (!a.chol_only) fin = fin && (a.best_cost[prob] == a.best_cost[prob]);
+      if (!fin) a.status[prob] = PRIEST_ERR_NONFINITE;
+    }
+  }
   __syncthreads();
-  const bool ok = cholesky_lds(A, D, red);
+  PRIEST_CEM_MARK(6);
   for (int e = tid; e < D * D; e += T) {
     const int i = e / D, j = e - i * D;
     L[e] = (j <= i) ? A[e] : 0.0f;
   }
-  if (tid == 0 && a.status) {
-    bool fin = ok;
-    if (!a.chol_only) fin = fin && (a.best_cost[prob] == a.best_cost[prob]);
-    if (!fin) a.status[prob] = PRIEST_ERR_NONFINITE;
-  }
+  PRIEST_CEM_MARK(7);
 }
 
 }  // namespace
 
 size_t cem_lds_bytes(int N, int D, int n_elite) {
-  return cem_layout(N, D, N, n_elite).total;
+  return cem_layout(D, N, n_elite).total;
+}
+
+template <int DM>
+static void launch_dm(const CemArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  if (a.N <= kCemThreads * 2) hipLaunchKernelGGL((cem_kernel<2, DM>), grid, block, lds, s, a);
+  else if (a.N <= kCemThreads * 4) hipLaunchKernelGGL((cem_kernel<4, DM>), grid, block, lds, s, a);
+  else hipLaunchKernelGGL((cem_kernel<16, DM>), grid, block, lds, s, a);
 }
 
 hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s) {
-  const size_t lds = cem_layout(a.N, a.D, a.n_proj, a.n_elite).total;
-  hipLaunchKernelGGL(cem_kernel, dim3(n_problems), dim3(kCemThreads), lds, s, a);
+  const size_t lds = cem_layout(a.D, a.n_proj, a.n_elite).total;
+  const dim3 grid(n_problems), block(kCemThreads);
+  // covariance factor rows padded to 24 / 36 / 48 (identity padding)
+  if (a.D <= 24) launch_dm<24>(a, grid, block, lds, s);
+  else if (a.D <= 36) launch_dm<36>(a, grid, block, lds, s);
+  else launch_dm<48>(a, grid, block, lds, s);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ namespace priest {
 
 constexpr int kMaxNV = PRIEST_MAX_COEFF;
 constexpr int kProjectThreads = 256;
-constexpr int kCemThreads = 1024;
+constexpr int kCemThreads = 512;
 
 // Sample sources of the projection kernel.
 enum SampleMode : int32_t {

@@ -1,393 +1,610 @@
-// Fused projection sweep for gfx950.
+// Fused projection sweep for gfx950 (MFMA + VALU, state in registers).
 //
-// One block owns a tile of S samples of one problem for the whole projection:
-// the samples' coefficient vectors (xi, xi_bar, lambda), the basis rows and
-// the obstacle table stay in LDS across all iterations, so HBM is touched only
-// to load the tile and write the result.  Per iteration (Appendix, eqs.
-// (15a)-(15g), rewritten for per-sample batching):
+// Work decomposition.  A block owns 4 samples of one problem for the whole
+// projection and has one 64-lane wave per 16-step time block (K <= 256, so at
+// most 16 waves).  Sample coefficients live in registers in the layout of the
+// 16x16 FP32 MFMA accumulator: column col = 4*sample + axis (axes padded to
+// 4), row = coefficient (padded to 16), lane l holding rows 4*(l/16)..+3 of
+// column l%16.  Per projection iteration (Appendix, eqs. (15a)-(15g), with
+// the per-sample batching of Sec. III-A):
 //
-//   phase 1  (sample, t) items: p, v, a = rows of [P; Pdot; Pddot] xi_bar;
-//            closed-form alpha/beta/d of every obstacle as a push-out
-//            delta_o = Delta * max(0, 1/n - 1) (n = scaled distance), summed
-//            over obstacles; velocity / acceleration push-outs
-//            delta = w * min(0, w_max/|w| - 1)            -> LDS
-//   phase 2  right-hand side g = P^T S_o + Pdot^T delta_v + Pddot^T delta_a
-//            (= F^T (e^{k+1} - F xi_bar^k), obstacle sum taken first)
-//   phase 3  multiplier lambda += rho g (eq. (15e)) and the QP of eq. (15g)
-//            through the fixed KKT block:
-//              k = 0 : xi_bar = Pi xi + c0 + M11 (lambda + rho g)
-//              k > 0 : xi_bar += M11 (xi - xi_bar + lambda + rho g)
-//            The k > 0 form equals M11 eta + M12 b whenever A xi_bar = b,
-//            which holds after the first step, and avoids cancelling
-//            n_obs |p| against rho F^T F xi_bar in FP32.
+//   forward   p, v, a rows of this wave's time block = W xi_bar
+//             (3 chains of 4 MFMA 16x16x4, W = [P; Pdot; Pddot] rows as A)
+//   transpose quad-local 4x4 transpose through LDS: lane l now holds every
+//             axis of one (sample, t) item, t = t0 + 4*(l/16) + l%4
+//   push-out  closed-form alpha/beta/d of each obstacle as a push-out
+//             Delta * max(0, 1/n - 1) (n = scaled distance), summed over the
+//             obstacles that survive a wave-level bounding-box cull;
+//             velocity / acceleration push-outs w * min(0, w_max/|w| - 1)
+//   transpose back to the column layout
+//   RHS       g_partial = W^T delta for this time block (MFMA, the sum over t
+//             is the MFMA reduction); partials of all waves summed through
+//             LDS in fixed order (one barrier)
+//   update    lambda += rho g (eq. (15e)); QP of eq. (15g) through the fixed
+//             KKT block, redone identically by every wave (MFMA):
+//               k = 0 : xi_bar = Pi xi + c0 + M11 (lambda + rho g)
+//               k > 0 : xi_bar += M11 (xi - xi_bar + lambda + rho g)
+//             The k > 0 form equals M11 eta + M12 b whenever A xi_bar = b,
+//             which holds after the first step; it avoids cancelling
+//             n_obs |p| against rho F^T F xi_bar in FP32.
 //
-// After the last iteration one more phase 1 evaluates r(xi_bar) and the
-// smoothness cost c1 = sum_t |a_t|^2 with fixed-order (deterministic) sums.
+// After the last iteration one more forward + push-out pass evaluates
+// r(xi_bar) and c1 = sum_t |a_t|^2, summed per sample in fixed order.
 #include "priest_internal.h"
+
+// Phase markers inside a projection iteration (no-ops unless a profiling
+// build defines them).
+#ifndef PRIEST_PROJ_MARK
+#define PRIEST_PROJ_MARK(i)
+#endif
 
 namespace priest {
 namespace {
 
-struct Layout {  // offsets into dynamic LDS, in floats
-  int W, obs, ab, M11, Pi, c0, X, Xb, Lam, U, Delta, G, mu, L, Z, total;
-};
+using f4 = __attribute__((ext_vector_type(4))) float;
 
 __host__ __device__ inline int round4(int n) { return (n + 3) & ~3; }
 
-__host__ __device__ inline Layout layout(int dims, int nv, int K, int M, int S, int G, int mode) {
+// obstacle records: three float4 per obstacle
+__host__ __device__ inline int records_capacity(int M) { return M; }
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Orders this wave's LDS writes before its subsequent LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Layout {  // offsets into dynamic LDS, in floats
+  int rec, xt, gp, fin, mu, L, z, xs, total;
+};
+
+// rec: obstacle records (12 floats each); xt: per-wave transpose buffers;
+// gp: double-buffered per-wave partial right-hand sides; fin: per-item
+// residual^2 and c1 of the final pass; mu/L/z/xs: sampler staging.
+__host__ __device__ inline Layout layout(int dims, int nv, int M, int TW, int mode) {
   Layout l{};
-  int o = 0;
   const int D = dims * nv;
-  l.W = o;   o += round4(K * 3 * nv);
-  l.obs = o; o += round4(M * 8);
-  l.ab = o;  o += round4(M * 2);
-  l.M11 = o; o += round4(nv * nv);
-  l.Pi = o;  o += round4(nv * nv);
-  l.c0 = o;  o += round4(D);
-  l.X = o;   o += round4(S * D);
-  l.Xb = o;  o += round4(S * D);
-  l.Lam = o; o += round4(S * D);
-  l.U = o;   o += round4(S * D);
-  // scratch: delta (phase 1/2) and partial sums (phase 2); the sampler's mu,
-  // L and z alias it before the first iteration
-  const int delta = round4(S * K * 3 * dims);
-  const int part = round4(G * S * D);
-  int scratch = delta + part;
-  const int samp = round4(D) + round4(D * D) + round4(S * round4(D));
-  if (mode != kFromInput && samp > scratch) scratch = samp;
-  l.Delta = o;
-  l.G = o + delta;
+  int o = 0;
+  l.rec = o; o += 12 * records_capacity(M);
+  l.xt = o;  o += TW * 3 * 256;
+  l.gp = o;  o += 2 * TW * 256;
+  l.fin = o; o += TW * 128;
+  l.xs = o;  o += 4 * round4(D);
   l.mu = o;
   l.L = o + round4(D);
-  l.Z = o + round4(D) + round4(D * D);
-  o += scratch;
+  l.z = o + round4(D) + round4(D * D);
+  if (mode != kFromInput) o += round4(D) + round4(D * D) + 4 * round4(D);
   l.total = o;
   return l;
 }
 
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// ---------------------------------------------------------------------------
+// Push-outs of one (sample, t) item (eqs. (15a)-(15c), (11a)-(11b) -> (13)).
+//
+// Obstacle records (scene order), three float4 each:
+//   R0 = (cx, cy, cz, cull)   cull = max(a, b) * 1.001 + 1e-4
+//   R1 = (vx, vy, vz, |v|)
+//   R2 = (a, a^2, 1/a^2, 1/b^2)
+// 2D uses circles of radius a (cz = vz = 0).  The push-out of obstacle j on a
+// robot at p is Delta (max(1, n)/n - 1) with Delta = p - o_j(t) and n the
+// scaled distance, i.e. f = max(0, a/|Delta| - 1) in 2D and
+// f = max(0, 1/n - 1) in 3D; a zero offset takes the canonical direction
+// (+x in 2D, +z in 3D).
+//
+// Culling: a wave tests all obstacles at once against the bounding box of its
+// 64 item positions (centre at the middle of the wave's time window, radius
+// cull + |v| * half-window) and loops only over the obstacles that may touch
+// the box.  A skipped obstacle is farther than a * 1.001 + 1e-4 from every
+// item, where the push-out is exactly 0, so culling does not change results.
+// ---------------------------------------------------------------------------
+constexpr float kTiny = 1.0e-30f;
 
-// Push-out of one obstacle at one instant (eqs. (15a)-(15c) -> (13)):
-// target - position = Delta * (max(1,n)/n - 1), n^2 = (dx^2+dy^2)/a^2 + dz^2/b^2.
-// A zero offset takes the canonical direction (+x in 2D, +z in 3D).
-template <int DIMS>
-__device__ __forceinline__ bool obstacle_push(const float* o, const float* ab, float tt,
-                                              const float p[DIMS], float d[DIMS]) {
-  // o = (cx, cy, cz, vx, vy, vz, 1/a^2, 1/b^2)
-  d[0] = p[0] - fmaf(o[3], tt, o[0]);
-  d[1] = p[1] - fmaf(o[4], tt, o[1]);
-  float q = (d[0] * d[0] + d[1] * d[1]) * o[6];
-  if (DIMS == 3) {
-    d[2] = p[2] - fmaf(o[5], tt, o[2]);
-    q = fmaf(d[2] * d[2], o[7], q);
-  }
-  if (!(q < 1.0f)) return false;
-  if (q > 0.0f) {
-    const float f = rsq(q) - 1.0f;
-#pragma unroll
-    for (int ax = 0; ax < DIMS; ++ax) d[ax] *= f;
-  } else {
-#pragma unroll
-    for (int ax = 0; ax < DIMS; ++ax) d[ax] = 0.0f;
-    if (DIMS == 3) d[DIMS - 1] = ab[1];
-    else d[0] = ab[0];
-  }
-  return true;
+// Wave-wide min / max: DPP within each row of 16 lanes (xor 1, xor 2,
+// rotate 4, rotate 8), then the four row results combined as uniform values.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF,
+                                                    0xF, false));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ float wave_min(float v) {
+  v = fminf(v, dpp<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fminf(v, dpp<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fminf(v, dpp<0x124>(v));  // row_ror:4
+  v = fminf(v, dpp<0x128>(v));  // row_ror:8
+  return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
+}
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x124>(v));
+  v = fmaxf(v, dpp<0x128>(v));
+  return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
 }
 
-// Push-out of a norm bound |w| <= wmax (eqs. (11a)/(11b)).
+struct Rec {  // one obstacle record held in (uniform) registers
+  float cx, cy, cz, vx, vy, vz, a, a2, ia2, ib2;
+  bool moving;
+};
+
+// Record of lane b broadcast to the wave; only the fields the push-out of a
+// DIMS-dimensional, static or moving obstacle reads.
+template <int DIMS>
+__device__ __forceinline__ Rec rec_from_lane(const float4& R0, const float4& R1, const float4& R2,
+                                             int b, bool moving) {
+  Rec r;
+  r.moving = moving;
+  r.cx = lane_f(R0.x, b);
+  r.cy = lane_f(R0.y, b);
+  r.cz = (DIMS == 3) ? lane_f(R0.z, b) : 0.0f;
+  r.vx = moving ? lane_f(R1.x, b) : 0.0f;
+  r.vy = moving ? lane_f(R1.y, b) : 0.0f;
+  r.vz = (moving && DIMS == 3) ? lane_f(R1.z, b) : 0.0f;
+  r.a = (DIMS == 2) ? lane_f(R2.x, b) : 0.0f;
+  r.a2 = (DIMS == 2) ? lane_f(R2.y, b) : 0.0f;
+  r.ia2 = (DIMS == 3) ? lane_f(R2.z, b) : 0.0f;
+  r.ib2 = (DIMS == 3) ? lane_f(R2.w, b) : 0.0f;
+  return r;
+}
+
+__device__ __forceinline__ Rec rec_from_lds(const float4* rec, int j) {
+  const float4 R0 = rec[3 * j], R1 = rec[3 * j + 1], R2 = rec[3 * j + 2];
+  Rec r;
+  r.cx = R0.x; r.cy = R0.y; r.cz = R0.z;
+  r.vx = R1.x; r.vy = R1.y; r.vz = R1.z;
+  r.moving = R1.w != 0.0f;
+  r.a = R2.x; r.a2 = R2.y; r.ia2 = R2.z; r.ib2 = R2.w;
+  return r;
+}
+
+// Push-out of one obstacle on one item, accumulated into s.  LAST: exact
+// hit test (so satisfied constraints give exactly 0) and r2 += |delta|^2.
+// Returns true if the offset is exactly zero (the caller adds the canonical
+// push-out for those lanes).
+template <int DIMS, bool LAST>
+__device__ __forceinline__ bool pair_push(const Rec& o, float tt, const float p[DIMS],
+                                          float s[DIMS], float& r2) {
+  float d[DIMS];
+  if (o.moving) {
+    d[0] = p[0] - fmaf(o.vx, tt, o.cx);
+    d[1] = p[1] - fmaf(o.vy, tt, o.cy);
+    if constexpr (DIMS == 3) d[2] = p[2] - fmaf(o.vz, tt, o.cz);
+  } else {
+    d[0] = p[0] - o.cx;
+    d[1] = p[1] - o.cy;
+    if constexpr (DIMS == 3) d[2] = p[2] - o.cz;
+  }
+  const float h = fmaf(d[1], d[1], d[0] * d[0]);
+  float q, f, len2;
+  if constexpr (DIMS == 2) {
+    q = h;
+    len2 = h;
+    f = fmaf(o.a, rsq(fmaxf(q, kTiny)), -1.0f);
+    if (LAST) f = (q < o.a2) ? f : 0.0f;
+  } else {
+    q = fmaf(d[2] * d[2], o.ib2, h * o.ia2);
+    len2 = fmaf(d[2], d[2], h);
+    f = rsq(fmaxf(q, kTiny)) - 1.0f;
+    if (LAST) f = (q < 1.0f) ? f : 0.0f;
+  }
+  f = fmaxf(f, 0.0f);
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x) s[x] = fmaf(d[x], f, s[x]);
+  if (LAST) r2 = fmaf(len2 * f, f, r2);
+  return q == 0.0f;
+}
+
+// Canonical push-out of a zero offset (+x by a in 2D, +z by b in 3D).
+template <int DIMS, bool LAST>
+__device__ __forceinline__ void zero_push(const Rec& o, float s[DIMS], float& r2) {
+  if constexpr (DIMS == 2) {
+    s[0] += o.a;
+    if (LAST) r2 += o.a2;
+  } else {
+    const float b = rsq(o.ib2);
+    s[2] += b;
+    if (LAST) r2 = fmaf(b, b, r2);
+  }
+}
+
 template <int DIMS>
 __device__ __forceinline__ float bound_push(const float w[DIMS], float wmax, float d[DIMS]) {
   float ww = 0.0f;
 #pragma unroll
-  for (int ax = 0; ax < DIMS; ++ax) ww = fmaf(w[ax], w[ax], ww);
+  for (int x = 0; x < DIMS; ++x) ww = fmaf(w[x], w[x], ww);
   float f = 0.0f;
-  if (ww > wmax * wmax) f = wmax * rsq(ww) - 1.0f;
+  if (ww > wmax * wmax) f = fmaf(wmax, rsq(ww), -1.0f);
 #pragma unroll
-  for (int ax = 0; ax < DIMS; ++ax) d[ax] = w[ax] * f;
+  for (int x = 0; x < DIMS; ++x) d[x] = w[x] * f;
   return ww * f * f;
 }
 
-template <int DIMS, int NVT>
-__device__ __forceinline__ void eval_row(const float* w, const float* xb, int nv_rt,
-                                         float p[DIMS], float v[DIMS], float acc[DIMS]) {
-  const int nv = NVT ? NVT : nv_rt;
-#pragma unroll
-  for (int ax = 0; ax < DIMS; ++ax) {
-    float sp = 0.0f, sv = 0.0f, sa = 0.0f;
-    const float* x = xb + ax * nv;
-#pragma unroll
-    for (int c = 0; c < (NVT ? NVT : kMaxNV); ++c) {
-      if (!NVT && c >= nv) break;
-      const float xc = x[c];
-      sp = fmaf(w[c], xc, sp);
-      sv = fmaf(w[nv + c], xc, sv);
-      sa = fmaf(w[2 * nv + c], xc, sa);
-    }
-    p[ax] = sp; v[ax] = sv; acc[ax] = sa;
+// Record table of one scene (any number of threads).
+template <int DIMS>
+__device__ void build_records(const float* obs, int M, int t, int nt, float4* rec) {
+  for (int j = t; j < M; j += nt) {
+    const float* o = obs + 8 * j;
+    const float a = o[6], b = (DIMS == 3) ? o[7] : o[6];
+    const float cz = (DIMS == 3) ? o[2] : 0.0f, vz = (DIMS == 3) ? o[5] : 0.0f;
+    const float sp = sqrtf(o[3] * o[3] + o[4] * o[4] + vz * vz);
+    rec[3 * j] = make_float4(o[0], o[1], cz, fmaxf(a, b) * 1.001f + 1.0e-4f);
+    rec[3 * j + 1] = make_float4(o[3], o[4], vz, sp);
+    rec[3 * j + 2] = make_float4(a, a * a, 1.0f / (a * a), 1.0f / (b * b));
   }
 }
 
-template <int DIMS, int NVT>
-__global__ __launch_bounds__(kProjectThreads) void project_kernel(ProjArgs a) {
+// Obstacle push-outs of this lane's item, summed over obstacles, with
+// wave-level culling.  tmid / thalf: centre and half-width of the wave's time
+// window.
+template <int DIMS, bool LAST>
+__device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, float tt, float tmid,
+                                                float thalf, bool ok, const float p[DIMS],
+                                                float S[DIMS], float& r2, int lane) {
+  float lo[DIMS], hi[DIMS];
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x) {
+    lo[x] = wave_min(ok ? p[x] : INFINITY);
+    hi[x] = wave_max(ok ? p[x] : -INFINITY);
+  }
+  PRIEST_PROJ_MARK(6);
+  for (int base = 0; base < M; base += 64) {
+    const int j = base + lane;
+    float4 R0 = make_float4(0, 0, 0, 0), R1 = R0, R2 = R0;
+    bool cand = false;
+    if (j < M) {
+      R0 = rec[3 * j];
+      R1 = rec[3 * j + 1];
+      R2 = rec[3 * j + 2];
+      const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y),
+                           fmaf(R1.z, tmid, R0.z)};
+      float d2 = 0.0f;
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) {
+        const float e = fmaxf(fmaxf(lo[x] - oc[x], oc[x] - hi[x]), 0.0f);
+        d2 = fmaf(e, e, d2);
+      }
+      const float rr = fmaf(R1.w, thalf, R0.w);
+      cand = d2 < rr * rr;
+    }
+    unsigned long long mask = __ballot(cand);
+    const unsigned long long moving = __ballot(cand && R1.w != 0.0f);
+    while (mask) {
+      const int b = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      if ((moving >> b) & 1ull) {
+        const Rec o = rec_from_lane<DIMS>(R0, R1, R2, b, true);
+        const bool zero = pair_push<DIMS, LAST>(o, tt, p, S, r2);
+        if (__ballot(zero && ok))
+          if (zero) zero_push<DIMS, LAST>(o, S, r2);
+      } else {
+        const Rec o = rec_from_lane<DIMS>(R0, R1, R2, b, false);
+        const bool zero = pair_push<DIMS, LAST>(o, tt, p, S, r2);
+        if (__ballot(zero && ok))
+          if (zero) zero_push<DIMS, LAST>(o, S, r2);
+      }
+    }
+  }
+  if (!ok) {
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) S[x] = 0.0f;
+    r2 = 0.0f;
+  }
+}
+
+template <int DIMS, bool LAST>
+__device__ __forceinline__ void item_push(const float4* rec, int M, float tt, float tmid,
+                                          float thalf, bool ok, const float p[DIMS],
+                                          const float v[DIMS], const float ac[DIMS], float vmax,
+                                          float amax, float S[DIMS], float dv[DIMS],
+                                          float da[DIMS], float& r2, int lane) {
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x) { S[x] = 0.0f; dv[x] = 0.0f; da[x] = 0.0f; }
+  r2 = 0.0f;
+  obstacle_pushes<DIMS, LAST>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane);
+  if (ok) {
+    r2 += bound_push<DIMS>(v, vmax, dv);
+    r2 += bound_push<DIMS>(ac, amax, da);
+  }
+}
+
+template <int DIMS, int MAXT>
+__global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
-  const int nv = NVT ? NVT : a.nv;
-  const int K = a.K, M = a.M, S = a.S, G = a.G;
-  const int D = DIMS * nv;
-  const Layout l = layout(DIMS, nv, K, M, S, G, a.mode);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, TW = blockDim.x >> 6;
+  const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv;
+  const Layout l = layout(DIMS, nv, M, TW, a.mode);
   const int prob = blockIdx.x / a.blocks_per_problem;
-  const int tile = blockIdx.x - prob * a.blocks_per_problem;
-  const int s0 = tile * S;
-  const int ns = min(S, a.N - s0);
-  const int tid = threadIdx.x, T = blockDim.x;
+  const int s0 = (blockIdx.x - prob * a.blocks_per_problem) * 4;
+  const int ns = min(4, a.N - s0);
+  // MFMA column layout: q = row group, col = 4*cs + cx
+  const int q = lane >> 4, col = lane & 15, cs = col >> 2, cx = col & 3;
+  // item layout after the transpose: sample cs, timestep t0 + 4q + ia
+  const int ia = lane & 3;
+  const int t0 = 16 * w;
+  const int t_item = t0 + 4 * q + ia;
+  const bool item_ok = (t_item < K) && (cs < ns);
+  const float tt = a.dt * static_cast<float>(t_item);
+  const float tmid = a.dt * (static_cast<float>(t0) + 7.5f);
+  const float thalf = a.dt * 7.5f;
 
-  float* sW = sm + l.W;
-  float* sObs = sm + l.obs;
-  float* sAB = sm + l.ab;
-  float* sM11 = sm + l.M11;
-  float* sPi = sm + l.Pi;
-  float* sC0 = sm + l.c0;
-  float* sX = sm + l.X;
-  float* sXb = sm + l.Xb;
-  float* sLam = sm + l.Lam;
-  float* sU = sm + l.U;
-  float* sDelta = sm + l.Delta;
-  float* sG = sm + l.G;
+  float4* rec = reinterpret_cast<float4*>(sm + l.rec);
+  float* xs = sm + l.xs;
 
-  // ---- constants -----------------------------------------------------------
-  for (int i = tid; i < K * 3 * nv; i += T) sW[i] = a.W[i];
-  const float* obs = a.obs + prob * a.obs_stride;
-  for (int j = tid; j < M; j += T) {
-    const float* o = obs + 8 * j;
-    float* so = sObs + 8 * j;
-    so[0] = o[0]; so[1] = o[1]; so[2] = (DIMS == 3) ? o[2] : 0.0f;
-    so[3] = o[3]; so[4] = o[4]; so[5] = (DIMS == 3) ? o[5] : 0.0f;
-    const float ra = o[6], rb = (DIMS == 3) ? o[7] : o[6];
-    so[6] = 1.0f / (ra * ra);
-    so[7] = 1.0f / (rb * rb);
-    sAB[2 * j] = ra;
-    sAB[2 * j + 1] = rb;
-  }
-  for (int i = tid; i < nv * nv; i += T) { sM11[i] = a.M11[i]; sPi[i] = a.Pi[i]; }
-  const float* bc = a.bc + prob * a.bc_stride;
-  for (int i = tid; i < D; i += T) {
-    const int ax = i / nv, c = i - ax * nv;
-    float s = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 6; ++r) s = fmaf(a.M12[c * 6 + r], bc[ax * 6 + r], s);
-    sC0[i] = s;
-  }
-
-  // ---- samples -------------------------------------------------------------
+  // ---- scene records, samples ---------------------------------------------
+  build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
   if (a.mode == kFromInput) {
     const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(s0) * D;
-    for (int i = tid; i < ns * D; i += T) sX[i] = src[i];
+    for (int i = tid; i < ns * D; i += blockDim.x) xs[(i / D) * round4(D) + i % D] = src[i];
   } else {
     float* sMu = sm + l.mu;
     float* sL = sm + l.L;
-    float* sZ = sm + l.Z;
+    float* sZ = sm + l.z;
     const int D4 = round4(D);
     const float* mu = a.mu + prob * a.mu_stride;
-    const float* L = a.L + prob * a.L_stride;
-    for (int i = tid; i < D; i += T) sMu[i] = mu[i];
-    for (int i = tid; i < D * D; i += T) sL[i] = L[i];
+    const float* Lm = a.L + prob * a.L_stride;
+    for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
+    for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
     if (a.mode == kFromNoise) {
       const float* z = a.noise + prob * a.noise_stride + static_cast<int64_t>(s0) * D;
-      for (int i = tid; i < ns * D; i += T) {
-        const int s = i / D;
-        sZ[s * D4 + (i - s * D)] = z[i];
-      }
+      for (int i = tid; i < ns * D; i += blockDim.x) sZ[(i / D) * D4 + i % D] = z[i];
     } else {
       const int nq = D4 / 4;
       const uint32_t stream = a.stream_base + static_cast<uint32_t>(prob);
-      for (int i = tid; i < ns * nq; i += T) {
-        const int s = i / nq, q = i - s * nq;
+      for (int i = tid; i < ns * nq; i += blockDim.x) {
+        const int s = i / nq, qq = i - s * nq;
         float z[4];
-        philox_normals4(a.seed, static_cast<uint32_t>(s0 + s), static_cast<uint32_t>(q),
+        philox_normals4(a.seed, static_cast<uint32_t>(s0 + s), static_cast<uint32_t>(qq),
                         static_cast<uint32_t>(a.iter), stream, z);
-        *reinterpret_cast<float4*>(sZ + s * D4 + 4 * q) = make_float4(z[0], z[1], z[2], z[3]);
+        *reinterpret_cast<float4*>(sZ + s * D4 + 4 * qq) = make_float4(z[0], z[1], z[2], z[3]);
       }
     }
     __syncthreads();
-    for (int i = tid; i < ns * D; i += T) {
+    for (int i = tid; i < ns * D; i += blockDim.x) {
       const int s = i / D, d = i - s * D;
-      const float* z = sZ + s * D4;
+      const float* zz = sZ + s * D4;
       const float* Lr = sL + d * D;
       float x = sMu[d];
-      for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], z[e], x);
-      sX[i] = x;
+      for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
+      xs[s * D4 + d] = x;
     }
     __syncthreads();
     if (a.xi_src) {
       float* dst = a.xi_src + prob * a.xi_src_stride + static_cast<int64_t>(s0) * D;
-      for (int i = tid; i < ns * D; i += T) dst[i] = sX[i];
+      for (int i = tid; i < ns * D; i += blockDim.x) dst[i] = xs[(i / D) * D4 + i % D];
     }
   }
   __syncthreads();
-  for (int i = tid; i < ns * D; i += T) { sXb[i] = sX[i]; sLam[i] = 0.0f; }
-  __syncthreads();
 
+  // ---- per-lane MFMA operands and sample state -------------------------------
+  float Af[3][4], Ab[3][4], Am[4], Ap[4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int tf = t0 + col, cf = 4 * q + r;
+      Af[d][r] = (tf < K && cf < nv) ? a.W[(tf * 3 + d) * nv + cf] : 0.0f;
+      const int tb = t0 + 4 * q + r;
+      Ab[d][r] = (tb < K && col < nv) ? a.W[(tb * 3 + d) * nv + col] : 0.0f;
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int cr = 4 * q + r;
+    const bool ok = (col < nv) && (cr < nv);
+    Am[r] = ok ? a.M11[col * nv + cr] : 0.0f;
+    Ap[r] = ok ? a.Pi[col * nv + cr] : 0.0f;
+  }
+  const bool colok = (cx < DIMS) && (cs < ns);
+  const float* bc = a.bc + prob * a.bc_stride;
+  f4 xi, c0v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int c = 4 * q + r;
+    const bool ok = colok && (c < nv);
+    xi[r] = ok ? xs[cs * round4(D) + cx * nv + c] : 0.0f;
+    float s = 0.0f;
+    if (ok)
+      for (int i = 0; i < 6; ++i) s = fmaf(a.M12[c * 6 + i], bc[cx * 6 + i], s);
+    c0v[r] = s;
+  }
+  f4 xb = xi;
+  f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
   const float rho = a.rho;
-  const float vmax = a.vmax, amax = a.amax;
-  const int nitems = ns * K;
-  const int SD = S * D;
+  float* xt = sm + l.xt + w * 768;
 
-  // ---- projection iterations -------------------------------------------------
+  // Forward rows of this wave's time block, transposed to the item layout.
+  auto forward = [&](float p[DIMS], float v[DIMS], float ac[DIMS]) {
+    // two independent depth-2 chains per row type, summed
+    const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    const f4 Y0 = mfma(Af[0][1], xb[1], mfma(Af[0][0], xb[0], z)) +
+                  mfma(Af[0][3], xb[3], mfma(Af[0][2], xb[2], z));
+    const f4 Y1 = mfma(Af[1][1], xb[1], mfma(Af[1][0], xb[0], z)) +
+                  mfma(Af[1][3], xb[3], mfma(Af[1][2], xb[2], z));
+    const f4 Y2 = mfma(Af[2][1], xb[1], mfma(Af[2][0], xb[0], z)) +
+                  mfma(Af[2][3], xb[3], mfma(Af[2][2], xb[2], z));
+    *reinterpret_cast<f4*>(xt + lane * 4) = Y0;
+    *reinterpret_cast<f4*>(xt + 256 + lane * 4) = Y1;
+    *reinterpret_cast<f4*>(xt + 512 + lane * 4) = Y2;
+    wave_lds_sync();
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) {
+      const int src = (lane - ia + x) * 4 + ia;
+      p[x] = xt[src];
+      v[x] = xt[256 + src];
+      ac[x] = xt[512 + src];
+    }
+    wave_lds_sync();
+  };
+
+  // ---- projection iterations ---------------------------------------------------
   for (int k = 0; k < a.n_iter; ++k) {
-    // phase 1: per (sample, t) push-outs
-    for (int it = tid; it < nitems; it += T) {
-      const int s = it / K, t = it - s * K;
-      float p[DIMS], v[DIMS], ac[DIMS];
-      eval_row<DIMS, NVT>(sW + t * 3 * nv, sXb + s * D, nv, p, v, ac);
-      const float tt = a.dt * static_cast<float>(t);
-      float so[DIMS];
+    PRIEST_PROJ_MARK(0);
+    float p[DIMS], v[DIMS], ac[DIMS];
+    forward(p, v, ac);
+    PRIEST_PROJ_MARK(1);
+    float S[DIMS], dv[DIMS], da[DIMS], r2;
+    item_push<DIMS, false>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv, da,
+                           r2, lane);
+    PRIEST_PROJ_MARK(2);
+    // back to the column layout
+    f4 T0 = {0.0f, 0.0f, 0.0f, 0.0f}, T1 = T0, T2 = T0;
 #pragma unroll
-      for (int ax = 0; ax < DIMS; ++ax) so[ax] = 0.0f;
-#pragma unroll 2
-      for (int j = 0; j < M; ++j) {
-        float d[DIMS];
-        if (obstacle_push<DIMS>(sObs + 8 * j, sAB + 2 * j, tt, p, d)) {
+    for (int x = 0; x < DIMS; ++x) { T0[x] = S[x]; T1[x] = dv[x]; T2[x] = da[x]; }
+    *reinterpret_cast<f4*>(xt + lane * 4) = T0;
+    *reinterpret_cast<f4*>(xt + 256 + lane * 4) = T1;
+    *reinterpret_cast<f4*>(xt + 512 + lane * 4) = T2;
+    wave_lds_sync();
+    float B[3][4];
 #pragma unroll
-          for (int ax = 0; ax < DIMS; ++ax) so[ax] += d[ax];
-        }
-      }
-      float dv[DIMS], da[DIMS];
-      bound_push<DIMS>(v, vmax, dv);
-      bound_push<DIMS>(ac, amax, da);
-      float* out = sDelta + it * 3 * DIMS;
+    for (int r = 0; r < 4; ++r) {
+      const int src = (lane - cx + r) * 4 + cx;
+      B[0][r] = xt[src];
+      B[1][r] = xt[256 + src];
+      B[2][r] = xt[512 + src];
+    }
+    const f4 zb = {0.0f, 0.0f, 0.0f, 0.0f};
+    f4 G0 = mfma(Ab[0][1], B[0][1], mfma(Ab[0][0], B[0][0], zb));
+    f4 G1 = mfma(Ab[0][3], B[0][3], mfma(Ab[0][2], B[0][2], zb));
+    f4 G2 = mfma(Ab[1][1], B[1][1], mfma(Ab[1][0], B[1][0], zb));
+    G0 = mfma(Ab[1][3], B[1][3], mfma(Ab[1][2], B[1][2], G0));
+    G1 = mfma(Ab[2][1], B[2][1], mfma(Ab[2][0], B[2][0], G1));
+    G2 = mfma(Ab[2][3], B[2][3], mfma(Ab[2][2], B[2][2], G2));
+    // issue all six LDS reads before the twelve MFMAs that consume them
+    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
+    PRIEST_PROJ_MARK(3);
+    float* gp = sm + l.gp + (k & 1) * TW * 256;
+    *reinterpret_cast<f4*>(gp + w * 256 + lane * 4) = G0 + G1 + G2;
+    __syncthreads();
+    // all partials loaded before any is used; slots past TW read slot TW-1
+    // and are replaced by zero; fixed summation order in every wave
+    constexpr int MW = MAXT / 64;
+    f4 part[MW];
 #pragma unroll
-      for (int ax = 0; ax < DIMS; ++ax) {
-        out[ax] = so[ax];
-        out[DIMS + ax] = dv[ax];
-        out[2 * DIMS + ax] = da[ax];
-      }
+    for (int ww = 0; ww < MW; ++ww)
+      part[ww] = *reinterpret_cast<const f4*>(gp + min(ww, TW - 1) * 256 + lane * 4);
+    const f4 zg = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ww = 1; ww < MW; ++ww) part[ww] = (ww < TW) ? part[ww] : zg;
+#pragma unroll
+    for (int step = 1; step < MW; step *= 2)
+#pragma unroll
+      for (int ww = 0; ww + step < MW; ww += 2 * step) part[ww] += part[ww + step];
+    const f4 g = part[0];
+    PRIEST_PROJ_MARK(4);
+    lam += rho * g;
+    const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (k == 0) {
+      const f4 u = lam + rho * g;
+      const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
+      const f4 h1 = mfma(Ap[3], xi[3], mfma(Ap[2], xi[2], z));
+      const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
+      const f4 h3 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
+      xb = (h0 + h1) + (h2 + h3);
+    } else {
+      const f4 u = (xi - xb) + lam + rho * g;
+      const f4 h0 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
+      const f4 h1 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
+      xb = xb + (h0 + h1);
     }
-    __syncthreads();
-    // phase 2: g = W^T delta, time range split into G groups
-    for (int idx = tid; idx < G * SD; idx += T) {
-      const int gi = idx / SD, o = idx - gi * SD;
-      const int s = o / D, r = o - s * D;
-      const int ax = r / nv, c = r - ax * nv;
-      if (s < ns) {
-        float acc = 0.0f;
-        for (int t = gi; t < K; t += G) {
-          const float* w = sW + t * 3 * nv;
-          const float* dl = sDelta + (s * K + t) * 3 * DIMS;
-          acc = fmaf(w[c], dl[ax], acc);
-          acc = fmaf(w[nv + c], dl[DIMS + ax], acc);
-          acc = fmaf(w[2 * nv + c], dl[2 * DIMS + ax], acc);
-        }
-        sG[gi * SD + o] = acc;
-      }
-    }
-    __syncthreads();
-    // phase 3a: multiplier update and QP right-hand side increment
-    for (int o = tid; o < ns * D; o += T) {
-      float g = 0.0f;
-      for (int gi = 0; gi < G; ++gi) g += sG[gi * SD + o];
-      const float lam = fmaf(rho, g, sLam[o]);
-      sLam[o] = lam;
-      const float u = (k == 0) ? fmaf(rho, g, lam) : fmaf(rho, g, (sX[o] - sXb[o]) + lam);
-      sU[o] = u;
-    }
-    __syncthreads();
-    // phase 3b: xi_bar through the fixed KKT block
-    for (int o = tid; o < ns * D; o += T) {
-      const int s = o / D, r = o - s * D;
-      const int ax = r / nv, c = r - ax * nv;
-      const float* u = sU + s * D + ax * nv;
-      const float* m = sM11 + c * nv;
-      float acc = 0.0f;
-      for (int e = 0; e < nv; ++e) acc = fmaf(m[e], u[e], acc);
-      if (k == 0) {
-        const float* x = sX + s * D + ax * nv;
-        const float* pi = sPi + c * nv;
-        float base = sC0[r];
-        for (int e = 0; e < nv; ++e) base = fmaf(pi[e], x[e], base);
-        sXb[o] = base + acc;
-      } else {
-        sXb[o] += acc;
-      }
-    }
-    __syncthreads();
+    PRIEST_PROJ_MARK(5);
   }
 
-  // ---- residual and smoothness cost of the returned iterate ------------------
-  for (int it = tid; it < nitems; it += T) {
-    const int s = it / K, t = it - s * K;
+  // ---- residual and smoothness cost of the returned iterate -----------------------
+  {
     float p[DIMS], v[DIMS], ac[DIMS];
-    eval_row<DIMS, NVT>(sW + t * 3 * nv, sXb + s * D, nv, p, v, ac);
-    const float tt = a.dt * static_cast<float>(t);
-    float r2 = 0.0f;
-    for (int j = 0; j < M; ++j) {
-      float d[DIMS];
-      if (obstacle_push<DIMS>(sObs + 8 * j, sAB + 2 * j, tt, p, d)) {
-#pragma unroll
-        for (int ax = 0; ax < DIMS; ++ax) r2 = fmaf(d[ax], d[ax], r2);
-      }
-    }
-    float dv[DIMS], da[DIMS];
-    r2 += bound_push<DIMS>(v, vmax, dv);
-    r2 += bound_push<DIMS>(ac, amax, da);
+    forward(p, v, ac);
+    float S[DIMS], dv[DIMS], da[DIMS], r2;
+    item_push<DIMS, true>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv, da,
+                          r2, lane);
     float cc = 0.0f;
 #pragma unroll
-    for (int ax = 0; ax < DIMS; ++ax) cc = fmaf(ac[ax], ac[ax], cc);
-    sDelta[2 * it] = r2;
-    sDelta[2 * it + 1] = cc;
+    for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[x], ac[x], cc);
+    float* fin = sm + l.fin + w * 128;
+    fin[2 * lane] = item_ok ? r2 : 0.0f;
+    fin[2 * lane + 1] = item_ok ? cc : 0.0f;
   }
   __syncthreads();
-  const int64_t nbase = prob * a.n_stride + s0;
-  for (int s = tid; s < ns; s += T) {
+  if (tid < ns) {
+    const int s = tid;
     float r2 = 0.0f, cc = 0.0f;
     for (int t = 0; t < K; ++t) {
-      r2 += sDelta[2 * (s * K + t)];
-      cc += sDelta[2 * (s * K + t) + 1];
+      const int ww = t >> 4, qq = (t >> 2) & 3, aa = t & 3;
+      const float* f = sm + l.fin + ww * 128 + 2 * (qq * 16 + s * 4 + aa);
+      r2 += f[0];
+      cc += f[1];
     }
     const float r = sqrtf(r2);
-    if (a.resid) a.resid[nbase + s] = r;
-    if (a.c1) a.c1[nbase + s] = cc;
+    const int64_t nb = prob * a.n_stride + s0 + s;
     const int64_t dense = static_cast<int64_t>(prob) * a.N + s0 + s;
+    if (a.resid) a.resid[nb] = r;
+    if (a.c1) a.c1[nb] = cc;
     if (a.resid2) a.resid2[dense] = r;
     if (a.c12) a.c12[dense] = cc;
   }
-  float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0) * D;
-  for (int i = tid; i < ns * D; i += T) dst[i] = sXb[i];
-  if (a.xi_out2) {
-    float* dst2 = a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0) * D;
-    for (int i = tid; i < ns * D; i += T) dst2[i] = sXb[i];
+  if (w == 0 && colok) {
+    float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0 + cs) * D + cx * nv;
+    float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0 + cs) * D + cx * nv
+                            : nullptr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 4 * q + r;
+      if (c < nv) {
+        dst[c] = xb[r];
+        if (dst2) dst2[c] = xb[r];
+      }
+    }
   }
 }
 
-// Per-row push-outs e(xi) - F xi, [N][M + 2][K][dims] (parity hook).
+// Per-row push-outs e(xi) - F xi, [N][M + 2][K][dims] (parity hook): one
+// thread per (sample, t), the same record table and per-pair push-out
+// arithmetic as the projection kernel, one obstacle at a time.
 template <int DIMS>
 __global__ void offsets_kernel(ProjArgs a, const float* xi, float* out) {
+  __shared__ float4 rec[3 * PRIEST_MAX_OBS];
   const int nv = a.nv, K = a.K, M = a.M;
   const int D = DIMS * nv;
+  build_records<DIMS>(a.obs, M, threadIdx.x, blockDim.x, rec);
+  __syncthreads();
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= a.N * K) return;
   const int s = it / K, t = it - s * K;
   float p[DIMS], v[DIMS], ac[DIMS];
-  eval_row<DIMS, 0>(a.W + t * 3 * nv, xi + static_cast<int64_t>(s) * D, nv, p, v, ac);
+  for (int x = 0; x < DIMS; ++x) {
+    float sp = 0.0f, sv = 0.0f, sa = 0.0f;
+    for (int c = 0; c < nv; ++c) {
+      const float xc = xi[static_cast<int64_t>(s) * D + x * nv + c];
+      sp = fmaf(a.W[(t * 3 + 0) * nv + c], xc, sp);
+      sv = fmaf(a.W[(t * 3 + 1) * nv + c], xc, sv);
+      sa = fmaf(a.W[(t * 3 + 2) * nv + c], xc, sa);
+    }
+    p[x] = sp; v[x] = sv; ac[x] = sa;
+  }
   const float tt = a.dt * static_cast<float>(t);
   float* o = out + static_cast<int64_t>(s) * (M + 2) * K * DIMS;
   for (int j = 0; j < M; ++j) {
-    const float* src = a.obs + 8 * j;
-    const float ra = src[6], rb = (DIMS == 3) ? src[7] : src[6];
-    const float ob[8] = {src[0], src[1], DIMS == 3 ? src[2] : 0.0f, src[3], src[4],
-                         DIMS == 3 ? src[5] : 0.0f, 1.0f / (ra * ra), 1.0f / (rb * rb)};
-    const float ab[2] = {ra, rb};
-    float d[DIMS];
-    if (!obstacle_push<DIMS>(ob, ab, tt, p, d))
-      for (int ax = 0; ax < DIMS; ++ax) d[ax] = 0.0f;
-    for (int ax = 0; ax < DIMS; ++ax) o[(j * K + t) * DIMS + ax] = d[ax];
+    const Rec r = rec_from_lds(rec, j);
+    float S[DIMS], r2 = 0.0f;
+    for (int x = 0; x < DIMS; ++x) S[x] = 0.0f;
+    if (pair_push<DIMS, false>(r, tt, p, S, r2)) zero_push<DIMS, false>(r, S, r2);
+    for (int x = 0; x < DIMS; ++x) o[(j * K + t) * DIMS + x] = S[x];
   }
   float dv[DIMS], da[DIMS];
   bound_push<DIMS>(v, a.vmax, dv);
   bound_push<DIMS>(ac, a.amax, da);
-  for (int ax = 0; ax < DIMS; ++ax) {
-    o[(M * K + t) * DIMS + ax] = dv[ax];
-    o[((M + 1) * K + t) * DIMS + ax] = da[ax];
+  for (int x = 0; x < DIMS; ++x) {
+    o[(M * K + t) * DIMS + x] = dv[x];
+    o[((M + 1) * K + t) * DIMS + x] = da[x];
   }
 }
 
@@ -395,57 +612,41 @@ __global__ void normals_kernel(uint64_t seed, uint32_t stream, int iter, int N, 
   const int nq = (D + 3) / 4;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * nq) return;
-  const int s = i / nq, q = i - s * nq;
+  const int s = i / nq, qq = i - s * nq;
   float w[4];
-  philox_normals4(seed, static_cast<uint32_t>(s), static_cast<uint32_t>(q),
+  philox_normals4(seed, static_cast<uint32_t>(s), static_cast<uint32_t>(qq),
                   static_cast<uint32_t>(iter), stream, w);
   for (int k = 0; k < 4; ++k)
-    if (4 * q + k < D) z[static_cast<int64_t>(s) * D + 4 * q + k] = w[k];
+    if (4 * qq + k < D) z[static_cast<int64_t>(s) * D + 4 * qq + k] = w[k];
 }
 
 }  // namespace
 
+int project_waves(int K) { return (K + 15) / 16; }
+
 size_t project_lds_bytes(const ProjArgs& a) {
-  return sizeof(float) * static_cast<size_t>(layout(a.dims, a.nv, a.K, a.M, a.S, a.G, a.mode).total);
+  return sizeof(float) *
+         static_cast<size_t>(layout(a.dims, a.nv, a.M, project_waves(a.K), a.mode).total);
 }
 
 int project_pick_tile(int dims, int nv, int K, int M, int N, int n_problems, int* S, int* G) {
-  // Smallest tile whose (sample, t) items fill the block, so that single
-  // problems still spread over all compute units; more samples per block only
-  // when the batch alone fills the chip several times over.
-  const int T = kProjectThreads;
-  int s = (T + K - 1) / K;
-  if (s < 1) s = 1;
-  const long long blocks = static_cast<long long>(n_problems) * ((N + s - 1) / s);
-  if (blocks > 8LL * 256) {
-    while (s * 2 * K <= 4 * T && s * 2 <= 16) s *= 2;
-  }
-  if (s > N) s = N;
-  const int D = dims * nv;
-  int g = T / (s * D);
-  if (g < 1) g = 1;
-  *S = s;
-  *G = g;
-  (void)M;
+  (void)dims; (void)nv; (void)K; (void)M; (void)N; (void)n_problems;
+  *S = 4;  // samples per block: 4 samples x 4 axis slots = 16 MFMA columns
+  *G = 1;
   return 0;
 }
 
 hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
   const size_t lds = project_lds_bytes(a);
   const dim3 grid(static_cast<unsigned>(n_problems * a.blocks_per_problem));
-  const dim3 block(kProjectThreads);
-  if (a.dims == 2) {
-    if (a.nv == 11) {
-      hipLaunchKernelGGL((project_kernel<2, 11>), grid, block, lds, s, a);
-    } else {
-      hipLaunchKernelGGL((project_kernel<2, 0>), grid, block, lds, s, a);
-    }
+  const dim3 block(64 * project_waves(a.K));
+  // up to 8 waves (K <= 128): a 512-thread bound leaves room for 256 VGPRs
+  if (block.x <= 512) {
+    if (a.dims == 2) hipLaunchKernelGGL((project_kernel<2, 512>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((project_kernel<3, 512>), grid, block, lds, s, a);
   } else {
-    if (a.nv == 11) {
-      hipLaunchKernelGGL((project_kernel<3, 11>), grid, block, lds, s, a);
-    } else {
-      hipLaunchKernelGGL((project_kernel<3, 0>), grid, block, lds, s, a);
-    }
+    if (a.dims == 2) hipLaunchKernelGGL((project_kernel<2, 1024>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((project_kernel<3, 1024>), grid, block, lds, s, a);
   }
   return hipGetLastError();
 }

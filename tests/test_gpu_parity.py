@@ -392,3 +392,24 @@ def test_plan_nonfinite_mean_isolated(priest):
     for q in (0, 2):
         assert torch.equal(out["best_xi"][q], ref["best_xi"][q])
     gp.close()
+
+
+def test_plan_one_iteration_3d(priest):
+    """3D (D = 33): covariance entries beyond one per thread and a 33 x 33
+    Cholesky, against the oracle's refit of the GPU's elites."""
+    say("plan 3D one CEM iteration, supplied noise")
+    wl = W.with_changes(W.C3, n_obs=20, n_steps=50, n_samples=160, n_proj=W.default_n_proj(160),
+                        n_elite=24, n_proj_iters=30)
+    gp, op = make(priest, wl)
+    bc = W.boundary_values(wl)
+    obs = W.obstacles(wl, 3003)
+    cem = _cem(wl)
+    mu0, cov0 = W.initial_mean(wl), W.initial_cov(wl)
+    noise = W.standard_normals(31, (1, wl.n_samples, wl.D))
+    mu, cov = t32(mu0), t32(cov0)
+    out = gp.plan(t32(bc), t32(obs), cem, mu, cov, noise=t32(noise))
+    torch.cuda.synchronize()
+    _check_cem_step(op, bc, obs, wl, cem, mu0, cov0, noise[0], out, np64(mu), np64(cov), "3d")
+    L = np.linalg.cholesky(np64(cov) + cem.cov_jitter * np.trace(np64(cov)) / wl.D * np.eye(wl.D))
+    assert np.all(np.isfinite(L))
+    gp.close()
