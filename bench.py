@@ -46,9 +46,11 @@ def projection_flops(dims: int, nv: int, K: int, M: int) -> float:
             + dims * (5 * nv + 2 * nv * nv))
 
 
-def cpu_baseline(wl, n_sample: int):
+def cpu_baseline(wl, n_sample: int, gpu_results=None):
     """The FP64 oracle on `n_sample` samples of the same workload (one
-    projection of n_proj_iters iterations), in projected samples x iters/s."""
+    projection of n_proj_iters iterations), in projected samples x iters/s.
+    `gpu_results` maps a label to GPU-projected samples of the same inputs
+    (first rows); their per-result error against this oracle run is returned."""
     import oracle as O
     from paper_2309_08235_amd import workloads as W
     try:
@@ -61,12 +63,85 @@ def cpu_baseline(wl, n_sample: int):
                      wl.a_max, wl.bc_mask)
     xi = W.samples(wl, 5, n=n_sample)
     t0 = time.perf_counter()
-    O.project(prob, bc, obs, xi, wl.n_proj_iters)
+    pr = O.project(prob, bc, obs, xi, wl.n_proj_iters)
     dt = time.perf_counter() - t0
+    errors = {}
+    for label, (xb, r) in (gpu_results or {}).items():
+        xb = np.asarray(xb, np.float64)[:n_sample]
+        r = np.asarray(r, np.float64)[:n_sample]
+        e = np.abs(xb - pr.xi_bar).max(1) / np.maximum(1.0, np.abs(pr.xi_bar).max(1))
+        er = np.abs(r - pr.resid)
+        errors[label] = {"coeff_rel_median": float(np.median(e)),
+                         "coeff_rel_p99": float(np.quantile(e, 0.99)),
+                         "coeff_rel_max": float(e.max()),
+                         "resid_abs_median": float(np.median(er)),
+                         "resid_abs_max": float(er.max())}
     return {"value": n_sample * wl.n_proj_iters / dt, "unit": "projected samples*iters/s",
             "cores": int(threads), "kind": "oracle",
             "sample": f"{n_sample} samples x {wl.n_proj_iters} projection iterations of the "
-                      f"{wl.name} scene (one CEM iteration's projection), FP64 NumPy, {dt:.1f} s"}
+                      f"{wl.name} scene (one CEM iteration's projection), FP64 NumPy, {dt:.1f} s",
+            "gpu_error_vs_oracle": errors}
+
+
+def batched_3d(P, W, steps: int, plain_problems: int):
+    """3D batched workload: 64 problems x N=2000 samples, M=128 spheres, K=100,
+    100 projection x 20 CEM iterations.  Batched = every CEM step of all 64
+    problems in one launch, the whole CEM loop captured in a hipGraph and
+    replayed; plain = one problem per launch, no graph (timed on
+    `plain_problems` problems and scaled)."""
+    import torch
+    wl = W.C3
+    dev = "cuda:0"
+    prob = P.Problem.from_workload(wl)
+    nP = wl.n_problems
+    scenes = [W.scene(wl, q) for q in range(nP)]
+    bc = torch.tensor(np.stack([s[0] for s in scenes]), dtype=torch.float32, device=dev)
+    obs = torch.tensor(np.stack([s[1] for s in scenes]), dtype=torch.float32, device=dev)
+    mu0 = torch.tensor(np.stack([W.initial_mean(wl)] * nP), dtype=torch.float32, device=dev)
+    cov0 = torch.tensor(np.stack([W.initial_cov(wl)] * nP), dtype=torch.float32, device=dev)
+    cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
+                n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
+                cov_jitter=wl.cov_jitter)
+    mu, cov = mu0.clone(), cov0.clone()
+    out = prob.plan_outputs(cem, nP, full=False)
+    ws = prob.workspace(cem, nP)
+    s = torch.cuda.Stream()
+
+    def batch_step():
+        mu.copy_(mu0)
+        cov.copy_(cov0)
+        prob.plan_batch(nP, bc, obs, cem, mu, cov, seed=77, stream_base=0, out=out, workspace=ws,
+                        use_graph=True, stream=s)
+
+    with torch.cuda.stream(s):
+        batch_step()                      # capture + first replay
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch_step()
+        s.synchronize()
+        t_batch = (time.perf_counter() - t0) / steps
+    assert int(out["status"].abs().sum().item()) == 0
+    # plain: one problem per launch, no graph
+    out1 = prob.plan_outputs(cem, 1, full=False)
+    ws1 = prob.workspace(cem, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(plain_problems):
+        m, c = mu0[q].clone(), cov0[q].clone()
+        prob.plan(bc[q], obs[q], cem, m, c, seed=77, stream_id=q, out=out1, workspace=ws1)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / plain_problems * nP
+    work = nP * wl.n_samples * wl.n_proj_iters * wl.n_cem
+    return {"workload": wl.name, "problems": nP,
+            "batched_graph": {"s_per_batch": round(t_batch, 4),
+                              "samples_iters_per_s": round(work / t_batch, 1),
+                              "plans_per_s": round(nP / t_batch, 2)},
+            "plain_per_problem": {"s_per_64_plans": round(t_plain, 4),
+                                  "samples_iters_per_s": round(work / t_plain, 1),
+                                  "plans_per_s": round(nP / t_plain, 2),
+                                  "timed_problems": plain_problems},
+            "speedup": round(t_plain / t_batch, 3)}
 
 
 def main():
@@ -77,6 +152,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched 3D comparison")
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--plain-problems", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every problem and "
@@ -152,9 +231,36 @@ def main():
                 "kernel": "project_kernel<2,11>", "kernel_ms": round(k_ms, 4),
                 "flops_per_launch": flops}
 
+    # mixed precision: same shape, BF16 operands for the right-hand side and
+    # a BF16 hi/lo KKT product, last 10 iterations in FP32
+    prob_bf = P.Problem.from_workload(wl, precision=P.BF16_MIXED, n_refine_fp32=10)
+    xo_bf = torch.empty_like(xi)
+    r_bf = torch.empty(wl.n_samples, device=dev)
+    for _ in range(3):
+        P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
+    torch.cuda.synchronize()
+    ka.record(stream)
+    for _ in range(args.kernel_reps):
+        P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
+    kb.record(stream)
+    torch.cuda.synchronize()
+    k_ms_bf = ka.elapsed_time(kb) / args.kernel_reps
+    P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+    torch.cuda.synchronize()
+    gpu_results = {"fp32": (xo.cpu().numpy(), r.cpu().numpy()),
+                   "bf16_mixed": (xo_bf.cpu().numpy(), r_bf.cpu().numpy())}
+    mixed = {"kernel_ms_fp32": round(k_ms, 4), "kernel_ms_bf16_mixed": round(k_ms_bf, 4),
+             "n_refine_fp32": 10,
+             "note": "BF16 operands for W^T(e - F xi) and a BF16 hi/lo split of M11 u, FP32 "
+                     "accumulation; errors vs the FP64 oracle in cpu_baseline.gpu_error_vs_oracle"}
+
+    extra = None
+    if not args.no_extra:
+        extra = batched_3d(P, W, args.batch_steps, args.plain_problems)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_sample)
+        cpu = cpu_baseline(wl, args.cpu_sample, gpu_results)
 
     line = {
         "metric": "projected samples*iters/s",
@@ -178,6 +284,8 @@ def main():
                        "p99": round(float(np.percentile(lat, 99)), 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed_precision": mixed,
+        "batched_3d": extra,
     }
     print(json.dumps(line), flush=True)
 

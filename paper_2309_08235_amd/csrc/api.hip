@@ -137,11 +137,20 @@ ProjArgs base_args(const priest_problem* p) {
   a.dt = static_cast<float>(d.horizon / (d.n_steps - 1));
   a.vmax = static_cast<float>(d.v_max);
   a.amax = static_cast<float>(d.a_max);
+  a.bf16_iters = 0;
   a.W = p->dW;
   a.M11 = p->dM11;
   a.Pi = p->dPi;
   a.M12 = p->dM12;
   return a;
+}
+
+// Mixed precision: BF16 MFMA operands for all but the last n_refine_fp32
+// projection iterations.
+int bf16_iters(const priest_problem* p, int n_iter) {
+  if (p->desc.precision != PRIEST_BF16_MIXED) return 0;
+  const int n = n_iter - p->desc.n_refine_fp32;
+  return n > 0 ? n : 0;
 }
 
 int32_t check_lds(const priest_problem* p, const ProjArgs& a) {
@@ -221,6 +230,7 @@ int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float*
   project_pick_tile(a.dims, a.nv, a.K, a.M, N, P, &a.S, &a.G);
   a.blocks_per_problem = (N + a.S - 1) / a.S;
   a.n_iter = c->n_proj_iters;
+  a.bf16_iters = bf16_iters(p, a.n_iter);
   a.mode = noise ? kFromNoise : kFromPhilox;
   a.seed = seed;
   a.stream_base = stream_base;
@@ -406,6 +416,7 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   project_pick_tile(a.dims, a.nv, a.K, a.M, N, 1, &a.S, &a.G);
   a.blocks_per_problem = (N + a.S - 1) / a.S;
   a.n_iter = n_iter;
+  a.bf16_iters = bf16_iters(p, n_iter);
   a.mode = kFromInput;
   a.bc = bc;
   a.obs = obs;

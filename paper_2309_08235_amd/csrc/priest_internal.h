@@ -31,6 +31,7 @@ struct ProjArgs {
   int32_t blocks_per_problem;
   int32_t G;                   // time-groups of the right-hand-side reduction
   int32_t mode;                // SampleMode
+  int32_t bf16_iters;          // leading iterations with BF16 MFMA operands (mixed precision)
   int32_t iter;                // CEM iteration (Philox counter word 2)
   uint32_t stream_base;        // Philox counter word 3 = stream_base + problem
   uint64_t seed;               // Philox key

@@ -54,6 +54,27 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 operands (mixed precision): round-to-nearest-even FP32 -> BF16 and the
+// K = 16 BF16 MFMA with FP32 accumulation.  Lane l's four values are the same
+// (row, k) slots the FP32 K = 4 MFMA uses across its four steps, so the
+// register layouts carry over unchanged.
+using s4 = __attribute__((ext_vector_type(4))) short;
+
+__device__ __forceinline__ short to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<short>(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(short h) {
+  return __uint_as_float(static_cast<uint32_t>(static_cast<unsigned short>(h)) << 16);
+}
+__device__ __forceinline__ s4 pack_bf16(float a0, float a1, float a2, float a3) {
+  return s4{to_bf16(a0), to_bf16(a1), to_bf16(a2), to_bf16(a3)};
+}
+__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // Orders this wave's LDS writes before its subsequent LDS reads by other lanes.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -316,7 +337,7 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, float tt, fl
   }
 }
 
-template <int DIMS, int MAXT>
+template <int DIMS, int MAXT, bool BF16>
 __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
@@ -419,6 +440,15 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
   f4 xb = xi;
   f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
   const float rho = a.rho;
+  // mixed precision: W^T rows as BF16, M11 as a BF16 hi/lo pair
+  s4 Abf[3], Mhi, Mlo;
+  if constexpr (BF16) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Abf[d] = pack_bf16(Ab[d][0], Ab[d][1], Ab[d][2], Ab[d][3]);
+    Mhi = pack_bf16(Am[0], Am[1], Am[2], Am[3]);
+    Mlo = pack_bf16(Am[0] - from_bf16(Mhi[0]), Am[1] - from_bf16(Mhi[1]),
+                    Am[2] - from_bf16(Mhi[2]), Am[3] - from_bf16(Mhi[3]));
+  }
   float* xt = sm + l.xt + w * 768;
 
   // Forward rows of this wave's time block, transposed to the item layout.
@@ -472,6 +502,16 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
       B[2][r] = xt[512 + src];
     }
     const f4 zb = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bool lowp = BF16 && (k < a.bf16_iters);
+    if (lowp) {
+      // right-hand side with BF16 operands, FP32 accumulation: one K = 16
+      // MFMA per row type covers the whole 16-step time block
+      const f4 g = mfma_bf16(Abf[0], pack_bf16(B[0][0], B[0][1], B[0][2], B[0][3]), zb) +
+                   mfma_bf16(Abf[1], pack_bf16(B[1][0], B[1][1], B[1][2], B[1][3]), zb) +
+                   mfma_bf16(Abf[2], pack_bf16(B[2][0], B[2][1], B[2][2], B[2][3]), zb);
+      float* gpl = sm + l.gp + (k & 1) * TW * 256;
+      *reinterpret_cast<f4*>(gpl + w * 256 + lane * 4) = g;
+    }
     f4 G0 = mfma(Ab[0][1], B[0][1], mfma(Ab[0][0], B[0][0], zb));
     f4 G1 = mfma(Ab[0][3], B[0][3], mfma(Ab[0][2], B[0][2], zb));
     f4 G2 = mfma(Ab[1][1], B[1][1], mfma(Ab[1][0], B[1][0], zb));
@@ -483,7 +523,7 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
     __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
     PRIEST_PROJ_MARK(3);
     float* gp = sm + l.gp + (k & 1) * TW * 256;
-    *reinterpret_cast<f4*>(gp + w * 256 + lane * 4) = G0 + G1 + G2;
+    if (!lowp) *reinterpret_cast<f4*>(gp + w * 256 + lane * 4) = G0 + G1 + G2;
     __syncthreads();
     // all partials loaded before any is used; slots past TW read slot TW-1
     // and are replaced by zero; fixed summation order in every wave
@@ -510,6 +550,13 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
       const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
       const f4 h3 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
       xb = (h0 + h1) + (h2 + h3);
+    } else if (lowp) {
+      // KKT product with BF16 hi/lo splits of M11 and u (three K = 16 MFMAs)
+      const f4 u = (xi - xb) + lam + rho * g;
+      const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
+      const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
+                              u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
+      xb = xb + (mfma_bf16(Mhi, uh, z) + (mfma_bf16(Mhi, ul, z) + mfma_bf16(Mlo, uh, z)));
     } else {
       const f4 u = (xi - xb) + lam + rho * g;
       const f4 h0 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
@@ -641,12 +688,23 @@ hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(n_problems * a.blocks_per_problem));
   const dim3 block(64 * project_waves(a.K));
   // up to 8 waves (K <= 128): a 512-thread bound leaves room for 256 VGPRs
+  const bool bf = a.bf16_iters > 0;
   if (block.x <= 512) {
-    if (a.dims == 2) hipLaunchKernelGGL((project_kernel<2, 512>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((project_kernel<3, 512>), grid, block, lds, s, a);
+    if (a.dims == 2) {
+      if (bf) hipLaunchKernelGGL((project_kernel<2, 512, true>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((project_kernel<2, 512, false>), grid, block, lds, s, a);
+    } else {
+      if (bf) hipLaunchKernelGGL((project_kernel<3, 512, true>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((project_kernel<3, 512, false>), grid, block, lds, s, a);
+    }
   } else {
-    if (a.dims == 2) hipLaunchKernelGGL((project_kernel<2, 1024>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((project_kernel<3, 1024>), grid, block, lds, s, a);
+    if (a.dims == 2) {
+      if (bf) hipLaunchKernelGGL((project_kernel<2, 1024, true>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((project_kernel<2, 1024, false>), grid, block, lds, s, a);
+    } else {
+      if (bf) hipLaunchKernelGGL((project_kernel<3, 1024, true>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((project_kernel<3, 1024, false>), grid, block, lds, s, a);
+    }
   }
   return hipGetLastError();
 }

@@ -413,3 +413,52 @@ def test_plan_one_iteration_3d(priest):
     L = np.linalg.cholesky(np64(cov) + cem.cov_jitter * np.trace(np64(cov)) / wl.D * np.eye(wl.D))
     assert np.all(np.isfinite(L))
     gp.close()
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: BF16 MFMA operands for the right-hand side and a BF16
+# hi/lo split of the KKT product, FP32 accumulation, FP32 refinement tail
+# ---------------------------------------------------------------------------
+def test_bf16_mixed_error_against_oracle(priest):
+    """Error of the mixed-precision projection against the FP64 oracle is
+    reported per coefficient and per constraint residual, and bounded."""
+    say("project c2 BF16 mixed precision, oracle on 40 sampled samples")
+    wl = W.C2
+    idx = np.random.default_rng(11).choice(1000, 40, replace=False)
+    bc, obs = W.scene(wl, 0)
+    xi = W.samples(wl, 5, n=1000).astype(np.float32)
+    gp32 = priest.Problem.from_workload(wl)
+    gpbf = priest.Problem.from_workload(wl, precision=priest.BF16_MIXED, n_refine_fp32=10)
+    x32, r32, _ = gp32.project(t32(bc), t32(obs), t32(xi), wl.n_proj_iters)
+    xbf, rbf, _ = gpbf.project(t32(bc), t32(obs), t32(xi), wl.n_proj_iters)
+    torch.cuda.synchronize()
+    op = oracle_problem(wl)
+    pr = O.project(op, bc, obs, xi[idx].astype(np.float64), wl.n_proj_iters)
+    e32 = rel_err(np64(x32)[idx], pr.xi_bar)
+    ebf = rel_err(np64(xbf)[idx], pr.xi_bar)
+    res_err = np.abs(np64(rbf)[idx] - pr.resid)
+    eq = np.abs(np64(xbf) @ op.A().T - op.b_eq(bc)).max()
+    print(f"[bf16] coefficient rel err median {np.median(ebf):.2e} p99 {np.quantile(ebf, .99):.2e} "
+          f"max {ebf.max():.2e} (fp32: median {np.median(e32):.2e}); residual abs err "
+          f"median {np.median(res_err):.2e} max {res_err.max():.2e}; max |A xi - b| {eq:.2e}",
+          flush=True)
+    assert np.median(ebf) < 3e-3
+    assert np.quantile(ebf, 0.9) < 3e-2
+    assert np.median(res_err) < 2e-2
+    assert eq < 1e-3
+    gp32.close(); gpbf.close()
+
+
+def test_bf16_mode_with_full_refinement_is_fp32(priest):
+    """With n_refine_fp32 >= n_iter no iteration runs in BF16: the result is
+    bitwise the FP32 one."""
+    say("BF16 mode with full FP32 refinement")
+    wl = W.C1
+    bc, obs = W.scene(wl, 0)
+    xi = t32(W.samples(wl, 5))
+    a = priest.Problem.from_workload(wl).project(t32(bc), t32(obs), xi, 50)
+    b = priest.Problem.from_workload(wl, precision=priest.BF16_MIXED, n_refine_fp32=50).project(
+        t32(bc), t32(obs), xi, 50)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
