@@ -144,6 +144,37 @@ def batched_3d(P, W, steps: int, plain_problems: int):
             "speedup": round(t_plain / t_batch, 3)}
 
 
+def serving(P, W, n_requests: int, plain_limit_s: float):
+    """Continuous-batching service: the Poisson request stream of many robots
+    (mixed N, M, K) replayed in real time through the server, and the same
+    stream through one priest_plan call per request (the plain form)."""
+    from paper_2309_08235_amd import serve as S
+    wl = W.C5
+    reqs = W.serving_requests(wl, n_requests=n_requests)
+    offered_flop = sum(projection_flops(wl.dims, wl.n_coeff, q.n_steps, q.n_obs) * q.n_samples
+                       for q in reqs) * wl.n_proj_iters * wl.n_cem
+    span = reqs[-1].arrival
+    srv = S.Server.for_workload(wl, max_active=1024, memory_budget=2 << 30)
+    S.prepare_shapes(srv, reqs)
+    warm = W.serving_requests(wl, n_requests=256)
+    S.run_stream(srv, warm, wl, realtime=False)          # warm-up (other robots' state reset below)
+    srv.close()
+    srv = S.Server.for_workload(wl, max_active=1024, memory_budget=2 << 30)
+    S.prepare_shapes(srv, reqs)
+    batched, done = S.run_stream(srv, reqs, wl, realtime=True)
+    bad = sum(1 for c in done if c.status != 0)
+    srv.close()
+    plain, _ = S.run_plain(reqs, wl, realtime=True, time_limit=plain_limit_s)
+    return {"workload": wl.name, "robots": wl.n_robots, "requests": n_requests,
+            "offered_req_per_s": round(n_requests / span, 1),
+            "offered_tflop_per_s": round(offered_flop / span / 1e12, 2),
+            "iterations": f"{wl.n_proj_iters} projection x {wl.n_cem} CEM",
+            "continuous_batching": batched, "nonfinite_results": bad,
+            "plain_per_request": plain,
+            "plain_note": f"one priest_plan per request, FIFO, synchronised; stopped after "
+                          f"{plain_limit_s} s if behind"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +187,9 @@ def main():
                     help="skip the batched 3D comparison")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--plain-problems", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-plain-limit", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every problem and "
@@ -258,6 +292,10 @@ def main():
     if not args.no_extra:
         extra = batched_3d(P, W, args.batch_steps, args.plain_problems)
 
+    serve_line = None
+    if not args.no_serve:
+        serve_line = serving(P, W, args.serve_requests, args.serve_plain_limit)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_sample, gpu_results)
@@ -286,6 +324,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed_precision": mixed,
         "batched_3d": extra,
+        "serving": serve_line,
     }
     print(json.dumps(line), flush=True)
 

@@ -195,6 +195,131 @@ int32_t priest_debug_normals(uint64_t seed, uint32_t stream_id, int32_t iter, in
 int32_t priest_debug_constants(const priest_problem* p, int32_t which, float* host_out,
                                int32_t count);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching server (the serving form of Alg. 1)
+ *
+ * Planning requests of different sizes (n_samples, n_obs, n_steps) from many
+ * robots arrive at any time.  Each priest_server_step advances every active
+ * request by ONE iteration of Alg. 1 - draw, project (eqs. (4)-(7)), select,
+ * refit (eqs. (9a)-(9c)) - with one projection launch per distinct n_steps
+ * and one selection/refit launch for all requests, every request on blocks
+ * of its own.  A pending request is admitted at a step boundary when a slot
+ * is free, its robot has no request in flight, and its device state fits the
+ * memory budget (first-fit); it leaves after n_cem iterations.  Each robot's
+ * sampling distribution (mu, Sigma) stays on the device between its requests
+ * (the warm start of the next plan).  Draws use Philox4x32-10 with key
+ * config.seed and counter (sample, d/4, CEM iteration, request.stream_id), so
+ * a request's result does not depend on which other requests share its steps.
+ *
+ * Threading: a server is used from one host thread at a time.  All device
+ * work is enqueued on the stream given at creation.
+ * ------------------------------------------------------------------------ */
+typedef struct priest_server priest_server; /* opaque */
+
+typedef struct priest_server_config {
+  int32_t dims;               /* 2 or 3 */
+  int32_t n_coeff;            /* coefficients per axis, 2..16 */
+  uint32_t bc_mask;           /* PRIEST_BC_* rows of every request */
+  int32_t precision;          /* PRIEST_FP32 or PRIEST_BF16_MIXED */
+  int32_t n_refine_fp32;      /* see priest_problem_desc */
+  int32_t max_active;         /* requests advanced together, 1..8192 */
+  int32_t max_robots;         /* robot ids are 0..max_robots-1, 1..65536 */
+  int32_t max_inflight_steps; /* steps the device may run behind the host, 1 or 2 */
+  int32_t dry_run;            /* 1: admission bookkeeping only, no device call (host tests) */
+  int32_t reserved;           /* must be 0 */
+  double rho, v_max, a_max;   /* as in priest_problem_desc */
+  uint64_t seed;              /* Philox key of every draw */
+  uint64_t memory_budget;     /* bytes of device memory for per-request state, >= 4096 */
+  float sigma, gamma, cov_jitter; /* as in priest_cem_params */
+  float init_std;             /* a reset covariance is init_std^2 I, > 0 */
+} priest_server_config;
+
+#define PRIEST_WARM_RESET 0     /* mu = straight line start -> goal, Sigma = init_std^2 I */
+#define PRIEST_WARM_KEEP 1      /* keep the robot's mu and Sigma (reset if it has none yet) */
+#define PRIEST_WARM_KEEP_MEAN 2 /* keep mu, reset Sigma */
+
+typedef struct priest_request {
+  int32_t robot;        /* 0..max_robots-1 */
+  int32_t n_steps;      /* 2..256 */
+  int32_t n_obs;        /* 0..1024 */
+  int32_t n_samples;    /* 1..8192 */
+  int32_t n_cem;        /* >= 1 */
+  int32_t n_proj_iters; /* >= 0 */
+  int32_t n_proj;       /* 1..n_samples */
+  int32_t n_elite;      /* 1..n_proj */
+  int32_t warm_start;   /* PRIEST_WARM_* */
+  uint32_t stream_id;   /* Philox stream of this request's draws */
+  double horizon;       /* T > 0 */
+  double arrival;       /* caller's timestamp (priest_server_now clock), echoed back */
+  const float* bc;      /* HOST [dims][6], copied at submit */
+  const float* obs;     /* HOST [n_obs][8], copied at submit */
+} priest_request;
+
+typedef struct priest_result {
+  int64_t request_id;
+  int32_t robot;
+  int32_t status;       /* PRIEST_OK or PRIEST_ERR_NONFINITE */
+  double arrival;       /* as submitted */
+  double t_admit;       /* host clock at admission */
+  double t_done;        /* host clock when the completion was observed */
+  float best_cost;      /* c_aug of best_xi */
+  float best_xi[3 * PRIEST_MAX_COEFF]; /* first D entries valid */
+} priest_result;
+
+typedef struct priest_server_stats {
+  int64_t submitted, admitted, completed, steps;
+  int64_t max_active_seen;
+  int64_t arena_used, arena_budget, arena_high_water; /* bytes */
+  int64_t sample_iters; /* sum of n_samples * n_proj_iters * n_cem over completed requests */
+} priest_server_stats;
+
+/* Host clock in seconds (monotonic) used for the timestamps above. */
+double priest_server_now(void);
+
+/* Creates a server: allocates the request arena (memory_budget bytes), the
+ * per-robot store (max_robots * (D + D*D) floats) and pinned staging.
+ * Errors: INVALID, NOMEM, DEVICE. */
+int32_t priest_server_create(const priest_server_config* cfg, void* stream, priest_server** out);
+
+/* Builds (and caches) the problem constants for one (n_steps, n_obs, horizon)
+ * ahead of time; otherwise they are built at the first admission of that
+ * shape, which synchronises the stream.  No-op in dry-run mode. */
+int32_t priest_server_prepare(priest_server* s, int32_t n_steps, int32_t n_obs, double horizon);
+
+/* Queues a request (FIFO).  `id` receives its id (> 0).  Errors: INVALID
+ * (bad sizes, non-finite scene values, unknown robot), NOMEM (state larger
+ * than the whole budget). */
+int32_t priest_server_submit(priest_server* s, const priest_request* r, int64_t* id);
+
+/* Observes finished steps, admits pending requests, and enqueues one CEM
+ * iteration of every active request.  Blocks only while max_inflight_steps
+ * steps are already running.  n_active (nullable) receives the number of
+ * requests in the enqueued step (0: nothing enqueued). */
+int32_t priest_server_step(priest_server* s, int32_t* n_active);
+
+/* Moves up to max_results finished requests to `out` (host), oldest first;
+ * n receives the count.  Non-blocking. */
+int32_t priest_server_poll(priest_server* s, priest_result* out, int32_t max_results, int32_t* n);
+
+/* Waits until every enqueued step has finished on the device. */
+int32_t priest_server_flush(priest_server* s);
+
+/* Numbers of queued, active (advanced by the next step) and in-flight steps
+ * (any pointer may be NULL). */
+int32_t priest_server_counts(const priest_server* s, int32_t* pending, int32_t* active,
+                             int32_t* inflight_steps);
+
+int32_t priest_server_stats_get(const priest_server* s, priest_server_stats* out);
+
+/* Copies a robot's current mu [D] and Sigma [D][D] to host memory after
+ * waiting for the enqueued work.  Errors: INVALID (robot has no state). */
+int32_t priest_server_robot_state(priest_server* s, int32_t robot, float* host_mu,
+                                  float* host_cov);
+
+/* Waits for the device, releases everything (NULL accepted).  Requests not
+ * yet polled are dropped. */
+int32_t priest_server_destroy(priest_server* s);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* priest_last_error(void);
 

@@ -269,6 +269,14 @@ int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float*
 
 }  // namespace
 
+// Helpers shared with the serving runtime (serve.hip).
+namespace priest {
+int32_t set_error(int32_t code, const char* msg) { return fail(code, "%s", msg); }
+ProjArgs problem_args(const priest_problem* p) { return base_args(p); }
+int problem_bf16_iters(const priest_problem* p, int n_iter) { return bf16_iters(p, n_iter); }
+int32_t problem_check_lds(const priest_problem* p, const ProjArgs& a) { return check_lds(p, a); }
+}  // namespace priest
+
 extern "C" {
 
 const char* priest_last_error(void) { return g_err.c_str(); }

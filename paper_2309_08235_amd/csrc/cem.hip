@@ -118,15 +118,16 @@ __device__ void select_sorted(const uint32_t* keys_in, const int* vals_in, int n
   }
 }
 
+// One block's work: selection, refit and factorisation for problem `prob`
+// of `a`.  Shared by the uniform-batch kernel and the descriptor-table kernel.
 template <int IPT, int DM>
-__global__ __launch_bounds__(kCemThreads) void cem_kernel(CemArgs a) {
+__device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   using Sort = hipcub::BlockRadixSort<uint32_t, kCemThreads, IPT, int>;
   __shared__ typename Sort::TempStorage sort_tmp;
   __shared__ uint32_t skey[kCemThreads * IPT];
   __shared__ int sval[kCemThreads * IPT];
   extern __shared__ float4 sm4[];
   char* sm = reinterpret_cast<char*>(sm4);
-  const int prob = blockIdx.x;
   const int D = a.D, N = a.N, tid = threadIdx.x, T = blockDim.x;
   const CemLayout l = cem_layout(D, a.n_proj, a.n_elite);
   int* proj = reinterpret_cast<int*>(sm + l.proj);
@@ -285,6 +286,17 @@ __global__ __launch_bounds__(kCemThreads) void cem_kernel(CemArgs a) {
   PRIEST_CEM_MARK(7);
 }
 
+template <int IPT, int DM>
+__global__ __launch_bounds__(kCemThreads) void cem_kernel(CemArgs a) {
+  cem_block<IPT, DM>(a, blockIdx.x);
+}
+
+// Descriptor table: block t handles task t with its own arguments.
+template <int IPT, int DM>
+__global__ __launch_bounds__(kCemThreads) void cem_task_kernel(const CemArgs* tasks) {
+  cem_block<IPT, DM>(tasks[blockIdx.x], 0);
+}
+
 }  // namespace
 
 size_t cem_lds_bytes(int N, int D, int n_elite) {
@@ -296,6 +308,22 @@ static void launch_dm(const CemArgs& a, dim3 grid, dim3 block, size_t lds, hipSt
   if (a.N <= kCemThreads * 2) hipLaunchKernelGGL((cem_kernel<2, DM>), grid, block, lds, s, a);
   else if (a.N <= kCemThreads * 4) hipLaunchKernelGGL((cem_kernel<4, DM>), grid, block, lds, s, a);
   else hipLaunchKernelGGL((cem_kernel<16, DM>), grid, block, lds, s, a);
+}
+
+template <int DM>
+static void launch_task_dm(const CemTaskLaunch& t, size_t lds, hipStream_t s) {
+  const dim3 grid(t.n_tasks), block(kCemThreads);
+  if (t.max_N <= kCemThreads * 2) hipLaunchKernelGGL((cem_task_kernel<2, DM>), grid, block, lds, s, t.tasks);
+  else if (t.max_N <= kCemThreads * 4) hipLaunchKernelGGL((cem_task_kernel<4, DM>), grid, block, lds, s, t.tasks);
+  else hipLaunchKernelGGL((cem_task_kernel<16, DM>), grid, block, lds, s, t.tasks);
+}
+
+hipError_t launch_cem_tasks(const CemTaskLaunch& t, hipStream_t s) {
+  const size_t lds = cem_layout(t.D, t.max_N, t.max_elite).total;
+  if (t.D <= 24) launch_task_dm<24>(t, lds, s);
+  else if (t.D <= 36) launch_task_dm<36>(t, lds, s);
+  else launch_task_dm<48>(t, lds, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s) {

@@ -11,7 +11,6 @@
 namespace priest {
 
 constexpr int kMaxNV = PRIEST_MAX_COEFF;
-constexpr int kProjectThreads = 256;
 constexpr int kCemThreads = 512;
 
 // Sample sources of the projection kernel.
@@ -72,7 +71,24 @@ struct CemArgs {
   int32_t* status;                         // nullable, [1] per problem
 };
 
+// Launch descriptions of the descriptor-table kernels (serving path): all
+// tasks of one projection launch share dims and n_steps; `tasks`/`prefix`
+// are device arrays (prefix[t] = first block of task t, prefix[n] = n_blocks).
+struct ProjTaskLaunch {
+  const ProjArgs* tasks;
+  const int* prefix;
+  int n_tasks, n_blocks, dims, K;
+  bool bf16;
+  size_t lds_bytes;
+};
+struct CemTaskLaunch {
+  const CemArgs* tasks;
+  int n_tasks, D, max_N, max_elite;
+};
+
 // host-side launchers (defined in the .hip files)
+hipError_t launch_project_tasks(const ProjTaskLaunch& t, hipStream_t s);
+hipError_t launch_cem_tasks(const CemTaskLaunch& t, hipStream_t s);
 size_t project_lds_bytes(const ProjArgs& a);
 int project_pick_tile(int dims, int nv, int K, int M, int N, int n_problems, int* S, int* G);
 hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s);
@@ -84,6 +100,13 @@ hipError_t launch_kkt(const double* Q, const double* A, int nv, int E, const int
 hipError_t launch_debug_offsets(const ProjArgs& a, const float* xi, float* out, hipStream_t s);
 hipError_t launch_debug_normals(uint64_t seed, uint32_t stream_id, int iter, int N, int D,
                                 float* z, hipStream_t s);
+
+// api.hip services used by the serving runtime
+#define PRIEST_HIDDEN __attribute__((visibility("hidden")))
+PRIEST_HIDDEN int32_t set_error(int32_t code, const char* msg);
+PRIEST_HIDDEN ProjArgs problem_args(const priest_problem* p);
+PRIEST_HIDDEN int problem_bf16_iters(const priest_problem* p, int n_iter);
+PRIEST_HIDDEN int32_t problem_check_lds(const priest_problem* p, const ProjArgs& a);
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the Philox S-P network

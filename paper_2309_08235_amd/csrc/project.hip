@@ -337,15 +337,17 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, float tt, fl
   }
 }
 
+// One block's work: samples [4*tile, 4*tile + 4) of problem `prob` of `a`
+// for the whole projection.  Shared by the uniform-batch kernel and the
+// descriptor-table kernel of the serving path.
 template <int DIMS, int MAXT, bool BF16>
-__global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
+__device__ __forceinline__ void project_block(const ProjArgs& a, int prob, int tile) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, TW = blockDim.x >> 6;
   const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv;
   const Layout l = layout(DIMS, nv, M, TW, a.mode);
-  const int prob = blockIdx.x / a.blocks_per_problem;
-  const int s0 = (blockIdx.x - prob * a.blocks_per_problem) * 4;
+  const int s0 = tile * 4;
   const int ns = min(4, a.N - s0);
   // MFMA column layout: q = row group, col = 4*cs + cx
   const int q = lane >> 4, col = lane & 15, cs = col >> 2, cx = col & 3;
@@ -613,6 +615,27 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
   }
 }
 
+// Uniform batch: block b works on problem b / blocks_per_problem.
+template <int DIMS, int MAXT, bool BF16>
+__global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
+  const int prob = blockIdx.x / a.blocks_per_problem;
+  project_block<DIMS, MAXT, BF16>(a, prob, blockIdx.x - prob * a.blocks_per_problem);
+}
+
+// Descriptor table (heterogeneous requests sharing n_steps): task t owns
+// blocks [prefix[t], prefix[t+1]); every field of its ProjArgs is its own.
+template <int DIMS, int MAXT, bool BF16>
+__global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* tasks,
+                                                            const int* prefix, int n_tasks) {
+  int lo = 0, hi = n_tasks;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= static_cast<int>(blockIdx.x)) lo = mid;
+    else hi = mid;
+  }
+  project_block<DIMS, MAXT, BF16>(tasks[lo], 0, static_cast<int>(blockIdx.x) - prefix[lo]);
+}
+
 // Per-row push-outs e(xi) - F xi, [N][M + 2][K][dims] (parity hook): one
 // thread per (sample, t), the same record table and per-pair push-out
 // arithmetic as the projection kernel, one obstacle at a time.
@@ -704,6 +727,31 @@ hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
     } else {
       if (bf) hipLaunchKernelGGL((project_kernel<3, 1024, true>), grid, block, lds, s, a);
       else hipLaunchKernelGGL((project_kernel<3, 1024, false>), grid, block, lds, s, a);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_tasks(const ProjTaskLaunch& t, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(t.n_blocks));
+  const dim3 block(64 * project_waves(t.K));
+  const size_t lds = t.lds_bytes;
+  const bool bf = t.bf16;
+  if (block.x <= 512) {
+    if (t.dims == 2) {
+      if (bf) hipLaunchKernelGGL((project_task_kernel<2, 512, true>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+      else hipLaunchKernelGGL((project_task_kernel<2, 512, false>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+    } else {
+      if (bf) hipLaunchKernelGGL((project_task_kernel<3, 512, true>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+      else hipLaunchKernelGGL((project_task_kernel<3, 512, false>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+    }
+  } else {
+    if (t.dims == 2) {
+      if (bf) hipLaunchKernelGGL((project_task_kernel<2, 1024, true>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+      else hipLaunchKernelGGL((project_task_kernel<2, 1024, false>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+    } else {
+      if (bf) hipLaunchKernelGGL((project_task_kernel<3, 1024, true>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
+      else hipLaunchKernelGGL((project_task_kernel<3, 1024, false>), grid, block, lds, s, t.tasks, t.prefix, t.n_tasks);
     }
   }
   return hipGetLastError();

@@ -35,7 +35,13 @@ EXPORTS = (
     "priest_init_problem", "priest_free_problem", "priest_problem_dim", "priest_project",
     "priest_plan_workspace_size", "priest_plan", "priest_plan_batch", "priest_debug_offsets",
     "priest_debug_normals", "priest_debug_constants", "priest_last_error", "priest_version",
+    "priest_server_now", "priest_server_create", "priest_server_prepare", "priest_server_submit",
+    "priest_server_step", "priest_server_poll", "priest_server_flush", "priest_server_counts",
+    "priest_server_stats_get", "priest_server_robot_state", "priest_server_destroy",
 )
+
+WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
+MAX_D = 48
 
 
 class ProblemDesc(ctypes.Structure):
@@ -63,6 +69,41 @@ class PlanOut(ctypes.Structure):
                 ("status", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("n_coeff", ctypes.c_int32),
+                ("bc_mask", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("n_refine_fp32", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("max_robots", ctypes.c_int32), ("max_inflight_steps", ctypes.c_int32),
+                ("dry_run", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("v_max", ctypes.c_double), ("a_max", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("memory_budget", ctypes.c_uint64),
+                ("sigma", ctypes.c_float), ("gamma", ctypes.c_float),
+                ("cov_jitter", ctypes.c_float), ("init_std", ctypes.c_float)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("robot", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("n_obs", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("n_cem", ctypes.c_int32), ("n_proj_iters", ctypes.c_int32),
+                ("n_proj", ctypes.c_int32), ("n_elite", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("stream_id", ctypes.c_uint32),
+                ("horizon", ctypes.c_double), ("arrival", ctypes.c_double),
+                ("bc", ctypes.c_void_p), ("obs", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_int64), ("robot", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("arrival", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("best_cost", ctypes.c_float), ("best_xi", ctypes.c_float * MAX_D)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "admitted", "completed", "steps", "max_active_seen", "arena_used",
+        "arena_budget", "arena_high_water", "sample_iters")]
+
+
 class PriestError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"priest status {code}: {msg}")
@@ -88,6 +129,17 @@ _SIGS = {
     "priest_debug_offsets": (_I, [_P, _P, _P, _P, _I, _P, _P]),
     "priest_debug_normals": (_I, [ctypes.c_uint64, ctypes.c_uint32, _I, _I, _I, _P, _P]),
     "priest_debug_constants": (_I, [_P, _I, _P, _I]),
+    "priest_server_now": (ctypes.c_double, []),
+    "priest_server_create": (_I, [ctypes.POINTER(ServerConfig), _P, ctypes.POINTER(_P)]),
+    "priest_server_prepare": (_I, [_P, _I, _I, ctypes.c_double]),
+    "priest_server_submit": (_I, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]),
+    "priest_server_step": (_I, [_P, ctypes.POINTER(_I)]),
+    "priest_server_poll": (_I, [_P, ctypes.POINTER(Result), _I, ctypes.POINTER(_I)]),
+    "priest_server_flush": (_I, [_P]),
+    "priest_server_counts": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "priest_server_stats_get": (_I, [_P, ctypes.POINTER(ServerStats)]),
+    "priest_server_robot_state": (_I, [_P, _I, _P, _P]),
+    "priest_server_destroy": (_I, [_P]),
     "priest_last_error": (ctypes.c_char_p, []),
     "priest_version": (_I, []),
 }
@@ -202,6 +254,69 @@ def priest_debug_constants(handle, which: int, count: int):
     buf = (ctypes.c_float * count)()
     _check(lib().priest_debug_constants(handle, which, buf, count))
     return list(buf)
+
+
+def priest_server_now() -> float:
+    return lib().priest_server_now()
+
+
+def priest_server_create(cfg: ServerConfig, stream=None):
+    """`stream`: a torch stream, or None for the current stream (dry-run
+    servers take no stream)."""
+    h = ctypes.c_void_p()
+    st = None if cfg.dry_run else _stream(stream)
+    _check(lib().priest_server_create(ctypes.byref(cfg), st, ctypes.byref(h)))
+    return h
+
+
+def priest_server_prepare(server, n_steps, n_obs, horizon):
+    _check(lib().priest_server_prepare(server, n_steps, n_obs, horizon))
+
+
+def priest_server_submit(server, req: Request) -> int:
+    rid = ctypes.c_int64()
+    _check(lib().priest_server_submit(server, ctypes.byref(req), ctypes.byref(rid)))
+    return rid.value
+
+
+def priest_server_step(server) -> int:
+    n = _I()
+    _check(lib().priest_server_step(server, ctypes.byref(n)))
+    return n.value
+
+
+def priest_server_poll(server, max_results=256):
+    buf = (Result * max_results)()
+    n = _I()
+    _check(lib().priest_server_poll(server, buf, max_results, ctypes.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def priest_server_flush(server):
+    _check(lib().priest_server_flush(server))
+
+
+def priest_server_counts(server):
+    p, a, f = _I(), _I(), _I()
+    _check(lib().priest_server_counts(server, ctypes.byref(p), ctypes.byref(a), ctypes.byref(f)))
+    return p.value, a.value, f.value
+
+
+def priest_server_stats_get(server) -> dict:
+    st = ServerStats()
+    _check(lib().priest_server_stats_get(server, ctypes.byref(st)))
+    return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+
+def priest_server_robot_state(server, robot: int, D: int):
+    mu = (ctypes.c_float * D)()
+    cov = (ctypes.c_float * (D * D))()
+    _check(lib().priest_server_robot_state(server, robot, mu, cov))
+    return list(mu), list(cov)
+
+
+def priest_server_destroy(server):
+    _check(lib().priest_server_destroy(server))
 
 
 # ---------------------------------------------------------------------------

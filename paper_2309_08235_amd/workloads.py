@@ -171,3 +171,117 @@ def with_changes(wl: Workload, **kw) -> Workload:
     d = dict(wl.__dict__)
     d.update(kw)
     return Workload(**d)
+
+
+# ---------------------------------------------------------------------------
+# Serving stream (continuous batching): many robots re-planning on Poisson
+# clocks with requests of mixed size.
+# ---------------------------------------------------------------------------
+@dataclass
+class ServingWorkload:
+    name: str = "c5_serving_2d_256robots"
+    n_robots: int = 256
+    n_requests: int = 4096
+    mean_period: float = 0.1          # s between a robot's requests (Poisson clock)
+    sizes: tuple = (256, 512, 1024, 2048)
+    obs_range: tuple = (8, 128)       # M ~ U{lo..hi}
+    steps: tuple = (50, 100)          # K fixed per robot
+    horizons: tuple = (10.0, 15.0)    # T for K = 50 / 100
+    dims: int = 2
+    n_coeff: int = 11
+    n_proj_iters: int = 20
+    n_cem: int = 5
+    v_max: float = 1.5
+    a_max: float = 2.0
+    rho: float = 1.0
+    sigma: float = 0.5
+    gamma: float = 1.0
+    cov_jitter: float = 1e-5
+    init_std: float = 1.0
+    bc_mask: int = BC_DEFAULT
+    seed: int = 5000
+
+
+C5 = ServingWorkload()
+
+
+@dataclass
+class ServingRequest:
+    index: int
+    robot: int
+    arrival: float      # s after the stream starts
+    n_samples: int
+    n_obs: int
+    n_steps: int
+    horizon: float
+    n_proj: int
+    n_elite: int
+    bc: np.ndarray      # [dims, 6]
+    obs: np.ndarray     # [n_obs, 8]
+
+
+def _serving_scene(rng, dims, start, goal, n_obs):
+    """Obstacles around the start-goal box; 60% static, 40% moving at
+    constant velocity (as in the dynamic benchmark).  Candidates within
+    (radius + 1 m) of the start or goal are dropped and re-drawn."""
+    lo = np.minimum(start, goal) - 0.5
+    hi = np.maximum(start, goal) + 0.5
+    cs, rs = [], []
+    while len(cs) < n_obs:
+        c = rng.uniform(lo, hi, size=(2 * n_obs, dims))
+        r = rng.uniform(0.2, 0.5, size=2 * n_obs)
+        ok = ((np.linalg.norm(c - start, axis=1) >= r + 1.0) &
+              (np.linalg.norm(c - goal, axis=1) >= r + 1.0))
+        cs.extend(c[ok])
+        rs.extend(r[ok])
+    c = np.array(cs[:n_obs])
+    r = np.array(rs[:n_obs])
+    n_static = int(round(n_obs * 0.6))
+    head = rng.uniform(0.0, 2.0 * np.pi, size=n_obs)
+    speed = rng.uniform(0.0, 1.0, size=n_obs)
+    speed[:n_static] = 0.0
+    obs = np.zeros((n_obs, 8))
+    obs[:, :dims] = c
+    obs[:, 3] = speed * np.cos(head)
+    obs[:, 4] = speed * np.sin(head)
+    obs[:, 6] = r
+    obs[:, 7] = r
+    return obs
+
+
+def serving_requests(wl: ServingWorkload = C5, n_requests: int | None = None,
+                     n_robots: int | None = None, rate_scale: float = 1.0):
+    """The request stream, ordered by arrival time.  Robot r has a fixed K
+    (alternating 50/100), a fixed goal, and exponential inter-arrival times
+    with mean mean_period / rate_scale; each request draws N and M
+    independently and gets a fresh obstacle scene.  A robot's start moves a
+    little toward its goal with every request."""
+    n_requests = wl.n_requests if n_requests is None else n_requests
+    n_robots = wl.n_robots if n_robots is None else n_robots
+    rng = np.random.Generator(np.random.PCG64(wl.seed))
+    d = wl.dims
+    K = [wl.steps[r % len(wl.steps)] for r in range(n_robots)]
+    T = [wl.horizons[r % len(wl.horizons)] for r in range(n_robots)]
+    base = rng.uniform(0.0, 2.0, size=(n_robots, d))
+    span = np.array([7.0 if k == wl.steps[0] else 10.0 for k in K])
+    goal = base + span[:, None]
+    # arrival times: per-robot Poisson clocks, merged
+    per_robot = max(1, -(-n_requests // n_robots)) + 2
+    gaps = rng.exponential(wl.mean_period / rate_scale, size=(n_robots, per_robot))
+    times = np.cumsum(gaps, axis=1)
+    events = sorted((times[r, j], r, j) for r in range(n_robots) for j in range(per_robot))
+    events = events[:n_requests]
+    out = []
+    for i, (t, r, j) in enumerate(events):
+        n = int(rng.choice(wl.sizes))
+        m = int(rng.integers(wl.obs_range[0], wl.obs_range[1] + 1))
+        frac = min(0.5, 0.02 * j)
+        start = base[r] + frac * (goal[r] - base[r])
+        bc = np.zeros((d, 6))
+        bc[:, 0] = start
+        bc[:, 3] = goal[r]
+        obs = _serving_scene(rng, d, start, goal[r], m)
+        out.append(ServingRequest(index=i, robot=r, arrival=float(t), n_samples=n, n_obs=m,
+                                  n_steps=K[r], horizon=T[r], n_proj=default_n_proj(n),
+                                  n_elite=default_n_elite(n), bc=bc, obs=obs))
+    return out
