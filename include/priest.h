@@ -175,6 +175,43 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
                           const float* noise, const priest_plan_out* out, void* workspace,
                           size_t workspace_bytes, int32_t use_graph, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Tile shape of the projection kernel
+ *
+ * The same projection can be laid out on the GPU in several ways: 4 MFMA
+ * columns per sample (4 samples per block) or, in 2D, 2 columns per sample
+ * (8 samples per block, two items per lane); one or two 16-step time blocks
+ * per wave; one block per tile or a persistent grid of resident blocks that
+ * loop over tiles.  Every shape gives bit-identical results.  By default the
+ * library times every candidate the first time a problem handle meets a new
+ * (N, n_problems, sampling mode, precision) - one warm-up and two timed
+ * launches of a shortened (<= 8 iteration) copy of the real launch, outputs
+ * redirected to scratch - and keeps the fastest.  That first call
+ * synchronises the stream (and priest_project allocates N*(D+2) floats of
+ * scratch for it).  No tuning happens while the stream is being captured
+ * into a graph, or with PRIEST_AUTOTUNE=0 in the environment: the default
+ * shape (4, 1, 0) is used.
+ * ------------------------------------------------------------------------ */
+typedef struct priest_tiling {
+  int32_t axis_slots; /* MFMA columns per sample: 4, or 2 (2D only) */
+  int32_t row_tiles;  /* 16-step time blocks per wave: 1 or 2 */
+  int32_t persistent; /* 1: grid of resident blocks looping over tiles */
+  int32_t reserved;   /* must be 0 */
+} priest_tiling;
+
+/* Candidate shapes for p (host call): writes up to max_out of them, n
+ * receives the total.  Entry 0 is the default shape. */
+int32_t priest_tiling_candidates(const priest_problem* p, priest_tiling* out, int32_t max_out,
+                                 int32_t* n);
+
+/* Forces every later projection launch of p to use *t; NULL returns to
+ * autotuning.  Errors: INVALID (not a candidate for p). */
+int32_t priest_set_tiling(priest_problem* p, const priest_tiling* t);
+
+/* Shape used by p's most recent projection launch; `tuned` (nullable)
+ * receives 1 if it came from the autotuner. */
+int32_t priest_last_tiling(const priest_problem* p, priest_tiling* out, int32_t* tuned);
+
 /* Debug/parity hook for the closed-form alpha/beta/d step (Appendix eqs.
  * (15a)-(15c), (13)): for samples xi [N][D] writes the per-row push-outs
  * e(xi) - F xi, laid out [N][n_obs + 2][K][dims] (obstacle blocks, then the

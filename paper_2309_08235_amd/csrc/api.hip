@@ -3,9 +3,11 @@
 // project.hip (projection), cem.hip (selection / refit / Cholesky) and
 // kkt.hip (one-time FP64 KKT factorisation); this file builds the Bernstein
 // basis and Q on the host in FP64 and orders the launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -61,6 +63,27 @@ struct GraphEntry {
 
 size_t align256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
 
+struct TuneEntry {
+  int N, P, mode, bf16;
+  TileCfg cfg;
+  std::vector<float> ms;
+};
+
+// PRIEST_AUTOTUNE=0 in the environment turns the autotuner off.
+bool autotune_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("PRIEST_AUTOTUNE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
+  return st != hipStreamCaptureStatusNone;
+}
+
 }  // namespace
 
 struct priest_problem {
@@ -77,6 +100,13 @@ struct priest_problem {
   std::vector<GraphEntry> graphs;
   int device = 0;
   size_t lds_limit = 0;
+  // projection tile shape: autotuner results per (N, n_problems, mode, bf16)
+  std::mutex tune_mu;
+  std::vector<TuneEntry> tuned;
+  bool forced = false;
+  TileCfg force_cfg{4, 1, 0};
+  TileCfg last_cfg{4, 1, 0};
+  int last_tuned = 0;
 };
 
 namespace {
@@ -177,11 +207,17 @@ PlanLayout plan_layout(int D, int N) {
   return l;
 }
 
-// Enqueues n_cem CEM iterations for n_problems problems of shape p.
-int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float* obs,
-                     const priest_cem_params* c, float* mu, float* cov, uint64_t seed,
-                     uint32_t stream_base, const float* noise, const priest_plan_out* out,
-                     char* ws, hipStream_t s) {
+struct PlanArgs {
+  ProjArgs a;
+  CemArgs ca;
+};
+
+// Launch arguments of the plan loop for n_problems problems of shape p, with
+// the default tile shape.
+PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* obs,
+                   const priest_cem_params* c, float* mu, float* cov, uint64_t seed,
+                   uint32_t stream_base, const float* noise, const priest_plan_out* out, char* ws) {
+  (void)P;
   const int D = p->D, N = c->n_samples;
   const PlanLayout pl = plan_layout(D, N);
   // per-problem workspace blocks are laid out [problem][...]: strides in floats
@@ -190,13 +226,8 @@ int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float*
   float* wr = reinterpret_cast<float*>(ws + pl.resid);
   float* wc = reinterpret_cast<float*>(ws + pl.c1);
   float* wL = reinterpret_cast<float*>(ws + pl.L);
-
-  if (out->status) {
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((P + 255) / 256), dim3(256), 0, s, out->status, P,
-                       PRIEST_OK);
-    HIP_TRY(hipGetLastError());
-  }
-  CemArgs ca{};
+  PlanArgs pa{};
+  CemArgs& ca = pa.ca;
   ca.D = D;
   ca.N = N;
   ca.n_proj = c->n_proj;
@@ -221,14 +252,11 @@ int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float*
   ca.elite_idx = out->elite_idx;
   ca.proj_idx = out->proj_idx;
   ca.status = out->status;
-  ca.chol_only = 1;
-  HIP_TRY(launch_cem(ca, P, s));
   ca.chol_only = 0;
 
-  ProjArgs a = base_args(p);
+  ProjArgs& a = pa.a;
+  a = base_args(p);
   a.N = N;
-  project_pick_tile(a.dims, a.nv, a.K, a.M, N, P, &a.S, &a.G);
-  a.blocks_per_problem = (N + a.S - 1) / a.S;
   a.n_iter = c->n_proj_iters;
   a.bf16_iters = bf16_iters(p, a.n_iter);
   a.mode = noise ? kFromNoise : kFromPhilox;
@@ -242,22 +270,37 @@ int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float*
   a.mu_stride = D;
   a.L = wL;
   a.L_stride = wstride;
+  a.noise = noise;
   a.noise_stride = static_cast<int64_t>(c->n_cem) * N * D;
   a.xi_out = wxb;
   a.xi_out_stride = wstride;
   a.resid = wr;
   a.c1 = wc;
   a.n_stride = wstride;
-  {
-    const int32_t st = check_lds(p, a);
-    if (st != PRIEST_OK) return st;
+  a.xi_src_stride = static_cast<int64_t>(N) * D;
+  apply_tiling(a, tile_candidates(a.dims)[0]);
+  return pa;
+}
+
+// Enqueues n_cem CEM iterations for n_problems problems.
+int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const float* noise,
+                     const priest_plan_out* out, hipStream_t s) {
+  ProjArgs a = pa.a;
+  CemArgs ca = pa.ca;
+  const int D = ca.D, N = ca.N;
+  if (out->status) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((P + 255) / 256), dim3(256), 0, s, out->status, P,
+                       PRIEST_OK);
+    HIP_TRY(hipGetLastError());
   }
+  ca.chol_only = 1;
+  HIP_TRY(launch_cem(ca, P, s));
+  ca.chol_only = 0;
   for (int l = 0; l < c->n_cem; ++l) {
     a.iter = l;
     a.noise = noise ? noise + static_cast<int64_t>(l) * N * D : nullptr;
     const bool last = (l == c->n_cem - 1);
     a.xi_src = last ? out->xi : nullptr;
-    a.xi_src_stride = static_cast<int64_t>(N) * D;
     a.resid2 = last ? out->resid : nullptr;
     a.c12 = last ? out->c1 : nullptr;
     a.xi_out2 = last ? out->xi_bar : nullptr;
@@ -265,6 +308,63 @@ int32_t enqueue_plan(priest_problem* p, int32_t P, const float* bc, const float*
     HIP_TRY(launch_cem(ca, P, s));
   }
   return PRIEST_OK;
+}
+
+bool tiling_cached(priest_problem* p, const ProjArgs& a, int P) {
+  std::lock_guard<std::mutex> lk(p->tune_mu);
+  if (p->forced) return true;
+  const int bf = a.bf16_iters > 0;
+  for (const TuneEntry& e : p->tuned)
+    if (e.N == a.N && e.P == P && e.mode == a.mode && e.bf16 == bf) return true;
+  return false;
+}
+
+// Tile shape for a projection of `a` over P problems: the forced shape, a
+// cached autotuner result, or, when `trial` is given and tuning is possible,
+// the fastest candidate measured on `trial` (which writes only scratch).
+// Otherwise the default shape.
+int32_t resolve_tiling(priest_problem* p, const ProjArgs& a, int P, hipStream_t s,
+                       const ProjArgs* trial, TileCfg* out) {
+  std::lock_guard<std::mutex> lk(p->tune_mu);
+  const std::vector<TileCfg> cands = tile_candidates(a.dims);
+  p->last_tuned = 0;
+  if (p->forced) {
+    *out = p->force_cfg;
+    p->last_cfg = *out;
+    return PRIEST_OK;
+  }
+  const int bf = a.bf16_iters > 0;
+  for (const TuneEntry& e : p->tuned)
+    if (e.N == a.N && e.P == P && e.mode == a.mode && e.bf16 == bf) {
+      *out = e.cfg;
+      p->last_cfg = *out;
+      p->last_tuned = 1;
+      return PRIEST_OK;
+    }
+  *out = cands[0];
+  p->last_cfg = *out;
+  if (!trial || !autotune_enabled() || stream_capturing(s)) return PRIEST_OK;
+  std::vector<float> ms;
+  HIP_TRY(time_tilings(*trial, P, p->lds_limit, s, cands, &ms));
+  const int best = pick_tiling(ms);
+  p->tuned.push_back(TuneEntry{a.N, P, a.mode, bf, cands[best], ms});
+  *out = cands[best];
+  p->last_cfg = *out;
+  p->last_tuned = 1;
+  return PRIEST_OK;
+}
+
+// A shortened copy of `a` for timing: at most 8 iterations (keeping BF16
+// iterations if `a` has any, so that the same kernel instance runs).
+ProjArgs trial_args(const ProjArgs& a) {
+  ProjArgs t = a;
+  t.n_iter = std::min(a.n_iter, 8);
+  t.bf16_iters = a.bf16_iters > 0 ? std::max(1, std::min(a.bf16_iters, t.n_iter)) : 0;
+  t.xi_src = nullptr;
+  t.resid2 = nullptr;
+  t.c12 = nullptr;
+  t.xi_out2 = nullptr;
+  return t;
 }
 
 }  // namespace
@@ -419,10 +519,9 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   if (!bc || !xi_in || !xi_out) return fail(PRIEST_ERR_INVALID, "bc, xi_in and xi_out are required");
   if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
   if (N == 0) return PRIEST_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
   ProjArgs a = base_args(p);
   a.N = N;
-  project_pick_tile(a.dims, a.nv, a.K, a.M, N, 1, &a.S, &a.G);
-  a.blocks_per_problem = (N + a.S - 1) / a.S;
   a.n_iter = n_iter;
   a.bf16_iters = bf16_iters(p, n_iter);
   a.mode = kFromInput;
@@ -432,9 +531,27 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   a.xi_out = xi_out;
   a.resid = resid;
   a.c1 = c1;
-  const int32_t st = check_lds(p, a);
+  apply_tiling(a, tile_candidates(a.dims)[0]);
+  int32_t st = check_lds(p, a);
   if (st != PRIEST_OK) return st;
-  HIP_TRY(launch_project(a, 1, static_cast<hipStream_t>(stream)));
+  TileCfg cfg{};
+  if (n_iter > 0 && autotune_enabled() && !tiling_cached(p, a, 1) && !stream_capturing(s)) {
+    // time the candidates with outputs in scratch (xi_in may alias xi_out)
+    float* scratch = nullptr;
+    const size_t n = static_cast<size_t>(N) * (p->D + 2);
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&scratch), sizeof(float) * n));
+    ProjArgs t = trial_args(a);
+    t.xi_out = scratch;
+    t.resid = scratch + static_cast<size_t>(N) * p->D;
+    t.c1 = t.resid + N;
+    st = resolve_tiling(p, a, 1, s, &t, &cfg);
+    (void)hipFree(scratch);
+  } else {
+    st = resolve_tiling(p, a, 1, s, nullptr, &cfg);
+  }
+  if (st != PRIEST_OK) return st;
+  apply_tiling(a, cfg);
+  HIP_TRY(launch_project(a, 1, s));
   return PRIEST_OK;
 }
 
@@ -467,10 +584,29 @@ static int32_t plan_common(priest_problem* p, int32_t P, const float* bc, const 
   if (cem_lds_bytes(c->n_samples, p->D, c->n_elite) > p->lds_limit)
     return fail(PRIEST_ERR_INVALID, "n_samples too large for the selection kernel");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!use_graph)
-    return enqueue_plan(p, P, bc, obs, c, mu, cov, seed, stream_base, noise, out,
-                        static_cast<char*>(workspace), s);
-  if (!s) return fail(PRIEST_ERR_INVALID, "graph capture needs a non-default stream");
+  if (use_graph && !s) return fail(PRIEST_ERR_INVALID, "graph capture needs a non-default stream");
+  PlanArgs pa = plan_args(p, P, bc, obs, c, mu, cov, seed, stream_base, noise, out,
+                          static_cast<char*>(workspace));
+  st = check_lds(p, pa.a);
+  if (st != PRIEST_OK) return st;
+  // tile shape (before any capture: timing synchronises the stream); the
+  // trial needs the first draw's Cholesky factor, which the loop recomputes
+  TileCfg cfg{};
+  if (pa.a.n_iter > 0 && autotune_enabled() && !tiling_cached(p, pa.a, P) && !stream_capturing(s)) {
+    CemArgs chol = pa.ca;
+    chol.chol_only = 1;
+    chol.status = nullptr;
+    HIP_TRY(launch_cem(chol, P, s));
+    const ProjArgs t = trial_args(pa.a);
+    st = resolve_tiling(p, pa.a, P, s, &t, &cfg);
+  } else {
+    st = resolve_tiling(p, pa.a, P, s, nullptr, &cfg);
+  }
+  if (st != PRIEST_OK) return st;
+  apply_tiling(pa.a, cfg);
+  st = check_lds(p, pa.a);
+  if (st != PRIEST_OK) return st;
+  if (!use_graph) return enqueue_plan(P, pa, c, noise, out, s);
   std::vector<uint64_t> key = {
       static_cast<uint64_t>(P), reinterpret_cast<uint64_t>(bc), reinterpret_cast<uint64_t>(obs),
       reinterpret_cast<uint64_t>(mu), reinterpret_cast<uint64_t>(cov), seed, stream_base,
@@ -482,6 +618,8 @@ static int32_t plan_common(priest_problem* p, int32_t P, const float* bc, const 
       reinterpret_cast<uint64_t>(out->c1), reinterpret_cast<uint64_t>(out->status)};
   const uint32_t* cw = reinterpret_cast<const uint32_t*>(c);
   for (size_t i = 0; i < sizeof(priest_cem_params) / 4; ++i) key.push_back(cw[i]);
+  key.push_back(static_cast<uint64_t>(cfg.axis_slots) | (static_cast<uint64_t>(cfg.row_tiles) << 8) |
+                (static_cast<uint64_t>(cfg.persistent) << 16));
   std::lock_guard<std::mutex> lk(p->graph_mu);
   for (auto& g : p->graphs)
     if (g.key == key) {
@@ -489,8 +627,7 @@ static int32_t plan_common(priest_problem* p, int32_t P, const float* bc, const 
       return PRIEST_OK;
     }
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  st = enqueue_plan(p, P, bc, obs, c, mu, cov, seed, stream_base, noise, out,
-                    static_cast<char*>(workspace), s);
+  st = enqueue_plan(P, pa, c, noise, out, s);
   hipGraph_t graph = nullptr;
   const hipError_t ce = hipStreamEndCapture(s, &graph);
   if (st != PRIEST_OK) {
@@ -527,6 +664,41 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
                           int32_t use_graph, void* stream) {
   return plan_common(p, n_problems, bc, obs, c, mu, cov, seed, stream_base, noise, out, workspace,
                      workspace_bytes, use_graph, stream);
+}
+
+int32_t priest_tiling_candidates(const priest_problem* p, priest_tiling* out, int32_t max_out,
+                                 int32_t* n) {
+  if (!p || !n || max_out < 0 || (max_out > 0 && !out))
+    return fail(PRIEST_ERR_INVALID, "problem and n are required");
+  const std::vector<TileCfg> c = tile_candidates(p->desc.dims);
+  *n = static_cast<int32_t>(c.size());
+  for (int32_t i = 0; i < max_out && i < *n; ++i)
+    out[i] = priest_tiling{c[i].axis_slots, c[i].row_tiles, c[i].persistent, 0};
+  return PRIEST_OK;
+}
+
+int32_t priest_set_tiling(priest_problem* p, const priest_tiling* t) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  std::lock_guard<std::mutex> lk(p->tune_mu);
+  if (!t) {
+    p->forced = false;
+    return PRIEST_OK;
+  }
+  if (!tiling_valid(p->desc.dims, t->axis_slots, t->row_tiles) ||
+      (t->persistent != 0 && t->persistent != 1) || t->reserved != 0)
+    return fail(PRIEST_ERR_INVALID, "tiling (%d, %d, %d) is not a candidate for dims %d",
+                t->axis_slots, t->row_tiles, t->persistent, p->desc.dims);
+  p->forced = true;
+  p->force_cfg = TileCfg{t->axis_slots, t->row_tiles, t->persistent};
+  return PRIEST_OK;
+}
+
+int32_t priest_last_tiling(const priest_problem* p, priest_tiling* out, int32_t* tuned) {
+  if (!p || !out) return fail(PRIEST_ERR_INVALID, "problem and out are required");
+  std::lock_guard<std::mutex> lk(const_cast<priest_problem*>(p)->tune_mu);
+  *out = priest_tiling{p->last_cfg.axis_slots, p->last_cfg.row_tiles, p->last_cfg.persistent, 0};
+  if (tuned) *tuned = p->last_tuned;
+  return PRIEST_OK;
 }
 
 int32_t priest_debug_offsets(priest_problem* p, const float* bc, const float* obs,

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/priest.h"
 
@@ -21,14 +22,16 @@ enum SampleMode : int32_t {
 };
 
 // Arguments of the fused projection kernel.  One launch covers
-// n_problems * blocks_per_problem blocks; block b works on problem
+// n_problems * blocks_per_problem tiles; tile b works on problem
 // b / blocks_per_problem, samples [tile*S, tile*S + S) of it.
 struct ProjArgs {
   int32_t dims, nv, K, M, N;
-  int32_t S;                   // samples per block
+  int32_t S;                   // samples per block = 16 / axis_slots
   int32_t n_iter;              // projection iterations
-  int32_t blocks_per_problem;
-  int32_t G;                   // time-groups of the right-hand-side reduction
+  int32_t blocks_per_problem;  // ceil(N / S)
+  int32_t axis_slots;          // MFMA columns per sample: 4, or 2 (2D only)
+  int32_t row_tiles;           // 16-step time blocks per wave: 1 or 2
+  int32_t persistent;          // 1: grid of resident blocks looping over tiles
   int32_t mode;                // SampleMode
   int32_t bf16_iters;          // leading iterations with BF16 MFMA operands (mixed precision)
   int32_t iter;                // CEM iteration (Philox counter word 2)
@@ -90,7 +93,10 @@ struct CemTaskLaunch {
 hipError_t launch_project_tasks(const ProjTaskLaunch& t, hipStream_t s);
 hipError_t launch_cem_tasks(const CemTaskLaunch& t, hipStream_t s);
 size_t project_lds_bytes(const ProjArgs& a);
-int project_pick_tile(int dims, int nv, int K, int M, int N, int n_problems, int* S, int* G);
+bool tiling_valid(int dims, int axis_slots, int row_tiles);
+int samples_per_block(int axis_slots);
+int project_threads(int K, int row_tiles);
+void set_default_tiling(ProjArgs& a);  // 4 axis slots, 1 time block per wave, not persistent
 hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s);
 size_t cem_lds_bytes(int N, int D, int n_elite);
 hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s);
@@ -100,6 +106,18 @@ hipError_t launch_kkt(const double* Q, const double* A, int nv, int E, const int
 hipError_t launch_debug_offsets(const ProjArgs& a, const float* xi, float* out, hipStream_t s);
 hipError_t launch_debug_normals(uint64_t seed, uint32_t stream_id, int iter, int N, int D,
                                 float* z, hipStream_t s);
+
+// Tile shape of the projection kernel (tune.hip)
+struct TileCfg {
+  int axis_slots, row_tiles, persistent;
+};
+std::vector<TileCfg> tile_candidates(int dims);  // [0] is the default shape
+void apply_tiling(ProjArgs& a, const TileCfg& t);
+// Times every candidate on `trial` (whose outputs must be safe to overwrite);
+// ms[i] < 0 marks a candidate that does not fit.  Synchronises s.
+hipError_t time_tilings(const ProjArgs& trial, int n_problems, size_t lds_limit, hipStream_t s,
+                        const std::vector<TileCfg>& cands, std::vector<float>* ms);
+int pick_tiling(const std::vector<float>& ms);
 
 // api.hip services used by the serving runtime
 #define PRIEST_HIDDEN __attribute__((visibility("hidden")))

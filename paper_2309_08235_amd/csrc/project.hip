@@ -1,25 +1,27 @@
 // Fused projection sweep for gfx950 (MFMA + VALU, state in registers).
 //
-// Work decomposition.  A block owns 4 samples of one problem for the whole
-// projection and has one 64-lane wave per 16-step time block (K <= 256, so at
-// most 16 waves).  Sample coefficients live in registers in the layout of the
-// 16x16 FP32 MFMA accumulator: column col = 4*sample + axis (axes padded to
-// 4), row = coefficient (padded to 16), lane l holding rows 4*(l/16)..+3 of
-// column l%16.  Per projection iteration (Appendix, eqs. (15a)-(15g), with
-// the per-sample batching of Sec. III-A):
+// Work decomposition.  A block owns SPB samples of one problem for the whole
+// projection and has one 64-lane wave per RT consecutive 16-step time blocks
+// (K <= 256).  Sample coefficients live in registers in the layout of the
+// 16x16 FP32 MFMA accumulator: column col = AS*sample + axis (AS axis slots
+// per sample: 4, or 2 for 2D so that 8 samples share the 16 columns), row =
+// coefficient (padded to 16), lane l holding rows 4*(l/16)..+3 of column
+// l%16.  Per projection iteration (Appendix, eqs. (15a)-(15g), with the
+// per-sample batching of Sec. III-A):
 //
-//   forward   p, v, a rows of this wave's time block = W xi_bar
-//             (3 chains of 4 MFMA 16x16x4, W = [P; Pdot; Pddot] rows as A)
-//   transpose quad-local 4x4 transpose through LDS: lane l now holds every
-//             axis of one (sample, t) item, t = t0 + 4*(l/16) + l%4
+//   forward   p, v, a rows of each of the wave's time blocks = W xi_bar
+//             (3 chains of 4 MFMA 16x16x4 per block, W = [P; Pdot; Pddot]
+//             rows as A)
+//   transpose quad-local transpose through LDS: each lane then holds every
+//             axis of 4/AS (sample, t) items per time block
 //   push-out  closed-form alpha/beta/d of each obstacle as a push-out
 //             Delta * max(0, 1/n - 1) (n = scaled distance), summed over the
 //             obstacles that survive a wave-level bounding-box cull;
 //             velocity / acceleration push-outs w * min(0, w_max/|w| - 1)
 //   transpose back to the column layout
-//   RHS       g_partial = W^T delta for this time block (MFMA, the sum over t
-//             is the MFMA reduction); partials of all waves summed through
-//             LDS in fixed order (one barrier)
+//   RHS       g_partial = W^T delta per 16-step block (MFMA, the sum over t
+//             is the MFMA reduction); the partials of all blocks summed
+//             through LDS in one fixed pairwise order (one barrier)
 //   update    lambda += rho g (eq. (15e)); QP of eq. (15g) through the fixed
 //             KKT block, redone identically by every wave (MFMA):
 //               k = 0 : xi_bar = Pi xi + c0 + M11 (lambda + rho g)
@@ -29,8 +31,16 @@
 //             n_obs |p| against rho F^T F xi_bar in FP32.
 //
 // After the last iteration one more forward + push-out pass evaluates
-// r(xi_bar) and c1 = sum_t |a_t|^2, summed per sample in fixed order.
+// r(xi_bar) and c1 = sum_t |a_t|^2, summed per sample in fixed t order.
+//
+// Tile shapes (AS, RT) and the persistent grid change only which lanes and
+// blocks do the work: every sample goes through the same operations in the
+// same order (per-column MFMA, per-16-step partials in one pairwise tree,
+// culled obstacles contribute exact zeros), so every shape gives bit-identical
+// results and the autotuner may pick any of them.
 #include "priest_internal.h"
+
+#include <mutex>
 
 // Phase markers inside a projection iteration (no-ops unless a profiling
 // build defines them).
@@ -44,9 +54,6 @@ namespace {
 using f4 = __attribute__((ext_vector_type(4))) float;
 
 __host__ __device__ inline int round4(int n) { return (n + 3) & ~3; }
-
-// obstacle records: three float4 per obstacle
-__host__ __device__ inline int records_capacity(int M) { return M; }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
@@ -86,22 +93,24 @@ struct Layout {  // offsets into dynamic LDS, in floats
   int rec, xt, gp, fin, mu, L, z, xs, total;
 };
 
-// rec: obstacle records (12 floats each); xt: per-wave transpose buffers;
-// gp: double-buffered per-wave partial right-hand sides; fin: per-item
-// residual^2 and c1 of the final pass; mu/L/z/xs: sampler staging.
-__host__ __device__ inline Layout layout(int dims, int nv, int M, int TW, int mode) {
+// rec: obstacle records (12 floats each); xt: per-wave transpose buffers (768
+// floats per 16-step block); gp: double-buffered partial right-hand sides
+// (256 per block); fin: per-(t, sample) residual^2 and c1 of the final pass;
+// xs: the block's samples; mu/L/z: sampler staging.  NB = 16-step blocks of
+// the launch, SPB = samples per block.
+__host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SPB, int mode) {
   Layout l{};
-  const int D = dims * nv;
+  const int D = dims * nv, D4 = round4(D);
   int o = 0;
-  l.rec = o; o += 12 * records_capacity(M);
-  l.xt = o;  o += TW * 3 * 256;
-  l.gp = o;  o += 2 * TW * 256;
-  l.fin = o; o += TW * 128;
-  l.xs = o;  o += 4 * round4(D);
+  l.rec = o; o += 12 * M;
+  l.xt = o;  o += NB * 768;
+  l.gp = o;  o += 2 * NB * 256;
+  l.fin = o; o += 2 * 16 * NB * SPB;
+  l.xs = o;  o += SPB * D4;
   l.mu = o;
-  l.L = o + round4(D);
-  l.z = o + round4(D) + round4(D * D);
-  if (mode != kFromInput) o += round4(D) + round4(D * D) + 4 * round4(D);
+  l.L = o + D4;
+  l.z = o + D4 + round4(D * D);
+  if (mode != kFromInput) o += D4 + round4(D * D) + SPB * D4;
   l.total = o;
   return l;
 }
@@ -263,18 +272,26 @@ __device__ void build_records(const float* obs, int M, int t, int nt, float4* re
   }
 }
 
-// Obstacle push-outs of this lane's item, summed over obstacles, with
+// Obstacle push-outs of this lane's NI items, summed over obstacles, with
 // wave-level culling.  tmid / thalf: centre and half-width of the wave's time
-// window.
-template <int DIMS, bool LAST>
-__device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, float tt, float tmid,
-                                                float thalf, bool ok, const float p[DIMS],
-                                                float S[DIMS], float& r2, int lane) {
+// window.  The items of a lane are independent, so their pair updates
+// interleave.
+template <int DIMS, bool LAST, int NI>
+__device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const float tt[NI],
+                                                float tmid, float thalf, const bool ok[NI],
+                                                const float p[NI][DIMS], float S[NI][DIMS],
+                                                float r2[NI], int lane) {
   float lo[DIMS], hi[DIMS];
 #pragma unroll
   for (int x = 0; x < DIMS; ++x) {
-    lo[x] = wave_min(ok ? p[x] : INFINITY);
-    hi[x] = wave_max(ok ? p[x] : -INFINITY);
+    float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      mn = fminf(mn, ok[i] ? p[i][x] : INFINITY);
+      mx = fmaxf(mx, ok[i] ? p[i][x] : -INFINITY);
+    }
+    lo[x] = wave_min(mn);
+    hi[x] = wave_max(mx);
   }
   PRIEST_PROJ_MARK(6);
   for (int base = 0; base < M; base += 64) {
@@ -301,124 +318,100 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, float 
     while (mask) {
       const int b = __builtin_ctzll(mask);
       mask &= mask - 1;
-      if ((moving >> b) & 1ull) {
-        const Rec o = rec_from_lane<DIMS>(R0, R1, R2, b, true);
-        const bool zero = pair_push<DIMS, LAST>(o, tt, p, S, r2);
-        if (__ballot(zero && ok))
-          if (zero) zero_push<DIMS, LAST>(o, S, r2);
-      } else {
-        const Rec o = rec_from_lane<DIMS>(R0, R1, R2, b, false);
-        const bool zero = pair_push<DIMS, LAST>(o, tt, p, S, r2);
-        if (__ballot(zero && ok))
-          if (zero) zero_push<DIMS, LAST>(o, S, r2);
-      }
+      // static and moving obstacles take separate copies of the pair code
+      auto pairs = [&](const Rec& o) {
+        bool zero[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) zero[i] = pair_push<DIMS, LAST>(o, tt[i], p[i], S[i], r2[i]);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+          if (__ballot(zero[i] && ok[i]))
+            if (zero[i]) zero_push<DIMS, LAST>(o, S[i], r2[i]);
+      };
+      if ((moving >> b) & 1ull) pairs(rec_from_lane<DIMS>(R0, R1, R2, b, true));
+      else pairs(rec_from_lane<DIMS>(R0, R1, R2, b, false));
     }
   }
-  if (!ok) {
 #pragma unroll
-    for (int x = 0; x < DIMS; ++x) S[x] = 0.0f;
-    r2 = 0.0f;
-  }
+  for (int i = 0; i < NI; ++i)
+    if (!ok[i]) {
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) S[i][x] = 0.0f;
+      r2[i] = 0.0f;
+    }
 }
 
-template <int DIMS, bool LAST>
-__device__ __forceinline__ void item_push(const float4* rec, int M, float tt, float tmid,
-                                          float thalf, bool ok, const float p[DIMS],
-                                          const float v[DIMS], const float ac[DIMS], float vmax,
-                                          float amax, float S[DIMS], float dv[DIMS],
-                                          float da[DIMS], float& r2, int lane) {
+template <int DIMS, bool LAST, int NI>
+__device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI], float tmid,
+                                          float thalf, const bool ok[NI], const float p[NI][DIMS],
+                                          const float v[NI][DIMS], const float ac[NI][DIMS],
+                                          float vmax, float amax, float S[NI][DIMS],
+                                          float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
+                                          int lane) {
 #pragma unroll
-  for (int x = 0; x < DIMS; ++x) { S[x] = 0.0f; dv[x] = 0.0f; da[x] = 0.0f; }
-  r2 = 0.0f;
-  obstacle_pushes<DIMS, LAST>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane);
-  if (ok) {
-    r2 += bound_push<DIMS>(v, vmax, dv);
-    r2 += bound_push<DIMS>(ac, amax, da);
+  for (int i = 0; i < NI; ++i) {
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) { S[i][x] = 0.0f; dv[i][x] = 0.0f; da[i][x] = 0.0f; }
+    r2[i] = 0.0f;
   }
+  obstacle_pushes<DIMS, LAST, NI>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane);
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+    if (ok[i]) {
+      r2[i] += bound_push<DIMS>(v[i], vmax, dv[i]);
+      r2[i] += bound_push<DIMS>(ac[i], amax, da[i]);
+    }
 }
 
-// One block's work: samples [4*tile, 4*tile + 4) of problem `prob` of `a`
-// for the whole projection.  Shared by the uniform-batch kernel and the
-// descriptor-table kernel of the serving path.
-template <int DIMS, int MAXT, bool BF16>
-__device__ __forceinline__ void project_block(const ProjArgs& a, int prob, int tile) {
+// One block's work: whole projections of tiles first, first + stride, ...
+// below `total` (LOOP), or of tile `first` only; tile t holds samples
+// [SPB*j, SPB*j + SPB) of problem t / blocks_per_problem, j its index within
+// the problem.  The problem constants (W rows, M11, Pi) are loaded once per
+// block.  AS: MFMA column slots per sample (4, or 2 in 2D); RT: 16-step time
+// blocks per wave; MAXT: the launch bound.
+template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP>
+__device__ __forceinline__ void project_block(const ProjArgs& a, int first, int stride, int total) {
+  static_assert(AS == 4 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
+  constexpr int SPB = 16 / AS;           // samples per block
+  constexpr int IPR = 4 / AS;            // items per lane per time block
+  constexpr int NI = RT * IPR;           // items per lane
+  constexpr int MB = (MAXT / 64) * RT;   // 16-step block slots (power of two)
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, TW = blockDim.x >> 6;
-  const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv;
-  const Layout l = layout(DIMS, nv, M, TW, a.mode);
-  const int s0 = tile * 4;
-  const int ns = min(4, a.N - s0);
-  // MFMA column layout: q = row group, col = 4*cs + cx
-  const int q = lane >> 4, col = lane & 15, cs = col >> 2, cx = col & 3;
-  // item layout after the transpose: sample cs, timestep t0 + 4q + ia
-  const int ia = lane & 3;
-  const int t0 = 16 * w;
-  const int t_item = t0 + 4 * q + ia;
-  const bool item_ok = (t_item < K) && (cs < ns);
-  const float tt = a.dt * static_cast<float>(t_item);
-  const float tmid = a.dt * (static_cast<float>(t0) + 7.5f);
-  const float thalf = a.dt * 7.5f;
+  const int NB = TW * RT;
+  const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv, D4 = round4(D);
+  const Layout l = layout(DIMS, nv, M, NB, SPB, a.mode);
+  // MFMA column layout: q = row group, col = AS*cs + cx
+  const int q = lane >> 4, col = lane & 15, cs = col / AS, cx = col % AS;
+  // items after the transpose: sample cs, step t0 + 16 rt + 4q + IPR cx + i
+  const int t0 = 16 * RT * w;
+  float tt[NI];
+  int t_item[NI];
+#pragma unroll
+  for (int n = 0; n < NI; ++n) {
+    t_item[n] = t0 + 16 * (n / IPR) + 4 * q + IPR * cx + (n % IPR);
+    tt[n] = a.dt * static_cast<float>(t_item[n]);
+  }
+  const float thalf = a.dt * (8.0f * RT - 0.5f);
+  const float tmid = a.dt * (static_cast<float>(t0) + (8.0f * RT - 0.5f));
 
   float4* rec = reinterpret_cast<float4*>(sm + l.rec);
   float* xs = sm + l.xs;
 
-  // ---- scene records, samples ---------------------------------------------
-  build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
-  if (a.mode == kFromInput) {
-    const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(s0) * D;
-    for (int i = tid; i < ns * D; i += blockDim.x) xs[(i / D) * round4(D) + i % D] = src[i];
-  } else {
-    float* sMu = sm + l.mu;
-    float* sL = sm + l.L;
-    float* sZ = sm + l.z;
-    const int D4 = round4(D);
-    const float* mu = a.mu + prob * a.mu_stride;
-    const float* Lm = a.L + prob * a.L_stride;
-    for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
-    for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
-    if (a.mode == kFromNoise) {
-      const float* z = a.noise + prob * a.noise_stride + static_cast<int64_t>(s0) * D;
-      for (int i = tid; i < ns * D; i += blockDim.x) sZ[(i / D) * D4 + i % D] = z[i];
-    } else {
-      const int nq = D4 / 4;
-      const uint32_t stream = a.stream_base + static_cast<uint32_t>(prob);
-      for (int i = tid; i < ns * nq; i += blockDim.x) {
-        const int s = i / nq, qq = i - s * nq;
-        float z[4];
-        philox_normals4(a.seed, static_cast<uint32_t>(s0 + s), static_cast<uint32_t>(qq),
-                        static_cast<uint32_t>(a.iter), stream, z);
-        *reinterpret_cast<float4*>(sZ + s * D4 + 4 * qq) = make_float4(z[0], z[1], z[2], z[3]);
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < ns * D; i += blockDim.x) {
-      const int s = i / D, d = i - s * D;
-      const float* zz = sZ + s * D4;
-      const float* Lr = sL + d * D;
-      float x = sMu[d];
-      for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
-      xs[s * D4 + d] = x;
-    }
-    __syncthreads();
-    if (a.xi_src) {
-      float* dst = a.xi_src + prob * a.xi_src_stride + static_cast<int64_t>(s0) * D;
-      for (int i = tid; i < ns * D; i += blockDim.x) dst[i] = xs[(i / D) * D4 + i % D];
-    }
-  }
-  __syncthreads();
-
   // ---- per-lane MFMA operands and sample state -------------------------------
-  float Af[3][4], Ab[3][4], Am[4], Ap[4];
+  float Af[RT][3][4], Ab[RT][3][4], Am[4], Ap[4];
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int tf = t0 + col, cf = 4 * q + r;
-      Af[d][r] = (tf < K && cf < nv) ? a.W[(tf * 3 + d) * nv + cf] : 0.0f;
-      const int tb = t0 + 4 * q + r;
-      Ab[d][r] = (tb < K && col < nv) ? a.W[(tb * 3 + d) * nv + col] : 0.0f;
-    }
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tf = t0 + 16 * rt + col, cf = 4 * q + r;
+        Af[rt][d][r] = (tf < K && cf < nv) ? a.W[(tf * 3 + d) * nv + cf] : 0.0f;
+        const int tb = t0 + 16 * rt + 4 * q + r;
+        Ab[rt][d][r] = (tb < K && col < nv) ? a.W[(tb * 3 + d) * nv + col] : 0.0f;
+      }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int cr = 4 * q + r;
@@ -426,204 +419,320 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int prob, int t
     Am[r] = ok ? a.M11[col * nv + cr] : 0.0f;
     Ap[r] = ok ? a.Pi[col * nv + cr] : 0.0f;
   }
-  const bool colok = (cx < DIMS) && (cs < ns);
-  const float* bc = a.bc + prob * a.bc_stride;
-  f4 xi, c0v;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int c = 4 * q + r;
-    const bool ok = colok && (c < nv);
-    xi[r] = ok ? xs[cs * round4(D) + cx * nv + c] : 0.0f;
-    float s = 0.0f;
-    if (ok)
-      for (int i = 0; i < 6; ++i) s = fmaf(a.M12[c * 6 + i], bc[cx * 6 + i], s);
-    c0v[r] = s;
-  }
-  f4 xb = xi;
-  f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
   const float rho = a.rho;
+  f4 xb;
   // mixed precision: W^T rows as BF16, M11 as a BF16 hi/lo pair
-  s4 Abf[3], Mhi, Mlo;
+  s4 Abf[RT][3], Mhi, Mlo;
   if constexpr (BF16) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) Abf[d] = pack_bf16(Ab[d][0], Ab[d][1], Ab[d][2], Ab[d][3]);
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        Abf[rt][d] = pack_bf16(Ab[rt][d][0], Ab[rt][d][1], Ab[rt][d][2], Ab[rt][d][3]);
     Mhi = pack_bf16(Am[0], Am[1], Am[2], Am[3]);
     Mlo = pack_bf16(Am[0] - from_bf16(Mhi[0]), Am[1] - from_bf16(Mhi[1]),
                     Am[2] - from_bf16(Mhi[2]), Am[3] - from_bf16(Mhi[3]));
   }
-  float* xt = sm + l.xt + w * 768;
+  float* xt = sm + l.xt + w * RT * 768;
 
-  // Forward rows of this wave's time block, transposed to the item layout.
-  auto forward = [&](float p[DIMS], float v[DIMS], float ac[DIMS]) {
-    // two independent depth-2 chains per row type, summed
+  // Forward rows of this wave's time blocks, transposed to the item layout.
+  auto forward = [&](float p[NI][DIMS], float v[NI][DIMS], float ac[NI][DIMS]) {
     const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    const f4 Y0 = mfma(Af[0][1], xb[1], mfma(Af[0][0], xb[0], z)) +
-                  mfma(Af[0][3], xb[3], mfma(Af[0][2], xb[2], z));
-    const f4 Y1 = mfma(Af[1][1], xb[1], mfma(Af[1][0], xb[0], z)) +
-                  mfma(Af[1][3], xb[3], mfma(Af[1][2], xb[2], z));
-    const f4 Y2 = mfma(Af[2][1], xb[1], mfma(Af[2][0], xb[0], z)) +
-                  mfma(Af[2][3], xb[3], mfma(Af[2][2], xb[2], z));
-    *reinterpret_cast<f4*>(xt + lane * 4) = Y0;
-    *reinterpret_cast<f4*>(xt + 256 + lane * 4) = Y1;
-    *reinterpret_cast<f4*>(xt + 512 + lane * 4) = Y2;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      // two independent depth-2 chains per row type, summed
+      const f4 Y0 = mfma(Af[rt][0][1], xb[1], mfma(Af[rt][0][0], xb[0], z)) +
+                    mfma(Af[rt][0][3], xb[3], mfma(Af[rt][0][2], xb[2], z));
+      const f4 Y1 = mfma(Af[rt][1][1], xb[1], mfma(Af[rt][1][0], xb[0], z)) +
+                    mfma(Af[rt][1][3], xb[3], mfma(Af[rt][1][2], xb[2], z));
+      const f4 Y2 = mfma(Af[rt][2][1], xb[1], mfma(Af[rt][2][0], xb[0], z)) +
+                    mfma(Af[rt][2][3], xb[3], mfma(Af[rt][2][2], xb[2], z));
+      float* x0 = xt + rt * 768;
+      *reinterpret_cast<f4*>(x0 + lane * 4) = Y0;
+      *reinterpret_cast<f4*>(x0 + 256 + lane * 4) = Y1;
+      *reinterpret_cast<f4*>(x0 + 512 + lane * 4) = Y2;
+    }
     wave_lds_sync();
 #pragma unroll
-    for (int x = 0; x < DIMS; ++x) {
-      const int src = (lane - ia + x) * 4 + ia;
-      p[x] = xt[src];
-      v[x] = xt[256 + src];
-      ac[x] = xt[512 + src];
-    }
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < IPR; ++i)
+#pragma unroll
+        for (int x = 0; x < DIMS; ++x) {
+          const int src = rt * 768 + (lane - cx + x) * 4 + IPR * cx + i;
+          p[rt * IPR + i][x] = xt[src];
+          v[rt * IPR + i][x] = xt[256 + src];
+          ac[rt * IPR + i][x] = xt[512 + src];
+        }
     wave_lds_sync();
   };
 
-  // ---- projection iterations ---------------------------------------------------
-  for (int k = 0; k < a.n_iter; ++k) {
-    PRIEST_PROJ_MARK(0);
-    float p[DIMS], v[DIMS], ac[DIMS];
-    forward(p, v, ac);
-    PRIEST_PROJ_MARK(1);
-    float S[DIMS], dv[DIMS], da[DIMS], r2;
-    item_push<DIMS, false>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv, da,
-                           r2, lane);
-    PRIEST_PROJ_MARK(2);
-    // back to the column layout
-    f4 T0 = {0.0f, 0.0f, 0.0f, 0.0f}, T1 = T0, T2 = T0;
+  int cur_prob = -1;
+  auto tile_body = [&](int t) {
+    const int prob = t / a.blocks_per_problem;
+    const int s0 = (t - prob * a.blocks_per_problem) * SPB;
+    const int ns = min(SPB, a.N - s0);
+    bool item_ok[NI];
 #pragma unroll
-    for (int x = 0; x < DIMS; ++x) { T0[x] = S[x]; T1[x] = dv[x]; T2[x] = da[x]; }
-    *reinterpret_cast<f4*>(xt + lane * 4) = T0;
-    *reinterpret_cast<f4*>(xt + 256 + lane * 4) = T1;
-    *reinterpret_cast<f4*>(xt + 512 + lane * 4) = T2;
-    wave_lds_sync();
-    float B[3][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int src = (lane - cx + r) * 4 + cx;
-      B[0][r] = xt[src];
-      B[1][r] = xt[256 + src];
-      B[2][r] = xt[512 + src];
-    }
-    const f4 zb = {0.0f, 0.0f, 0.0f, 0.0f};
-    const bool lowp = BF16 && (k < a.bf16_iters);
-    if (lowp) {
-      // right-hand side with BF16 operands, FP32 accumulation: one K = 16
-      // MFMA per row type covers the whole 16-step time block
-      const f4 g = mfma_bf16(Abf[0], pack_bf16(B[0][0], B[0][1], B[0][2], B[0][3]), zb) +
-                   mfma_bf16(Abf[1], pack_bf16(B[1][0], B[1][1], B[1][2], B[1][3]), zb) +
-                   mfma_bf16(Abf[2], pack_bf16(B[2][0], B[2][1], B[2][2], B[2][3]), zb);
-      float* gpl = sm + l.gp + (k & 1) * TW * 256;
-      *reinterpret_cast<f4*>(gpl + w * 256 + lane * 4) = g;
-    }
-    f4 G0 = mfma(Ab[0][1], B[0][1], mfma(Ab[0][0], B[0][0], zb));
-    f4 G1 = mfma(Ab[0][3], B[0][3], mfma(Ab[0][2], B[0][2], zb));
-    f4 G2 = mfma(Ab[1][1], B[1][1], mfma(Ab[1][0], B[1][0], zb));
-    G0 = mfma(Ab[1][3], B[1][3], mfma(Ab[1][2], B[1][2], G0));
-    G1 = mfma(Ab[2][1], B[2][1], mfma(Ab[2][0], B[2][0], G1));
-    G2 = mfma(Ab[2][3], B[2][3], mfma(Ab[2][2], B[2][2], G2));
-    // issue all six LDS reads before the twelve MFMAs that consume them
-    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
-    PRIEST_PROJ_MARK(3);
-    float* gp = sm + l.gp + (k & 1) * TW * 256;
-    if (!lowp) *reinterpret_cast<f4*>(gp + w * 256 + lane * 4) = G0 + G1 + G2;
-    __syncthreads();
-    // all partials loaded before any is used; slots past TW read slot TW-1
-    // and are replaced by zero; fixed summation order in every wave
-    constexpr int MW = MAXT / 64;
-    f4 part[MW];
-#pragma unroll
-    for (int ww = 0; ww < MW; ++ww)
-      part[ww] = *reinterpret_cast<const f4*>(gp + min(ww, TW - 1) * 256 + lane * 4);
-    const f4 zg = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int ww = 1; ww < MW; ++ww) part[ww] = (ww < TW) ? part[ww] : zg;
-#pragma unroll
-    for (int step = 1; step < MW; step *= 2)
-#pragma unroll
-      for (int ww = 0; ww + step < MW; ww += 2 * step) part[ww] += part[ww + step];
-    const f4 g = part[0];
-    PRIEST_PROJ_MARK(4);
-    lam += rho * g;
-    const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (k == 0) {
-      const f4 u = lam + rho * g;
-      const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
-      const f4 h1 = mfma(Ap[3], xi[3], mfma(Ap[2], xi[2], z));
-      const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
-      const f4 h3 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
-      xb = (h0 + h1) + (h2 + h3);
-    } else if (lowp) {
-      // KKT product with BF16 hi/lo splits of M11 and u (three K = 16 MFMAs)
-      const f4 u = (xi - xb) + lam + rho * g;
-      const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
-      const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
-                              u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
-      xb = xb + (mfma_bf16(Mhi, uh, z) + (mfma_bf16(Mhi, ul, z) + mfma_bf16(Mlo, uh, z)));
+    for (int n = 0; n < NI; ++n) item_ok[n] = (t_item[n] < K) && (cs < ns);
+    // ---- scene records, samples ---------------------------------------------
+    // (every reader of the previous tile's records passed the barrier that
+    // precedes its epilogue)
+    if (prob != cur_prob) build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
+    cur_prob = prob;
+    if (a.mode == kFromInput) {
+      const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(s0) * D;
+      for (int i = tid; i < ns * D; i += blockDim.x) xs[(i / D) * D4 + i % D] = src[i];
     } else {
-      const f4 u = (xi - xb) + lam + rho * g;
-      const f4 h0 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
-      const f4 h1 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
-      xb = xb + (h0 + h1);
-    }
-    PRIEST_PROJ_MARK(5);
-  }
-
-  // ---- residual and smoothness cost of the returned iterate -----------------------
-  {
-    float p[DIMS], v[DIMS], ac[DIMS];
-    forward(p, v, ac);
-    float S[DIMS], dv[DIMS], da[DIMS], r2;
-    item_push<DIMS, true>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv, da,
-                          r2, lane);
-    float cc = 0.0f;
-#pragma unroll
-    for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[x], ac[x], cc);
-    float* fin = sm + l.fin + w * 128;
-    fin[2 * lane] = item_ok ? r2 : 0.0f;
-    fin[2 * lane + 1] = item_ok ? cc : 0.0f;
-  }
-  __syncthreads();
-  if (tid < ns) {
-    const int s = tid;
-    float r2 = 0.0f, cc = 0.0f;
-    for (int t = 0; t < K; ++t) {
-      const int ww = t >> 4, qq = (t >> 2) & 3, aa = t & 3;
-      const float* f = sm + l.fin + ww * 128 + 2 * (qq * 16 + s * 4 + aa);
-      r2 += f[0];
-      cc += f[1];
-    }
-    const float r = sqrtf(r2);
-    const int64_t nb = prob * a.n_stride + s0 + s;
-    const int64_t dense = static_cast<int64_t>(prob) * a.N + s0 + s;
-    if (a.resid) a.resid[nb] = r;
-    if (a.c1) a.c1[nb] = cc;
-    if (a.resid2) a.resid2[dense] = r;
-    if (a.c12) a.c12[dense] = cc;
-  }
-  if (w == 0 && colok) {
-    float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0 + cs) * D + cx * nv;
-    float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0 + cs) * D + cx * nv
-                            : nullptr;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = 4 * q + r;
-      if (c < nv) {
-        dst[c] = xb[r];
-        if (dst2) dst2[c] = xb[r];
+      float* sMu = sm + l.mu;
+      float* sL = sm + l.L;
+      float* sZ = sm + l.z;
+      const float* mu = a.mu + prob * a.mu_stride;
+      const float* Lm = a.L + prob * a.L_stride;
+      for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
+      for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
+      if (a.mode == kFromNoise) {
+        const float* z = a.noise + prob * a.noise_stride + static_cast<int64_t>(s0) * D;
+        for (int i = tid; i < ns * D; i += blockDim.x) sZ[(i / D) * D4 + i % D] = z[i];
+      } else {
+        const int nq = D4 / 4;
+        const uint32_t stream = a.stream_base + static_cast<uint32_t>(prob);
+        for (int i = tid; i < ns * nq; i += blockDim.x) {
+          const int s = i / nq, qq = i - s * nq;
+          float z[4];
+          philox_normals4(a.seed, static_cast<uint32_t>(s0 + s), static_cast<uint32_t>(qq),
+                          static_cast<uint32_t>(a.iter), stream, z);
+          *reinterpret_cast<float4*>(sZ + s * D4 + 4 * qq) = make_float4(z[0], z[1], z[2], z[3]);
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < ns * D; i += blockDim.x) {
+        const int s = i / D, d = i - s * D;
+        const float* zz = sZ + s * D4;
+        const float* Lr = sL + d * D;
+        float x = sMu[d];
+        for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
+        xs[s * D4 + d] = x;
+      }
+      __syncthreads();
+      if (a.xi_src) {
+        float* dst = a.xi_src + prob * a.xi_src_stride + static_cast<int64_t>(s0) * D;
+        for (int i = tid; i < ns * D; i += blockDim.x) dst[i] = xs[(i / D) * D4 + i % D];
       }
     }
+    __syncthreads();
+
+    const bool colok = (cx < DIMS) && (cs < ns);
+    const float* bc = a.bc + prob * a.bc_stride;
+    f4 xi, c0v;
+  #pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 4 * q + r;
+      const bool ok = colok && (c < nv);
+      xi[r] = ok ? xs[cs * D4 + cx * nv + c] : 0.0f;
+      float s = 0.0f;
+      if (ok)
+        for (int i = 0; i < 6; ++i) s = fmaf(a.M12[c * 6 + i], bc[cx * 6 + i], s);
+      c0v[r] = s;
+    }
+    xb = xi;
+    f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
+
+    // ---- projection iterations ---------------------------------------------------
+    for (int k = 0; k < a.n_iter; ++k) {
+      PRIEST_PROJ_MARK(0);
+      float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS];
+      forward(p, v, ac);
+      PRIEST_PROJ_MARK(1);
+      float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+      item_push<DIMS, false, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv,
+                                 da, r2, lane);
+      PRIEST_PROJ_MARK(2);
+      // back to the column layout: slot AS*i + x of the lane's f4 holds axis x
+      // of item i
+  #pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        f4 T0 = {0.0f, 0.0f, 0.0f, 0.0f}, T1 = T0, T2 = T0;
+  #pragma unroll
+        for (int i = 0; i < IPR; ++i)
+  #pragma unroll
+          for (int x = 0; x < DIMS; ++x) {
+            T0[AS * i + x] = S[rt * IPR + i][x];
+            T1[AS * i + x] = dv[rt * IPR + i][x];
+            T2[AS * i + x] = da[rt * IPR + i][x];
+          }
+        float* x0 = xt + rt * 768;
+        *reinterpret_cast<f4*>(x0 + lane * 4) = T0;
+        *reinterpret_cast<f4*>(x0 + 256 + lane * 4) = T1;
+        *reinterpret_cast<f4*>(x0 + 512 + lane * 4) = T2;
+      }
+      wave_lds_sync();
+      float B[RT][3][4];
+  #pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int src = rt * 768 + (lane - cx + r / IPR) * 4 + AS * (r % IPR) + cx;
+          B[rt][0][r] = xt[src];
+          B[rt][1][r] = xt[256 + src];
+          B[rt][2][r] = xt[512 + src];
+        }
+      const f4 zb = {0.0f, 0.0f, 0.0f, 0.0f};
+      const bool lowp = BF16 && (k < a.bf16_iters);
+      float* gp = sm + l.gp + (k & 1) * NB * 256;
+      if (lowp) {
+        // right-hand side with BF16 operands, FP32 accumulation: one K = 16
+        // MFMA per row type covers a whole 16-step block
+  #pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const f4 g = mfma_bf16(Abf[rt][0], pack_bf16(B[rt][0][0], B[rt][0][1], B[rt][0][2], B[rt][0][3]), zb) +
+                       mfma_bf16(Abf[rt][1], pack_bf16(B[rt][1][0], B[rt][1][1], B[rt][1][2], B[rt][1][3]), zb) +
+                       mfma_bf16(Abf[rt][2], pack_bf16(B[rt][2][0], B[rt][2][1], B[rt][2][2], B[rt][2][3]), zb);
+          *reinterpret_cast<f4*>(gp + (w * RT + rt) * 256 + lane * 4) = g;
+        }
+      } else {
+        f4 G[RT];
+  #pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          f4 G0 = mfma(Ab[rt][0][1], B[rt][0][1], mfma(Ab[rt][0][0], B[rt][0][0], zb));
+          f4 G1 = mfma(Ab[rt][0][3], B[rt][0][3], mfma(Ab[rt][0][2], B[rt][0][2], zb));
+          f4 G2 = mfma(Ab[rt][1][1], B[rt][1][1], mfma(Ab[rt][1][0], B[rt][1][0], zb));
+          G0 = mfma(Ab[rt][1][3], B[rt][1][3], mfma(Ab[rt][1][2], B[rt][1][2], G0));
+          G1 = mfma(Ab[rt][2][1], B[rt][2][1], mfma(Ab[rt][2][0], B[rt][2][0], G1));
+          G2 = mfma(Ab[rt][2][3], B[rt][2][3], mfma(Ab[rt][2][2], B[rt][2][2], G2));
+          G[rt] = G0 + G1 + G2;
+        }
+        // issue the LDS reads before the MFMAs that consume them
+        __builtin_amdgcn_sched_group_barrier(0x100, 6 * RT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 12 * RT, 0);
+  #pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          *reinterpret_cast<f4*>(gp + (w * RT + rt) * 256 + lane * 4) = G[rt];
+      }
+      PRIEST_PROJ_MARK(3);
+      __syncthreads();
+      // g = sum of the NB block partials, in the pairwise order of a balanced
+      // tree over MB slots (empty slots are zero, which leaves every partial
+      // sum unchanged): a running stack of subtree sums, one level per bit.
+      f4 g;
+      {
+        const f4 zg = {0.0f, 0.0f, 0.0f, 0.0f};
+        f4 lvl[6];
+  #pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          f4 v = zg;
+          if (b < NB) v = *reinterpret_cast<const f4*>(gp + b * 256 + lane * 4);
+  #pragma unroll
+          for (int e = 0; e < 6; ++e) {
+            if ((b >> e) & 1) {
+              v = lvl[e] + v;
+            } else {
+              lvl[e] = v;
+              break;
+            }
+          }
+          if (b == MB - 1) g = v;
+        }
+      }
+      PRIEST_PROJ_MARK(4);
+      lam += rho * g;
+      const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (k == 0) {
+        const f4 u = lam + rho * g;
+        const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
+        const f4 h1 = mfma(Ap[3], xi[3], mfma(Ap[2], xi[2], z));
+        const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
+        const f4 h3 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
+        xb = (h0 + h1) + (h2 + h3);
+      } else if (lowp) {
+        // KKT product with BF16 hi/lo splits of M11 and u (three K = 16 MFMAs)
+        const f4 u = (xi - xb) + lam + rho * g;
+        const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
+        const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
+                                u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
+        xb = xb + (mfma_bf16(Mhi, uh, z) + (mfma_bf16(Mhi, ul, z) + mfma_bf16(Mlo, uh, z)));
+      } else {
+        const f4 u = (xi - xb) + lam + rho * g;
+        const f4 h0 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
+        const f4 h1 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
+        xb = xb + (h0 + h1);
+      }
+      PRIEST_PROJ_MARK(5);
+    }
+
+    // ---- residual and smoothness cost of the returned iterate -----------------------
+    {
+      float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS];
+      forward(p, v, ac);
+      float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+      item_push<DIMS, true, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv,
+                                da, r2, lane);
+      float* fin = sm + l.fin;
+  #pragma unroll
+      for (int n = 0; n < NI; ++n) {
+        float cc = 0.0f;
+  #pragma unroll
+        for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[n][x], ac[n][x], cc);
+        float* f = fin + 2 * (t_item[n] * SPB + cs);
+        f[0] = item_ok[n] ? r2[n] : 0.0f;
+        f[1] = item_ok[n] ? cc : 0.0f;
+      }
+    }
+    __syncthreads();
+    if (tid < ns) {
+      const int s = tid;
+      float r2 = 0.0f, cc = 0.0f;
+      for (int t = 0; t < K; ++t) {
+        const float* f = sm + l.fin + 2 * (t * SPB + s);
+        r2 += f[0];
+        cc += f[1];
+      }
+      const float r = sqrtf(r2);
+      const int64_t nb = prob * a.n_stride + s0 + s;
+      const int64_t dense = static_cast<int64_t>(prob) * a.N + s0 + s;
+      if (a.resid) a.resid[nb] = r;
+      if (a.c1) a.c1[nb] = cc;
+      if (a.resid2) a.resid2[dense] = r;
+      if (a.c12) a.c12[dense] = cc;
+    }
+    if (w == 0 && colok) {
+      float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0 + cs) * D + cx * nv;
+      float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0 + cs) * D + cx * nv
+                              : nullptr;
+  #pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 4 * q + r;
+        if (c < nv) {
+          dst[c] = xb[r];
+          if (dst2) dst2[c] = xb[r];
+        }
+      }
+    }
+  };
+  if constexpr (LOOP) {
+    for (int t = first; t < total; t += stride) tile_body(t);
+  } else {
+    if (first < total) tile_body(first);
   }
 }
 
-// Uniform batch: block b works on problem b / blocks_per_problem.
-template <int DIMS, int MAXT, bool BF16>
-__global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a) {
-  const int prob = blockIdx.x / a.blocks_per_problem;
-  project_block<DIMS, MAXT, BF16>(a, prob, blockIdx.x - prob * a.blocks_per_problem);
+// Uniform batch of `total` tiles (problem = tile / blocks_per_problem).  With
+// a grid smaller than `total` (persistent launch) every block loops over
+// tiles with stride gridDim.x.  When the grid is a multiple of the 8 XCDs,
+// logical block ids are laid out so that each XCD (which receives every 8th
+// hardware block) walks a contiguous range of tiles, keeping a problem's
+// scene in one L2.
+template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP>
+__global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a, int total) {
+  const int G = gridDim.x;
+  int lb = blockIdx.x;
+  if ((G & 7) == 0) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  project_block<DIMS, AS, RT, MAXT, BF16, LOOP>(a, lb, G, total);
 }
 
 // Descriptor table (heterogeneous requests sharing n_steps): task t owns
 // blocks [prefix[t], prefix[t+1]); every field of its ProjArgs is its own.
+// Serving uses the default tile shape (4 axis slots, one time block per wave).
 template <int DIMS, int MAXT, bool BF16>
 __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* tasks,
                                                             const int* prefix, int n_tasks) {
@@ -633,7 +742,8 @@ __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* task
     if (prefix[mid] <= static_cast<int>(blockIdx.x)) lo = mid;
     else hi = mid;
   }
-  project_block<DIMS, MAXT, BF16>(tasks[lo], 0, static_cast<int>(blockIdx.x) - prefix[lo]);
+  project_block<DIMS, 4, 1, MAXT, BF16, false>(tasks[lo], static_cast<int>(blockIdx.x) - prefix[lo], 1,
+                                              tasks[lo].blocks_per_problem);
 }
 
 // Per-row push-outs e(xi) - F xi, [N][M + 2][K][dims] (parity hook): one
@@ -690,51 +800,117 @@ __global__ void normals_kernel(uint64_t seed, uint32_t stream, int iter, int N, 
     if (4 * qq + k < D) z[static_cast<int64_t>(s) * D + 4 * qq + k] = w[k];
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+int waves_for(int K, int RT) { return (K + 16 * RT - 1) / (16 * RT); }
 
-int project_waves(int K) { return (K + 15) / 16; }
+// Resident blocks per CU of one kernel instance for a block size and LDS
+// size, cached (the query is not free and launches repeat).
+struct OccKey {
+  const void* fn;
+  int threads;
+  size_t lds;
+};
 
-size_t project_lds_bytes(const ProjArgs& a) {
-  return sizeof(float) *
-         static_cast<size_t>(layout(a.dims, a.nv, a.M, project_waves(a.K), a.mode).total);
+int resident_blocks(const void* fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static OccKey keys[64];
+  static int vals[64];
+  static int n = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < n; ++i)
+    if (keys[i].fn == fn && keys[i].threads == threads && keys[i].lds == lds) return vals[i];
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  const int v = per_cu * cus;
+  if (n < 64) {
+    keys[n] = OccKey{fn, threads, lds};
+    vals[n] = v;
+    ++n;
+  }
+  return v;
 }
 
-int project_pick_tile(int dims, int nv, int K, int M, int N, int n_problems, int* S, int* G) {
-  (void)dims; (void)nv; (void)K; (void)M; (void)N; (void)n_problems;
-  *S = 4;  // samples per block: 4 samples x 4 axis slots = 16 MFMA columns
-  *G = 1;
-  return 0;
-}
-
-hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
-  const size_t lds = project_lds_bytes(a);
-  const dim3 grid(static_cast<unsigned>(n_problems * a.blocks_per_problem));
-  const dim3 block(64 * project_waves(a.K));
-  // up to 8 waves (K <= 128): a 512-thread bound leaves room for 256 VGPRs
-  const bool bf = a.bf16_iters > 0;
-  if (block.x <= 512) {
-    if (a.dims == 2) {
-      if (bf) hipLaunchKernelGGL((project_kernel<2, 512, true>), grid, block, lds, s, a);
-      else hipLaunchKernelGGL((project_kernel<2, 512, false>), grid, block, lds, s, a);
-    } else {
-      if (bf) hipLaunchKernelGGL((project_kernel<3, 512, true>), grid, block, lds, s, a);
-      else hipLaunchKernelGGL((project_kernel<3, 512, false>), grid, block, lds, s, a);
-    }
+template <int DIMS, int AS, int RT, int MAXT, bool BF16>
+hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s) {
+  if (a.persistent) {
+    const void* fn = reinterpret_cast<const void*>(&project_kernel<DIMS, AS, RT, MAXT, BF16, true>);
+    const int grid = std::min(total, resident_blocks(fn, threads, lds));
+    hipLaunchKernelGGL((project_kernel<DIMS, AS, RT, MAXT, BF16, true>), dim3(grid), dim3(threads),
+                       lds, s, a, total);
   } else {
-    if (a.dims == 2) {
-      if (bf) hipLaunchKernelGGL((project_kernel<2, 1024, true>), grid, block, lds, s, a);
-      else hipLaunchKernelGGL((project_kernel<2, 1024, false>), grid, block, lds, s, a);
-    } else {
-      if (bf) hipLaunchKernelGGL((project_kernel<3, 1024, true>), grid, block, lds, s, a);
-      else hipLaunchKernelGGL((project_kernel<3, 1024, false>), grid, block, lds, s, a);
-    }
+    hipLaunchKernelGGL((project_kernel<DIMS, AS, RT, MAXT, BF16, false>), dim3(total),
+                       dim3(threads), lds, s, a, total);
   }
   return hipGetLastError();
 }
 
+template <int DIMS, bool BF16>
+hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s) {
+  if (a.row_tiles == 2) {
+    if constexpr (DIMS == 2)
+      if (a.axis_slots == 2) return launch_shape<DIMS, 2, 2, 512, BF16>(a, total, threads, lds, s);
+    return launch_shape<DIMS, 4, 2, 512, BF16>(a, total, threads, lds, s);
+  }
+  if (threads <= 512) {
+    if constexpr (DIMS == 2)
+      if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 512, BF16>(a, total, threads, lds, s);
+    return launch_shape<DIMS, 4, 1, 512, BF16>(a, total, threads, lds, s);
+  }
+  if constexpr (DIMS == 2)
+    if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 1024, BF16>(a, total, threads, lds, s);
+  return launch_shape<DIMS, 4, 1, 1024, BF16>(a, total, threads, lds, s);
+}
+
+}  // namespace
+
+bool tiling_valid(int dims, int axis_slots, int row_tiles) {
+  return (axis_slots == 4 || (axis_slots == 2 && dims == 2)) && (row_tiles == 1 || row_tiles == 2);
+}
+
+int samples_per_block(int axis_slots) { return 16 / axis_slots; }
+
+int project_threads(int K, int row_tiles) { return 64 * waves_for(K, row_tiles); }
+
+size_t project_lds_bytes(const ProjArgs& a) {
+  const int NB = waves_for(a.K, a.row_tiles) * a.row_tiles;
+  return sizeof(float) *
+         static_cast<size_t>(layout(a.dims, a.nv, a.M, NB, samples_per_block(a.axis_slots), a.mode).total);
+}
+
+void set_default_tiling(ProjArgs& a) {
+  a.axis_slots = 4;
+  a.row_tiles = 1;
+  a.persistent = 0;
+  a.S = samples_per_block(a.axis_slots);
+}
+
+hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
+  if (!tiling_valid(a.dims, a.axis_slots, a.row_tiles) || a.S != samples_per_block(a.axis_slots) ||
+      a.blocks_per_problem != (a.N + a.S - 1) / a.S)
+    return hipErrorInvalidValue;
+  const size_t lds = project_lds_bytes(a);
+  const int threads = project_threads(a.K, a.row_tiles);
+  const int total = n_problems * a.blocks_per_problem;
+  if (total <= 0) return hipSuccess;
+  const bool bf = a.bf16_iters > 0;
+  if (a.dims == 2) return bf ? launch_dims<2, true>(a, total, threads, lds, s)
+                             : launch_dims<2, false>(a, total, threads, lds, s);
+  return bf ? launch_dims<3, true>(a, total, threads, lds, s)
+            : launch_dims<3, false>(a, total, threads, lds, s);
+}
+
 hipError_t launch_project_tasks(const ProjTaskLaunch& t, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(t.n_blocks));
-  const dim3 block(64 * project_waves(t.K));
+  const dim3 block(project_threads(t.K, 1));
   const size_t lds = t.lds_bytes;
   const bool bf = t.bf16;
   if (block.x <= 512) {

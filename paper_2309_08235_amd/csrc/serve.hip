@@ -206,9 +206,9 @@ int32_t get_problem(priest_server* s, int K, int M, double T, priest_problem** o
   if (st != PRIEST_OK) return st;
   ProjArgs a = problem_args(p);
   a.N = 4;
-  a.S = 4;
-  a.G = 1;
   a.mode = kFromPhilox;
+  set_default_tiling(a);
+  a.blocks_per_problem = 1;
   st = problem_check_lds(p, a);
   if (st != PRIEST_OK) {
     priest_free_problem(p);
@@ -461,7 +461,7 @@ int32_t launch_step(priest_server* s, int slot_index, const std::vector<Req*>& f
       const Req* q = order[i];
       ProjArgs a = problem_args(q->prob);
       a.N = q->r.n_samples;
-      project_pick_tile(a.dims, a.nv, a.K, a.M, a.N, 1, &a.S, &a.G);
+      set_default_tiling(a);  // the descriptor-table kernel's shape
       a.blocks_per_problem = (a.N + a.S - 1) / a.S;
       a.n_iter = q->r.n_proj_iters;
       a.bf16_iters = problem_bf16_iters(q->prob, a.n_iter);

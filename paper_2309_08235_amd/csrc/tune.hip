@@ -1,0 +1,69 @@
+// Autotuner of the projection kernel's tile shape.
+//
+// Candidates differ in how samples map to MFMA columns (4 axis slots per
+// sample, or 2 in 2D so that 8 samples fill the 16 columns), in how many
+// 16-step time blocks one wave carries (1 or 2: more independent items per
+// lane, fewer waves per block), and in the grid (one block per tile, or a
+// persistent grid of resident blocks looping over tiles).  All candidates
+// compute bit-identical results, so the choice only affects time: each
+// candidate runs one warm-up launch and two timed launches of the caller's
+// real arguments (outputs redirected by the caller) with HIP events on the
+// caller's stream, and the fastest one is kept.
+#include <algorithm>
+#include <vector>
+
+#include "priest_internal.h"
+
+namespace priest {
+
+std::vector<TileCfg> tile_candidates(int dims) {
+  std::vector<TileCfg> out;
+  const int slots[2] = {4, 2};
+  for (int rt = 1; rt <= 2; ++rt)
+    for (int s : slots)
+      for (int pers = 0; pers <= 1; ++pers)
+        if (tiling_valid(dims, s, rt)) out.push_back(TileCfg{s, rt, pers});
+  return out;
+}
+
+void apply_tiling(ProjArgs& a, const TileCfg& t) {
+  a.axis_slots = t.axis_slots;
+  a.row_tiles = t.row_tiles;
+  a.persistent = t.persistent;
+  a.S = samples_per_block(t.axis_slots);
+  a.blocks_per_problem = (a.N + a.S - 1) / a.S;
+}
+
+hipError_t time_tilings(const ProjArgs& trial, int n_problems, size_t lds_limit, hipStream_t s,
+                        const std::vector<TileCfg>& cands, std::vector<float>* ms) {
+  ms->assign(cands.size(), -1.0f);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  for (size_t i = 0; i < cands.size() && err == hipSuccess; ++i) {
+    ProjArgs a = trial;
+    apply_tiling(a, cands[i]);
+    if (project_lds_bytes(a) > lds_limit) continue;
+    err = launch_project(a, n_problems, s);  // warm-up (first use of the instance)
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch_project(a, n_problems, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    if (err == hipSuccess) (*ms)[i] = t / 2.0f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return err;
+}
+
+int pick_tiling(const std::vector<float>& ms) {
+  // the default (index 0) unless another candidate is more than 2% faster
+  int best = 0;
+  for (size_t i = 1; i < ms.size(); ++i)
+    if (ms[i] >= 0.0f && (ms[best] < 0.0f || ms[i] < ms[best] * 0.98f)) best = static_cast<int>(i);
+  return best;
+}
+
+}  // namespace priest

@@ -38,6 +38,7 @@ EXPORTS = (
     "priest_server_now", "priest_server_create", "priest_server_prepare", "priest_server_submit",
     "priest_server_step", "priest_server_poll", "priest_server_flush", "priest_server_counts",
     "priest_server_stats_get", "priest_server_robot_state", "priest_server_destroy",
+    "priest_tiling_candidates", "priest_set_tiling", "priest_last_tiling",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -104,6 +105,14 @@ class ServerStats(ctypes.Structure):
         "arena_budget", "arena_high_water", "sample_iters")]
 
 
+class Tiling(ctypes.Structure):
+    _fields_ = [("axis_slots", ctypes.c_int32), ("row_tiles", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.axis_slots, self.row_tiles, self.persistent)
+
+
 class PriestError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"priest status {code}: {msg}")
@@ -140,6 +149,9 @@ _SIGS = {
     "priest_server_stats_get": (_I, [_P, ctypes.POINTER(ServerStats)]),
     "priest_server_robot_state": (_I, [_P, _I, _P, _P]),
     "priest_server_destroy": (_I, [_P]),
+    "priest_tiling_candidates": (_I, [_P, ctypes.POINTER(Tiling), _I, ctypes.POINTER(_I)]),
+    "priest_set_tiling": (_I, [_P, ctypes.POINTER(Tiling)]),
+    "priest_last_tiling": (_I, [_P, ctypes.POINTER(Tiling), ctypes.POINTER(_I)]),
     "priest_last_error": (ctypes.c_char_p, []),
     "priest_version": (_I, []),
 }
@@ -256,6 +268,30 @@ def priest_debug_constants(handle, which: int, count: int):
     return list(buf)
 
 
+def priest_tiling_candidates(handle):
+    n = _I()
+    _check(lib().priest_tiling_candidates(handle, None, 0, ctypes.byref(n)))
+    buf = (Tiling * n.value)()
+    _check(lib().priest_tiling_candidates(handle, buf, n.value, ctypes.byref(n)))
+    return [buf[i].as_tuple() for i in range(n.value)]
+
+
+def priest_set_tiling(handle, tiling=None):
+    """tiling: (axis_slots, row_tiles, persistent) or None for autotuning."""
+    if tiling is None:
+        _check(lib().priest_set_tiling(handle, None))
+    else:
+        t = Tiling(*tiling, 0)
+        _check(lib().priest_set_tiling(handle, ctypes.byref(t)))
+
+
+def priest_last_tiling(handle):
+    t = Tiling()
+    tuned = _I()
+    _check(lib().priest_last_tiling(handle, ctypes.byref(t), ctypes.byref(tuned)))
+    return t.as_tuple(), bool(tuned.value)
+
+
 def priest_server_now() -> float:
     return lib().priest_server_now()
 
@@ -367,6 +403,15 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def tiling_candidates(self):
+        return priest_tiling_candidates(self.handle)
+
+    def set_tiling(self, tiling=None):
+        priest_set_tiling(self.handle, tiling)
+
+    def last_tiling(self):
+        return priest_last_tiling(self.handle)
 
     def project(self, bc, obs, xi, n_iter, stream=None):
         N = xi.shape[0]
