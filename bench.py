@@ -10,12 +10,18 @@ Cholesky) on the GPU.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: the metric is projected samples x iterations per
 second (N * n_proj_iters * n_cem per plan), plus plans/s and per-plan
-latency percentiles, the roofline position of the projection kernel and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+latency percentiles, the roofline position of the projection kernel (its
+launches inside the timed region, timed with HIP events on the plan's
+stream) and the FP64 CPU oracle timed on a bounded sample of the same
+workload.  Extra sections compare the systems patterns with the plain
+one-problem-per-launch FP32 form: batched problems with graph-captured CEM
+loops and autotuned tile shapes (2D x64 and 3D x64), BF16 mixed precision,
+and the continuous-batching server.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,13 +32,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector / MFMA peak
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_kernel_c2_traffic.txt")
+KERNEL_SOURCES = ("paper_2309_08235_amd/csrc/project.hip", "paper_2309_08235_amd/csrc/priest_internal.h")
 
 
 def projection_flops(dims: int, nv: int, K: int, M: int) -> float:
-    """Algorithmic FLOPs of one projection iteration for one sample (lower
-    bound: obstacle pairs counted at their no-contact cost).
+    """Algorithmic FLOPs of one projection iteration for one sample (every
+    obstacle pair counted at its no-contact cost; pairs the kernel skips by
+    culling are still counted).
 
       forward rows p, v, a      : 3 dims nv K FMA        -> 6 dims nv K
       obstacle pair (t, j)      : centre at t (dims FMA), offset (dims),
@@ -44,6 +53,32 @@ def projection_flops(dims: int, nv: int, K: int, M: int) -> float:
     pair = 2 * dims + dims + 2 * dims + 1 + 1
     return (12 * dims * nv * K + pair * K * M + 2 * K * (2 * dims + 2)
             + dims * (5 * nv + 2 * nv * nv))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per projection launch at the headline shape, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/ (null when the
+    kernel sources changed since the counters were taken)."""
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip()
+        if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, n_sample: int, gpu_results=None):
@@ -83,14 +118,24 @@ def cpu_baseline(wl, n_sample: int, gpu_results=None):
             "gpu_error_vs_oracle": errors}
 
 
-def batched_3d(P, W, steps: int, plain_problems: int):
-    """3D batched workload: 64 problems x N=2000 samples, M=128 spheres, K=100,
-    100 projection x 20 CEM iterations.  Batched = every CEM step of all 64
-    problems in one launch, the whole CEM loop captured in a hipGraph and
-    replayed; plain = one problem per launch, no graph (timed on
-    `plain_problems` problems and scaled)."""
+def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note):
+    flops = projection_flops(wl.dims, wl.n_coeff, wl.n_steps, wl.n_obs) * n_samples_per_launch * \
+        wl.n_proj_iters
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "kernel": f"project_kernel<{wl.dims}D, tiling {tuple(tiling)}>",
+            "kernel_ms": round(avg_ms, 4), "launches": launches,
+            "flops_per_launch": flops, "timing": note}
+
+
+def batched(P, W, wl, steps: int, plain_problems: int):
+    """n_problems independent problems of workload `wl`: batched = every CEM
+    step of all problems in one launch, the whole CEM loop captured in a
+    hipGraph and replayed, tile shape from the autotuner; plain = one problem
+    per launch, no graph, default tile shape (timed on `plain_problems`
+    problems and scaled)."""
     import torch
-    wl = W.C3
     dev = "cuda:0"
     prob = P.Problem.from_workload(wl)
     nP = wl.n_problems
@@ -107,22 +152,33 @@ def batched_3d(P, W, steps: int, plain_problems: int):
     ws = prob.workspace(cem, nP)
     s = torch.cuda.Stream()
 
-    def batch_step():
+    def batch_step(graph=True):
         mu.copy_(mu0)
         cov.copy_(cov0)
         prob.plan_batch(nP, bc, obs, cem, mu, cov, seed=77, stream_base=0, out=out, workspace=ws,
-                        use_graph=True, stream=s)
+                        use_graph=graph, stream=s)
 
     with torch.cuda.stream(s):
-        batch_step()                      # capture + first replay
+        batch_step()                      # autotune + capture + first replay
         s.synchronize()
+        tiling = prob.last_tiling()
         t0 = time.perf_counter()
         for _ in range(steps):
             batch_step()
         s.synchronize()
         t_batch = (time.perf_counter() - t0) / steps
+        # projection kernel time of the same launches outside the graph
+        P.priest_profile_read()
+        P.priest_profile_enable(True)
+        batch_step(graph=False)
+        s.synchronize()
+        P.priest_profile_enable(False)
+        n_l, ms = P.priest_profile_read()
     assert int(out["status"].abs().sum().item()) == 0
-    # plain: one problem per launch, no graph
+    roof = roofline_entry(wl, nP * wl.n_samples, ms / n_l, n_l, tiling[0],
+                          "HIP events around each projection launch of one batched plan (no graph)")
+    # plain: one problem per launch, no graph, default tile shape
+    prob.set_tiling((4, 1, 0))
     out1 = prob.plan_outputs(cem, 1, full=False)
     ws1 = prob.workspace(cem, 1)
     torch.cuda.synchronize()
@@ -133,15 +189,18 @@ def batched_3d(P, W, steps: int, plain_problems: int):
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / plain_problems * nP
     work = nP * wl.n_samples * wl.n_proj_iters * wl.n_cem
-    return {"workload": wl.name, "problems": nP,
+    prob.close()
+    return {"workload": wl.name, "problems": nP, "tiling": list(tiling[0]),
+            "tiling_from_autotuner": tiling[1],
             "batched_graph": {"s_per_batch": round(t_batch, 4),
                               "samples_iters_per_s": round(work / t_batch, 1),
                               "plans_per_s": round(nP / t_batch, 2)},
-            "plain_per_problem": {"s_per_64_plans": round(t_plain, 4),
+            "plain_per_problem": {"s_per_batch_equivalent": round(t_plain, 4),
                                   "samples_iters_per_s": round(work / t_plain, 1),
                                   "plans_per_s": round(nP / t_plain, 2),
                                   "timed_problems": plain_problems},
-            "speedup": round(t_plain / t_batch, 3)}
+            "speedup": round(t_plain / t_batch, 3),
+            "roofline": roof}
 
 
 def serving(P, W, n_requests: int, plain_limit_s: float):
@@ -157,11 +216,11 @@ def serving(P, W, n_requests: int, plain_limit_s: float):
     srv = S.Server.for_workload(wl, max_active=1024, memory_budget=2 << 30)
     S.prepare_shapes(srv, reqs)
     warm = W.serving_requests(wl, n_requests=256)
-    S.run_stream(srv, warm, wl, realtime=False)          # warm-up (other robots' state reset below)
+    S.run_stream(srv, warm, wl, realtime=False)          # warm-up on a throw-away server
     srv.close()
     srv = S.Server.for_workload(wl, max_active=1024, memory_budget=2 << 30)
     S.prepare_shapes(srv, reqs)
-    batched, done = S.run_stream(srv, reqs, wl, realtime=True)
+    batched_line, done = S.run_stream(srv, reqs, wl, realtime=True)
     bad = sum(1 for c in done if c.status != 0)
     srv.close()
     plain, _ = S.run_plain(reqs, wl, realtime=True, time_limit=plain_limit_s)
@@ -169,7 +228,7 @@ def serving(P, W, n_requests: int, plain_limit_s: float):
             "offered_req_per_s": round(n_requests / span, 1),
             "offered_tflop_per_s": round(offered_flop / span / 1e12, 2),
             "iterations": f"{wl.n_proj_iters} projection x {wl.n_cem} CEM",
-            "continuous_batching": batched, "nonfinite_results": bad,
+            "continuous_batching": batched_line, "nonfinite_results": bad,
             "plain_per_request": plain,
             "plain_note": f"one priest_plan per request, FIFO, synchronised; stopped after "
                           f"{plain_limit_s} s if behind"}
@@ -181,19 +240,25 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--cpu-sample", type=int, default=150)
+    ap.add_argument("--cpu-sample", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched 3D comparison")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched comparisons")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision section")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--plain-problems", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-plain-limit", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-standalone", action="store_true",
+                    help="skip the standalone projection launches (profiling runs)")
+    ap.add_argument("--tiling", type=str, default=None,
+                    help="axis_slots,row_tiles,persistent for the headline plan (default: autotuned)")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every problem and "
-              "sample shard is independent, so N GPUs would run N disjoint copies", file=sys.stderr)
+              "request is independent, so N GPUs would run N disjoint copies", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -203,6 +268,14 @@ def main():
     wl = W.C2
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = P.Problem.from_workload(wl)
     bc_h, obs_h = W.scene(wl, 0)
     bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
@@ -213,6 +286,8 @@ def main():
     cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
                 n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
                 cov_jitter=wl.cov_jitter)
+    if args.tiling:
+        prob.set_tiling(tuple(int(v) for v in args.tiling.split(",")))
     out = prob.plan_outputs(cem, full=False)
     ws = prob.workspace(cem)
     stream = torch.cuda.current_stream()
@@ -222,11 +297,14 @@ def main():
         cov.copy_(cov0)
         prob.plan(bc, obs, cem, mu, cov, seed=1234 + i, stream_id=0, out=out, workspace=ws)
 
-    for i in range(args.warmup):
+    for i in range(args.warmup):       # the first plan also runs the autotuner
         step(i)
     torch.cuda.synchronize()
+    tiling = prob.last_tiling()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    P.priest_profile_read()
+    P.priest_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -235,62 +313,76 @@ def main():
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    P.priest_profile_enable(False)
+    n_launch, k_total_ms = P.priest_profile_read()
     lat = np.array([a.elapsed_time(b) for a, b in ev])          # ms per plan
     status = int(out["status"][0].item())
     best = float(out["best_cost"][0].item())
     assert status == 0 and np.isfinite(best), (status, best)
+    assert n_launch == args.steps * wl.n_cem, n_launch
 
     per_plan = wl.n_samples * wl.n_proj_iters * wl.n_cem
     value = per_plan * args.steps / wall
+    roofline = roofline_entry(wl, wl.n_samples, k_total_ms / n_launch, n_launch, tiling[0],
+                              "HIP events on the plan's stream around every projection launch "
+                              "inside the timed region")
+    roofline["traffic"] = measured_traffic()
+    roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE "
+                                "(profiles/project_kernel_c2_traffic.txt), null if the kernel "
+                                "changed since")
 
-    # projection kernel alone: same shape, same stream, events around R launches
+    if args.no_standalone:
+        args.no_mixed = True
+    # standalone projection of fresh samples at the same shape (the samples
+    # inside a plan concentrate over the CEM iterations, so launches differ)
     xi = torch.tensor(W.samples(wl, 5), dtype=torch.float32, device=dev)
     xo = torch.empty_like(xi)
     r = torch.empty(wl.n_samples, device=dev)
     c1 = torch.empty(wl.n_samples, device=dev)
-    for _ in range(3):
-        P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
     ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ka.record(stream)
-    for _ in range(args.kernel_reps):
-        P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
-    kb.record(stream)
-    torch.cuda.synchronize()
-    k_ms = ka.elapsed_time(kb) / args.kernel_reps
-    flops = projection_flops(wl.dims, wl.n_coeff, wl.n_steps, wl.n_obs) * wl.n_samples * wl.n_proj_iters
-    achieved = flops / (k_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "project_kernel<2,11>", "kernel_ms": round(k_ms, 4),
-                "flops_per_launch": flops}
+    k_ms = None
+    gpu_results = {}
+    if not args.no_standalone:
+        for _ in range(3):
+            P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+        torch.cuda.synchronize()
+        ka.record(stream)
+        for _ in range(args.kernel_reps):
+            P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+        kb.record(stream)
+        torch.cuda.synchronize()
+        k_ms = round(ka.elapsed_time(kb) / args.kernel_reps, 4)
+        gpu_results["fp32"] = (xo.cpu().numpy(), r.cpu().numpy())
 
-    # mixed precision: same shape, BF16 operands for the right-hand side and
-    # a BF16 hi/lo KKT product, last 10 iterations in FP32
-    prob_bf = P.Problem.from_workload(wl, precision=P.BF16_MIXED, n_refine_fp32=10)
-    xo_bf = torch.empty_like(xi)
-    r_bf = torch.empty(wl.n_samples, device=dev)
-    for _ in range(3):
-        P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
-    torch.cuda.synchronize()
-    ka.record(stream)
-    for _ in range(args.kernel_reps):
-        P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
-    kb.record(stream)
-    torch.cuda.synchronize()
-    k_ms_bf = ka.elapsed_time(kb) / args.kernel_reps
-    P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
-    torch.cuda.synchronize()
-    gpu_results = {"fp32": (xo.cpu().numpy(), r.cpu().numpy()),
-                   "bf16_mixed": (xo_bf.cpu().numpy(), r_bf.cpu().numpy())}
-    mixed = {"kernel_ms_fp32": round(k_ms, 4), "kernel_ms_bf16_mixed": round(k_ms_bf, 4),
-             "n_refine_fp32": 10,
-             "note": "BF16 operands for W^T(e - F xi) and a BF16 hi/lo split of M11 u, FP32 "
-                     "accumulation; errors vs the FP64 oracle in cpu_baseline.gpu_error_vs_oracle"}
+    mixed = None
+    if not args.no_mixed:
+        # BF16 operands for the right-hand side and a BF16 hi/lo KKT product,
+        # last 10 iterations in FP32
+        prob_bf = P.Problem.from_workload(wl, precision=P.BF16_MIXED, n_refine_fp32=10)
+        xo_bf = torch.empty_like(xi)
+        r_bf = torch.empty(wl.n_samples, device=dev)
+        for _ in range(3):
+            P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
+        torch.cuda.synchronize()
+        ka.record(stream)
+        for _ in range(args.kernel_reps):
+            P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
+        kb.record(stream)
+        torch.cuda.synchronize()
+        k_ms_bf = ka.elapsed_time(kb) / args.kernel_reps
+        gpu_results["bf16_mixed"] = (xo_bf.cpu().numpy(), r_bf.cpu().numpy())
+        mixed = {"kernel_ms_fp32": k_ms, "kernel_ms_bf16_mixed": round(k_ms_bf, 4),
+                 "n_refine_fp32": 10,
+                 "note": "BF16 operands for W^T(e - F xi) and a BF16 hi/lo split of M11 u, "
+                         "FP32 accumulation; errors vs the FP64 oracle in "
+                         "cpu_baseline.gpu_error_vs_oracle"}
+        prob_bf.close()
 
-    extra = None
+    extra_2d = extra_3d = None
     if not args.no_extra:
-        extra = batched_3d(P, W, args.batch_steps, args.plain_problems)
+        extra_2d = batched(P, W, W.with_changes(W.C2, name="c2x64_2d_k100_n1000_m50", n_problems=64),
+                           args.batch_steps, args.plain_problems)
+        extra_3d = batched(P, W, W.C3, args.batch_steps, args.plain_problems)
 
     serve_line = None
     if not args.no_serve:
@@ -320,10 +412,13 @@ def main():
         "plans_per_sec": round(args.steps / wall, 3),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
+        "tiling": {"shape": list(tiling[0]), "from_autotuner": tiling[1]},
         "roofline": roofline,
+        "kernel_standalone_ms": k_ms,
         "cpu_baseline": cpu,
         "mixed_precision": mixed,
-        "batched_3d": extra,
+        "batched_2d": extra_2d,
+        "batched_3d": extra_3d,
         "serving": serve_line,
     }
     print(json.dumps(line), flush=True)

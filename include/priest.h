@@ -212,6 +212,15 @@ int32_t priest_set_tiling(priest_problem* p, const priest_tiling* t);
  * receives 1 if it came from the autotuner. */
 int32_t priest_last_tiling(const priest_problem* p, priest_tiling* out, int32_t* tuned);
 
+/* Profiling hook.  While enabled (process-wide), every projection launch made
+ * by priest_project / priest_plan / priest_plan_batch outside graph capture
+ * is bracketed by two HIP events on its stream.  priest_profile_read waits
+ * for the events recorded since the previous read and returns their count
+ * and summed duration in milliseconds (host pointers).  Meant for
+ * benchmarks: kernel time measured inside the timed region. */
+int32_t priest_profile_enable(int32_t on);
+int32_t priest_profile_read(int32_t* n_launches, double* total_ms);
+
 /* Debug/parity hook for the closed-form alpha/beta/d step (Appendix eqs.
  * (15a)-(15c), (13)): for samples xi [N][D] writes the per-row push-outs
  * e(xi) - F xi, laid out [N][n_obs + 2][K][dims] (obstacle blocks, then the

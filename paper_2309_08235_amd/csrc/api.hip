@@ -207,6 +207,48 @@ PlanLayout plan_layout(int D, int N) {
   return l;
 }
 
+// Profiling hook: event pairs around projection launches (see priest.h).
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, pool;
+};
+Profiler& profiler() {
+  static Profiler* p = new Profiler();  // lives until exit
+  return *p;
+}
+
+// launch_project, bracketed by events when profiling is on and the stream is
+// not being captured.
+hipError_t launch_project_timed(const ProjArgs& a, int P, hipStream_t s) {
+  Profiler& pr = profiler();
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(pr.mu);
+    if (pr.on && !stream_capturing(s)) {
+      if (!pr.pool.empty()) {
+        ev = pr.pool.back();
+        pr.pool.pop_back();
+      } else {
+        hipError_t e = hipEventCreate(&ev.first);
+        if (e == hipSuccess) e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  if (ev.first) {
+    const hipError_t e = hipEventRecord(ev.first, s);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_project(a, P, s);
+  if (ev.first) {
+    if (e == hipSuccess) e = hipEventRecord(ev.second, s);
+    std::lock_guard<std::mutex> lk(pr.mu);
+    pr.pending.push_back(ev);
+  }
+  return e;
+}
+
 struct PlanArgs {
   ProjArgs a;
   CemArgs ca;
@@ -304,7 +346,7 @@ int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const f
     a.resid2 = last ? out->resid : nullptr;
     a.c12 = last ? out->c1 : nullptr;
     a.xi_out2 = last ? out->xi_bar : nullptr;
-    HIP_TRY(launch_project(a, P, s));
+    HIP_TRY(launch_project_timed(a, P, s));
     HIP_TRY(launch_cem(ca, P, s));
   }
   return PRIEST_OK;
@@ -551,7 +593,7 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   }
   if (st != PRIEST_OK) return st;
   apply_tiling(a, cfg);
-  HIP_TRY(launch_project(a, 1, s));
+  HIP_TRY(launch_project_timed(a, 1, s));
   return PRIEST_OK;
 }
 
@@ -664,6 +706,39 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
                           int32_t use_graph, void* stream) {
   return plan_common(p, n_problems, bc, obs, c, mu, cov, seed, stream_base, noise, out, workspace,
                      workspace_bytes, use_graph, stream);
+}
+
+int32_t priest_profile_enable(int32_t on) {
+  Profiler& pr = profiler();
+  std::lock_guard<std::mutex> lk(pr.mu);
+  pr.on = on != 0;
+  return PRIEST_OK;
+}
+
+int32_t priest_profile_read(int32_t* n_launches, double* total_ms) {
+  if (!n_launches || !total_ms) return fail(PRIEST_ERR_INVALID, "n_launches and total_ms are required");
+  Profiler& pr = profiler();
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  {
+    std::lock_guard<std::mutex> lk(pr.mu);
+    evs.swap(pr.pending);
+  }
+  double sum = 0.0;
+  hipError_t err = hipSuccess;
+  for (auto& ev : evs) {
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventSynchronize(ev.second);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev.first, ev.second);
+    sum += ms;
+  }
+  {
+    std::lock_guard<std::mutex> lk(pr.mu);
+    for (auto& ev : evs) pr.pool.push_back(ev);
+  }
+  if (err != hipSuccess) return fail(PRIEST_ERR_DEVICE, "profile read failed: %s", hipGetErrorString(err));
+  *n_launches = static_cast<int32_t>(evs.size());
+  *total_ms = sum;
+  return PRIEST_OK;
 }
 
 int32_t priest_tiling_candidates(const priest_problem* p, priest_tiling* out, int32_t max_out,

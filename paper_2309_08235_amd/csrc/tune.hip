@@ -8,7 +8,7 @@
 // compute bit-identical results, so the choice only affects time: each
 // candidate runs one warm-up launch and two timed launches of the caller's
 // real arguments (outputs redirected by the caller) with HIP events on the
-// caller's stream, and the fastest one is kept.
+// caller's stream, and the fastest one is kept (by a 5% margin).
 #include <algorithm>
 #include <vector>
 
@@ -59,10 +59,11 @@ hipError_t time_tilings(const ProjArgs& trial, int n_problems, size_t lds_limit,
 }
 
 int pick_tiling(const std::vector<float>& ms) {
-  // the default (index 0) unless another candidate is more than 2% faster
+  // a candidate replaces the current pick only if it is more than 5% faster,
+  // so timing noise between near-equal shapes does not flip the choice
   int best = 0;
   for (size_t i = 1; i < ms.size(); ++i)
-    if (ms[i] >= 0.0f && (ms[best] < 0.0f || ms[i] < ms[best] * 0.98f)) best = static_cast<int>(i);
+    if (ms[i] >= 0.0f && (ms[best] < 0.0f || ms[i] < ms[best] * 0.95f)) best = static_cast<int>(i);
   return best;
 }
 

@@ -39,6 +39,7 @@ EXPORTS = (
     "priest_server_step", "priest_server_poll", "priest_server_flush", "priest_server_counts",
     "priest_server_stats_get", "priest_server_robot_state", "priest_server_destroy",
     "priest_tiling_candidates", "priest_set_tiling", "priest_last_tiling",
+    "priest_profile_enable", "priest_profile_read",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -152,6 +153,8 @@ _SIGS = {
     "priest_tiling_candidates": (_I, [_P, ctypes.POINTER(Tiling), _I, ctypes.POINTER(_I)]),
     "priest_set_tiling": (_I, [_P, ctypes.POINTER(Tiling)]),
     "priest_last_tiling": (_I, [_P, ctypes.POINTER(Tiling), ctypes.POINTER(_I)]),
+    "priest_profile_enable": (_I, [_I]),
+    "priest_profile_read": (_I, [ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
     "priest_last_error": (ctypes.c_char_p, []),
     "priest_version": (_I, []),
 }
@@ -290,6 +293,18 @@ def priest_last_tiling(handle):
     tuned = _I()
     _check(lib().priest_last_tiling(handle, ctypes.byref(t), ctypes.byref(tuned)))
     return t.as_tuple(), bool(tuned.value)
+
+
+def priest_profile_enable(on: bool = True):
+    _check(lib().priest_profile_enable(int(bool(on))))
+
+
+def priest_profile_read():
+    """(launches, total_ms) of projection launches since the previous read."""
+    n = _I()
+    ms = ctypes.c_double()
+    _check(lib().priest_profile_read(ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def priest_server_now() -> float:

@@ -212,6 +212,7 @@ def run_plain(requests, wl: ServingWorkload = C5, realtime=True, seed=0, time_li
         if key not in probs:
             probs[key] = P.Problem(wl.dims, wl.n_coeff, q.n_steps, q.horizon, q.n_obs, rho=wl.rho,
                                    v_max=wl.v_max, a_max=wl.a_max, bc_mask=wl.bc_mask)
+            probs[key].set_tiling((4, 1, 0))   # the plain form: default shape, no tuning
     torch.cuda.synchronize()
     now = time.perf_counter
     t0 = now() + 0.01
