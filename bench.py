@@ -203,6 +203,49 @@ def batched(P, W, wl, steps: int, plain_problems: int):
             "roofline": roof}
 
 
+def unfused_baseline(P, W, reps: int):
+    """The projection at the headline shape (N=1000) and at N=64000 (the C2
+    scene replicated x64) in the fused kernel and in the plain unfused form
+    (three kernels per iteration through HBM), HIP-event timed."""
+    import torch
+    dev = "cuda:0"
+    wl = W.C2
+    out = {}
+    bc_h, obs_h = W.scene(wl, 0)
+    bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
+    obs = torch.tensor(obs_h, dtype=torch.float32, device=dev)
+    prob = P.Problem.from_workload(wl)
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for N in (wl.n_samples, 64 * wl.n_samples):
+        xi = torch.tensor(W.samples(wl, 5, n=N), dtype=torch.float32, device=dev)
+        ws = torch.empty(P.priest_project_unfused_workspace_size(prob.handle, N), dtype=torch.uint8,
+                         device=dev)
+        xo = torch.empty_like(xi)
+        r = torch.empty(N, device=dev)
+        c1 = torch.empty(N, device=dev)
+        times = {}
+        for name, fn in (("fused", lambda: P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters,
+                                                            xo, r, c1)),
+                         ("unfused", lambda: P.priest_project_unfused(prob.handle, bc, obs, xi,
+                                                                      wl.n_proj_iters, xo, r, c1, ws))):
+            fn()
+            torch.cuda.synchronize()
+            ka.record()
+            for _ in range(reps):
+                fn()
+            kb.record()
+            torch.cuda.synchronize()
+            times[name] = ka.elapsed_time(kb) / reps
+        out[f"n{N}"] = {"fused_ms": round(times["fused"], 4), "unfused_ms": round(times["unfused"], 4),
+                        "speedup": round(times["unfused"] / times["fused"], 2),
+                        "fused_tiling": list(prob.last_tiling()[0])}
+    prob.close()
+    out["note"] = ("one projection of 100 iterations of the C2 scene; unfused = forward, push-out "
+                   "and update kernels per iteration with p/v/a and push-outs in HBM, no MFMA, no "
+                   "culling; per-pass HBM throughput in profiles/unfused_passes_c2x64.md")
+    return out
+
+
 def serving(P, W, n_requests: int, plain_limit_s: float):
     """Continuous-batching service: the Poisson request stream of many robots
     (mixed N, M, K) replayed in real time through the server, and the same
@@ -249,6 +292,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-plain-limit", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--only-unfused", action="store_true",
+                    help="run only the unfused-baseline section (profiling runs)")
     ap.add_argument("--no-standalone", action="store_true",
                     help="skip the standalone projection launches (profiling runs)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -265,7 +310,6 @@ def main():
     from paper_2309_08235_amd import priest as P
     from paper_2309_08235_amd import workloads as W
 
-    wl = W.C2
     dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.calibration_copy_mib > 0:
@@ -276,6 +320,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_unfused:
+        print(json.dumps({"unfused_baseline": unfused_baseline(P, W, reps=2)}), flush=True)
+        return
+
+    wl = W.C2
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
     prob = P.Problem.from_workload(wl)
     bc_h, obs_h = W.scene(wl, 0)
     bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
@@ -384,6 +435,10 @@ def main():
                            args.batch_steps, args.plain_problems)
         extra_3d = batched(P, W, W.C3, args.batch_steps, args.plain_problems)
 
+    unfused = None
+    if not args.no_extra:
+        unfused = unfused_baseline(P, W, reps=3)
+
     serve_line = None
     if not args.no_serve:
         serve_line = serving(P, W, args.serve_requests, args.serve_plain_limit)
@@ -419,6 +474,7 @@ def main():
         "mixed_precision": mixed,
         "batched_2d": extra_2d,
         "batched_3d": extra_3d,
+        "unfused_baseline": unfused,
         "serving": serve_line,
     }
     print(json.dumps(line), flush=True)

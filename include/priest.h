@@ -139,6 +139,23 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs,
                        const float* xi_in, int32_t N, int32_t n_iter,
                        float* xi_out, float* resid, float* c1, void* stream);
 
+/* The same projection as priest_project in its plain, unfused form, kept as
+ * the baseline the fused kernel is measured against: per iteration three
+ * kernels - forward rows p, v, a of every (sample, t) to HBM; closed-form
+ * push-outs of every (sample, t) against every obstacle (eqs. (15a)-(15c)) to
+ * HBM; g = F^T(e - F xi_bar), the multiplier update and the KKT step per
+ * (sample, axis) - then a final forward + push-out pass for r and c1.  No
+ * MFMA, no obstacle culling, FP32 only.  Results match priest_project within
+ * FP32 rounding (not bit for bit: the sums run in another order).
+ * workspace: device buffer of priest_project_unfused_workspace_size bytes
+ * (about 2 * N * K * 3 * dims floats).  Errors: INVALID (also for a problem
+ * built with PRIEST_BF16_MIXED), NOMEM (workspace too small). */
+int32_t priest_project_unfused_workspace_size(const priest_problem* p, int32_t N, size_t* bytes);
+int32_t priest_project_unfused(priest_problem* p, const float* bc, const float* obs,
+                               const float* xi_in, int32_t N, int32_t n_iter, float* xi_out,
+                               float* resid, float* c1, void* workspace, size_t workspace_bytes,
+                               void* stream);
+
 /* Bytes of device workspace priest_plan / priest_plan_batch need for
  * n_problems problems with settings `c` (host call). */
 int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_params* c,

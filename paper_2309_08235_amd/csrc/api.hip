@@ -597,6 +597,39 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   return PRIEST_OK;
 }
 
+int32_t priest_project_unfused_workspace_size(const priest_problem* p, int32_t N, size_t* bytes) {
+  if (!p || !bytes) return fail(PRIEST_ERR_INVALID, "problem and bytes are required");
+  if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);
+  *bytes = unfused_layout(N, p->desc.n_steps, p->desc.dims, p->desc.n_coeff).total;
+  return PRIEST_OK;
+}
+
+int32_t priest_project_unfused(priest_problem* p, const float* bc, const float* obs,
+                               const float* xi_in, int32_t N, int32_t n_iter, float* xi_out,
+                               float* resid, float* c1, void* workspace, size_t workspace_bytes,
+                               void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);
+  if (n_iter < 0) return fail(PRIEST_ERR_INVALID, "n_iter must be >= 0");
+  if (!bc || !xi_in || !xi_out) return fail(PRIEST_ERR_INVALID, "bc, xi_in and xi_out are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  if (p->desc.precision != PRIEST_FP32)
+    return fail(PRIEST_ERR_INVALID, "the unfused form is FP32 only");
+  if (N == 0) return PRIEST_OK;
+  size_t need = 0;
+  priest_project_unfused_workspace_size(p, N, &need);
+  if (!workspace || workspace_bytes < need)
+    return fail(PRIEST_ERR_NOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+  ProjArgs a = base_args(p);
+  a.N = N;
+  a.n_iter = n_iter;
+  a.bc = bc;
+  a.obs = obs;
+  HIP_TRY(launch_unfused(a, xi_in, xi_out, resid, c1, static_cast<char*>(workspace),
+                         static_cast<hipStream_t>(stream)));
+  return PRIEST_OK;
+}
+
 int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_params* c,
                                    int32_t n_problems, size_t* bytes) {
   if (!p || !bytes) return fail(PRIEST_ERR_INVALID, "problem and bytes are required");

@@ -119,6 +119,14 @@ hipError_t time_tilings(const ProjArgs& trial, int n_problems, size_t lds_limit,
                         const std::vector<TileCfg>& cands, std::vector<float>* ms);
 int pick_tiling(const std::vector<float>& ms);
 
+// Unfused projection (unfused.hip): workspace layout in bytes and launcher.
+struct UnfusedLayout {
+  size_t pva, delta, r2, xb, lam, total;
+};
+UnfusedLayout unfused_layout(int N, int K, int dims, int nv);
+hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, float* resid,
+                          float* c1, char* ws, hipStream_t s);
+
 // api.hip services used by the serving runtime
 #define PRIEST_HIDDEN __attribute__((visibility("hidden")))
 PRIEST_HIDDEN int32_t set_error(int32_t code, const char* msg);

@@ -39,7 +39,8 @@ EXPORTS = (
     "priest_server_step", "priest_server_poll", "priest_server_flush", "priest_server_counts",
     "priest_server_stats_get", "priest_server_robot_state", "priest_server_destroy",
     "priest_tiling_candidates", "priest_set_tiling", "priest_last_tiling",
-    "priest_profile_enable", "priest_profile_read",
+    "priest_profile_enable", "priest_profile_read", "priest_project_unfused_workspace_size",
+    "priest_project_unfused",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -153,6 +154,8 @@ _SIGS = {
     "priest_tiling_candidates": (_I, [_P, ctypes.POINTER(Tiling), _I, ctypes.POINTER(_I)]),
     "priest_set_tiling": (_I, [_P, ctypes.POINTER(Tiling)]),
     "priest_last_tiling": (_I, [_P, ctypes.POINTER(Tiling), ctypes.POINTER(_I)]),
+    "priest_project_unfused_workspace_size": (_I, [_P, _I, ctypes.POINTER(ctypes.c_size_t)]),
+    "priest_project_unfused": (_I, [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "priest_profile_enable": (_I, [_I]),
     "priest_profile_read": (_I, [ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
     "priest_last_error": (ctypes.c_char_p, []),
@@ -220,6 +223,20 @@ def priest_problem_dim(handle) -> int:
 def priest_project(handle, bc, obs, xi_in, n_iter, xi_out, resid=None, c1=None, stream=None):
     _check(lib().priest_project(handle, _ptr(bc), _ptr(obs), _ptr(xi_in), xi_in.shape[0], n_iter,
                                 _ptr(xi_out), _ptr(resid), _ptr(c1), _stream(stream)))
+
+
+def priest_project_unfused_workspace_size(handle, N: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().priest_project_unfused_workspace_size(handle, N, ctypes.byref(n)))
+    return n.value
+
+
+def priest_project_unfused(handle, bc, obs, xi_in, n_iter, xi_out, resid, c1, workspace,
+                           stream=None):
+    _check(lib().priest_project_unfused(handle, _ptr(bc), _ptr(obs), _ptr(xi_in), xi_in.shape[0],
+                                        n_iter, _ptr(xi_out), _ptr(resid), _ptr(c1),
+                                        _ptr(workspace, torch.uint8), workspace.numel(),
+                                        _stream(stream)))
 
 
 def priest_plan_workspace_size(handle, params: CemParams, n_problems: int = 1) -> int:
@@ -435,6 +452,19 @@ class Problem:
         r = torch.empty(N, device=dev, dtype=torch.float32)
         c1 = torch.empty(N, device=dev, dtype=torch.float32)
         priest_project(self.handle, bc, obs, xi, n_iter, xo, r, c1, stream)
+        return xo, r, c1
+
+    def project_unfused(self, bc, obs, xi, n_iter, workspace=None, stream=None):
+        """The plain unfused form of project() (baseline)."""
+        N = xi.shape[0]
+        dev = xi.device
+        if workspace is None:
+            workspace = torch.empty(priest_project_unfused_workspace_size(self.handle, N),
+                                    dtype=torch.uint8, device=dev)
+        xo = torch.empty_like(xi)
+        r = torch.empty(N, device=dev, dtype=torch.float32)
+        c1 = torch.empty(N, device=dev, dtype=torch.float32)
+        priest_project_unfused(self.handle, bc, obs, xi, n_iter, xo, r, c1, workspace, stream)
         return xo, r, c1
 
     def offsets(self, bc, obs, xi, stream=None):
