@@ -41,11 +41,15 @@
 #include "priest_internal.h"
 
 #include <mutex>
+#include <type_traits>
 
 // Phase markers inside a projection iteration (no-ops unless a profiling
 // build defines them).
 #ifndef PRIEST_PROJ_MARK
 #define PRIEST_PROJ_MARK(i)
+#endif
+#ifndef PRIEST_PROJ_COUNT
+#define PRIEST_PROJ_COUNT(n)
 #endif
 
 namespace priest {
@@ -90,14 +94,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 struct Layout {  // offsets into dynamic LDS, in floats
-  int rec, xt, gp, fin, mu, L, z, xs, total;
+  int rec, xt, gp, fin, cm, mu, L, z, xs, total;
 };
 
 // rec: obstacle records (12 floats each); xt: per-wave transpose buffers (768
 // floats per 16-step block); gp: double-buffered partial right-hand sides
 // (256 per block); fin: per-(t, sample) residual^2 and c1 of the final pass;
-// xs: the block's samples; mu/L/z: sampler staging.  NB = 16-step blocks of
-// the launch, SPB = samples per block.
+// cm: per-wave obstacle candidate masks (4 words per 64 obstacles); xs: the
+// block's samples; mu/L/z: sampler staging.  NB = 16-step blocks of the
+// launch, SPB = samples per block.
 __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SPB, int mode) {
   Layout l{};
   const int D = dims * nv, D4 = round4(D);
@@ -106,6 +111,7 @@ __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SP
   l.xt = o;  o += NB * 768;
   l.gp = o;  o += 2 * NB * 256;
   l.fin = o; o += 2 * 16 * NB * SPB;
+  l.cm = o;  o += NB * 4 * ((M + 63) / 64);
   l.xs = o;  o += SPB * D4;
   l.mu = o;
   l.L = o + D4;
@@ -121,7 +127,7 @@ __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SP
 // Obstacle records (scene order), three float4 each:
 //   R0 = (cx, cy, cz, cull)   cull = max(a, b) * 1.001 + 1e-4
 //   R1 = (vx, vy, vz, |v|)
-//   R2 = (a, a^2, 1/a^2, 1/b^2)
+//   R2 = (a, a^2 (2D) or rsq(1/b^2) (3D), 1/a^2, 1/b^2)
 // 2D uses circles of radius a (cz = vz = 0).  The push-out of obstacle j on a
 // robot at p is Delta (max(1, n)/n - 1) with Delta = p - o_j(t) and n the
 // scaled distance, i.e. f = max(0, a/|Delta| - 1) in 2D and
@@ -135,6 +141,12 @@ __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SP
 // item, where the push-out is exactly 0, so culling does not change results.
 // ---------------------------------------------------------------------------
 constexpr float kTiny = 1.0e-30f;
+
+// Obstacle candidates processed together in the push-out loop.
+#ifndef PRIEST_CAND_UNROLL
+#define PRIEST_CAND_UNROLL 1
+#endif
+constexpr int kCandUnroll = PRIEST_CAND_UNROLL;
 
 // Wave-wide min / max: DPP within each row of 16 lanes (xor 1, xor 2,
 // rotate 4, rotate 8), then the four row results combined as uniform values.
@@ -233,6 +245,84 @@ __device__ __forceinline__ bool pair_push(const Rec& o, float tt, const float p[
   return q == 0.0f;
 }
 
+// The same push-out split in two so that the independent parts of several
+// obstacles can interleave: pair_term computes the offset and the factor
+// (MOVING: centre advanced to time t), pair_add accumulates them in the
+// order the caller adds obstacles.  The canonical push-out of a zero offset
+// is added through a select: other lanes add +0, which leaves the sums
+// unchanged (they are never -0).
+template <int DIMS>
+struct PairTerm {
+  float d[DIMS];
+  float f, len2;
+  bool zero;
+};
+
+template <int DIMS, bool LAST, bool MOVING>
+__device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, const float p[DIMS]) {
+  PairTerm<DIMS> r;
+  if constexpr (MOVING) {
+    r.d[0] = p[0] - fmaf(o.vx, tt, o.cx);
+    r.d[1] = p[1] - fmaf(o.vy, tt, o.cy);
+    if constexpr (DIMS == 3) r.d[2] = p[2] - fmaf(o.vz, tt, o.cz);
+  } else {
+    r.d[0] = p[0] - o.cx;
+    r.d[1] = p[1] - o.cy;
+    if constexpr (DIMS == 3) r.d[2] = p[2] - o.cz;
+  }
+  const float h = fmaf(r.d[1], r.d[1], r.d[0] * r.d[0]);
+  float q, f;
+  if constexpr (DIMS == 2) {
+    q = h;
+    r.len2 = h;
+    f = fmaf(o.a, rsq(fmaxf(q, kTiny)), -1.0f);
+    if (LAST) f = (q < o.a2) ? f : 0.0f;
+  } else {
+    q = fmaf(r.d[2] * r.d[2], o.ib2, h * o.ia2);
+    r.len2 = fmaf(r.d[2], r.d[2], h);
+    f = rsq(fmaxf(q, kTiny)) - 1.0f;
+    if (LAST) f = (q < 1.0f) ? f : 0.0f;
+  }
+  r.f = fmaxf(f, 0.0f);
+  r.zero = q == 0.0f;
+  return r;
+}
+
+template <int DIMS, bool LAST>
+__device__ __forceinline__ void pair_add(const Rec& o, const PairTerm<DIMS>& t, float s[DIMS],
+                                         float& r2) {
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x) s[x] = fmaf(t.d[x], t.f, s[x]);
+  if (LAST) r2 = fmaf(t.len2 * t.f, t.f, r2);
+  if constexpr (DIMS == 2) {
+    s[0] += t.zero ? o.a : 0.0f;
+    if (LAST) r2 += t.zero ? o.a2 : 0.0f;
+  } else {
+    const float b = o.a2;  // rsq(1/b^2), precomputed in the record
+    s[2] += t.zero ? b : 0.0f;
+    if (LAST) r2 = t.zero ? fmaf(b, b, r2) : r2;
+  }
+}
+
+// Record of lane b broadcast to the wave (velocity only if MOVING).
+template <int DIMS, bool MOVING>
+__device__ __forceinline__ Rec rec_of_lane(const float4& R0, const float4& R1, const float4& R2,
+                                           int b) {
+  Rec r;
+  r.moving = MOVING;
+  r.cx = lane_f(R0.x, b);
+  r.cy = lane_f(R0.y, b);
+  r.cz = (DIMS == 3) ? lane_f(R0.z, b) : 0.0f;
+  r.vx = MOVING ? lane_f(R1.x, b) : 0.0f;
+  r.vy = MOVING ? lane_f(R1.y, b) : 0.0f;
+  r.vz = (MOVING && DIMS == 3) ? lane_f(R1.z, b) : 0.0f;
+  r.a = (DIMS == 2) ? lane_f(R2.x, b) : 0.0f;
+  r.a2 = lane_f(R2.y, b);
+  r.ia2 = (DIMS == 3) ? lane_f(R2.z, b) : 0.0f;
+  r.ib2 = (DIMS == 3) ? lane_f(R2.w, b) : 0.0f;
+  return r;
+}
+
 // Canonical push-out of a zero offset (+x by a in 2D, +z by b in 3D).
 template <int DIMS, bool LAST>
 __device__ __forceinline__ void zero_push(const Rec& o, float s[DIMS], float& r2) {
@@ -268,69 +358,162 @@ __device__ void build_records(const float* obs, int M, int t, int nt, float4* re
     const float sp = sqrtf(o[3] * o[3] + o[4] * o[4] + vz * vz);
     rec[3 * j] = make_float4(o[0], o[1], cz, fmaxf(a, b) * 1.001f + 1.0e-4f);
     rec[3 * j + 1] = make_float4(o[3], o[4], vz, sp);
-    rec[3 * j + 2] = make_float4(a, a * a, 1.0f / (a * a), 1.0f / (b * b));
+    // 3D keeps rsq(1/b^2), the canonical zero-offset push-out, in place of a^2
+    const float ib2 = 1.0f / (b * b);
+    rec[3 * j + 2] = make_float4(a, (DIMS == 3) ? rsq(ib2) : a * a, 1.0f / (a * a), ib2);
   }
 }
 
+// Per-wave memory of the last obstacle cull: every item's position when the
+// candidate sets were built, and the displacement (squared) up to which they
+// stay valid.  The candidate masks themselves live in LDS (4 words per group
+// of 64 obstacles: candidate and moving bits).
+template <int NI, int DIMS>
+struct CullCache {
+  float pref[NI][DIMS];
+  float lim2;
+  bool valid;
+};
+
+// Growth of the candidate radius that lets a candidate set be reused: an
+// obstacle is a candidate if it may come within (1 + kSlack) * cull of the
+// wave's box, and the set is reused while no item has moved farther than
+// kSlack * (smallest cull radius) from where it was when the set was built.
+// A skipped obstacle then stays farther than its cull radius from every item,
+// where its push-out is exactly zero.
+#ifndef PRIEST_CULL_SLACK
+#define PRIEST_CULL_SLACK 0.5f
+#endif
+constexpr float kSlack = PRIEST_CULL_SLACK;
+
 // Obstacle push-outs of this lane's NI items, summed over obstacles, with
 // wave-level culling.  tmid / thalf: centre and half-width of the wave's time
-// window.  The items of a lane are independent, so their pair updates
-// interleave.
+// window.  Candidates are added in one canonical order: per group of 64, the
+// static obstacles by index, then the moving ones by index.
 template <int DIMS, bool LAST, int NI>
 __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const float tt[NI],
                                                 float tmid, float thalf, const bool ok[NI],
                                                 const float p[NI][DIMS], float S[NI][DIMS],
-                                                float r2[NI], int lane) {
-  float lo[DIMS], hi[DIMS];
-#pragma unroll
-  for (int x = 0; x < DIMS; ++x) {
-    float mn = INFINITY, mx = -INFINITY;
+                                                float r2[NI], int lane, CullCache<NI, DIMS>& cc,
+                                                uint32_t* wm) {
+  // reuse the candidate sets if every item is still within the slack
+  bool reuse = false;
+  if (cc.valid) {
+    bool far = false;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      mn = fminf(mn, ok[i] ? p[i][x] : INFINITY);
-      mx = fmaxf(mx, ok[i] ? p[i][x] : -INFINITY);
+      float d2 = 0.0f;
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) {
+        const float e = p[i][x] - cc.pref[i][x];
+        d2 = fmaf(e, e, d2);
+      }
+      far = far || (ok[i] && !(d2 <= cc.lim2));
     }
-    lo[x] = wave_min(mn);
-    hi[x] = wave_max(mx);
+    reuse = __ballot(far) == 0ull;
   }
-  PRIEST_PROJ_MARK(6);
-  for (int base = 0; base < M; base += 64) {
+  if (!reuse) {
+    float lo[DIMS], hi[DIMS];
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) {
+      float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        mn = fminf(mn, ok[i] ? p[i][x] : INFINITY);
+        mx = fmaxf(mx, ok[i] ? p[i][x] : -INFINITY);
+      }
+      lo[x] = wave_min(mn);
+      hi[x] = wave_max(mx);
+    }
+    PRIEST_PROJ_MARK(6);
+    float cmin = INFINITY;
+    for (int base = 0, g = 0; base < M; base += 64, ++g) {
+      const int j = base + lane;
+      bool cand = false, mv = false;
+      if (j < M) {
+        const float4 R0 = rec[3 * j], R1 = rec[3 * j + 1];
+        const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y),
+                             fmaf(R1.z, tmid, R0.z)};
+        float d2 = 0.0f;
+#pragma unroll
+        for (int x = 0; x < DIMS; ++x) {
+          const float e = fmaxf(fmaxf(lo[x] - oc[x], oc[x] - hi[x]), 0.0f);
+          d2 = fmaf(e, e, d2);
+        }
+        const float rr = fmaf(R1.w, thalf, R0.w * (1.0f + kSlack));
+        cand = d2 < rr * rr;
+        mv = R1.w != 0.0f;
+        cmin = fminf(cmin, R0.w);
+      }
+      const unsigned long long mask = __ballot(cand);
+      const unsigned long long moving = __ballot(cand && mv);
+      if (lane == 0) {
+        wm[4 * g + 0] = static_cast<uint32_t>(mask);
+        wm[4 * g + 1] = static_cast<uint32_t>(mask >> 32);
+        wm[4 * g + 2] = static_cast<uint32_t>(moving);
+        wm[4 * g + 3] = static_cast<uint32_t>(moving >> 32);
+      }
+    }
+    const float lim = kSlack * wave_min(cmin);
+    cc.lim2 = lim * lim;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) cc.pref[i][x] = p[i][x];
+    cc.valid = true;
+    wave_lds_sync();
+  }
+  for (int base = 0, g = 0; base < M; base += 64, ++g) {
+    const uint4 m4 = *reinterpret_cast<const uint4*>(wm + 4 * g);
+    // (readfirstlane returns int: widen through uint32_t, not sign-extended)
+    auto u64 = [](uint32_t lo, uint32_t hi) {
+      return static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo))) |
+             (static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi)))
+              << 32);
+    };
+    const unsigned long long cmask = u64(m4.x, m4.y);
+    if (!cmask) continue;
+    const unsigned long long mvmask = u64(m4.z, m4.w);
     const int j = base + lane;
     float4 R0 = make_float4(0, 0, 0, 0), R1 = R0, R2 = R0;
-    bool cand = false;
     if (j < M) {
       R0 = rec[3 * j];
       R1 = rec[3 * j + 1];
       R2 = rec[3 * j + 2];
-      const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y),
-                           fmaf(R1.z, tmid, R0.z)};
-      float d2 = 0.0f;
+    }
+    // kCandUnroll candidates at a time (their offsets and factors are
+    // independent), added in the canonical order, the tail one at a time
+    auto run = [&](unsigned long long mask, auto moving_tag) {
+      constexpr bool MV = decltype(moving_tag)::value;
+      PRIEST_PROJ_COUNT(__builtin_popcountll(mask));
+      while (mask) {
+        if (__builtin_popcountll(mask) >= kCandUnroll) {
+          Rec o[kCandUnroll];
 #pragma unroll
-      for (int x = 0; x < DIMS; ++x) {
-        const float e = fmaxf(fmaxf(lo[x] - oc[x], oc[x] - hi[x]), 0.0f);
-        d2 = fmaf(e, e, d2);
+          for (int u = 0; u < kCandUnroll; ++u) {
+            o[u] = rec_of_lane<DIMS, MV>(R0, R1, R2, __builtin_ctzll(mask));
+            mask &= mask - 1;
+          }
+          PairTerm<DIMS> tm[kCandUnroll][NI];
+#pragma unroll
+          for (int u = 0; u < kCandUnroll; ++u)
+#pragma unroll
+            for (int i = 0; i < NI; ++i) tm[u][i] = pair_term<DIMS, LAST, MV>(o[u], tt[i], p[i]);
+#pragma unroll
+          for (int u = 0; u < kCandUnroll; ++u)
+#pragma unroll
+            for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o[u], tm[u][i], S[i], r2[i]);
+        } else {
+          const Rec o0 = rec_of_lane<DIMS, MV>(R0, R1, R2, __builtin_ctzll(mask));
+          mask &= mask - 1;
+#pragma unroll
+          for (int i = 0; i < NI; ++i)
+            pair_add<DIMS, LAST>(o0, pair_term<DIMS, LAST, MV>(o0, tt[i], p[i]), S[i], r2[i]);
+        }
       }
-      const float rr = fmaf(R1.w, thalf, R0.w);
-      cand = d2 < rr * rr;
-    }
-    unsigned long long mask = __ballot(cand);
-    const unsigned long long moving = __ballot(cand && R1.w != 0.0f);
-    while (mask) {
-      const int b = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      // static and moving obstacles take separate copies of the pair code
-      auto pairs = [&](const Rec& o) {
-        bool zero[NI];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) zero[i] = pair_push<DIMS, LAST>(o, tt[i], p[i], S[i], r2[i]);
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-          if (__ballot(zero[i] && ok[i]))
-            if (zero[i]) zero_push<DIMS, LAST>(o, S[i], r2[i]);
-      };
-      if ((moving >> b) & 1ull) pairs(rec_from_lane<DIMS>(R0, R1, R2, b, true));
-      else pairs(rec_from_lane<DIMS>(R0, R1, R2, b, false));
-    }
+    };
+    run(cmask & ~mvmask, std::false_type{});
+    run(mvmask, std::true_type{});
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i)
@@ -347,14 +530,14 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
                                           const float v[NI][DIMS], const float ac[NI][DIMS],
                                           float vmax, float amax, float S[NI][DIMS],
                                           float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
-                                          int lane) {
+                                          int lane, CullCache<NI, DIMS>& cc, uint32_t* wm) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
     for (int x = 0; x < DIMS; ++x) { S[i][x] = 0.0f; dv[i][x] = 0.0f; da[i][x] = 0.0f; }
     r2[i] = 0.0f;
   }
-  obstacle_pushes<DIMS, LAST, NI>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane);
+  obstacle_pushes<DIMS, LAST, NI>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc, wm);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (ok[i]) {
@@ -434,6 +617,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
                     Am[2] - from_bf16(Mhi[2]), Am[3] - from_bf16(Mhi[3]));
   }
   float* xt = sm + l.xt + w * RT * 768;
+  uint32_t* wm = reinterpret_cast<uint32_t*>(sm + l.cm) + w * 4 * ((M + 63) / 64);
 
   // Forward rows of this wave's time blocks, transposed to the item layout.
   auto forward = [&](float p[NI][DIMS], float v[NI][DIMS], float ac[NI][DIMS]) {
@@ -537,6 +721,8 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     }
     xb = xi;
     f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
+    CullCache<NI, DIMS> cull;
+    cull.valid = false;
 
     // ---- projection iterations ---------------------------------------------------
     for (int k = 0; k < a.n_iter; ++k) {
@@ -546,7 +732,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       PRIEST_PROJ_MARK(1);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
       item_push<DIMS, false, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv,
-                                 da, r2, lane);
+                                 da, r2, lane, cull, wm);
       PRIEST_PROJ_MARK(2);
       // back to the column layout: slot AS*i + x of the lane's f4 holds axis x
       // of item i
@@ -666,7 +852,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       forward(p, v, ac);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
       item_push<DIMS, true, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv,
-                                da, r2, lane);
+                                da, r2, lane, cull, wm);
       float* fin = sm + l.fin;
   #pragma unroll
       for (int n = 0; n < NI; ++n) {
