@@ -25,7 +25,6 @@ namespace priest {
 namespace {
 
 constexpr int kStageFloats = 4096;  // elite rows staged in LDS per chunk
-constexpr int kOwn = 3;             // covariance entries per thread (D <= 48)
 
 __host__ __device__ inline size_t align16(size_t n) { return (n + 15) & ~static_cast<size_t>(15); }
 
@@ -66,11 +65,13 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 }
 
 // Lower Cholesky of the D x D matrix A (LDS) by one wave, rows padded to DM
-// with the identity; lane i keeps row i in registers and column j is
-// broadcast lane by lane.  Writes L back into A (lower triangle).  Returns
-// false if a pivot is not positive and finite (it is replaced by 1).
+// with the identity; lane i keeps row i in registers.  Column j is
+// broadcast through `col` (LDS, DM floats): lane c's value of the column is
+// exactly what the update of entry c reads.  Writes L back into A (lower
+// triangle).  Returns false if a pivot is not positive and finite (it is
+// replaced by 1).
 template <int DM>
-__device__ bool cholesky_wave(float* A, int D, int lane) {
+__device__ bool cholesky_wave(float* A, int D, int lane, float* col) {
   float row[DM];
 #pragma unroll
   for (int c = 0; c < DM; ++c)
@@ -81,11 +82,21 @@ __device__ bool cholesky_wave(float* A, int D, int lane) {
     const float piv = bcast(row[j], j);
     const bool b = !(piv > 0.0f) || !(piv < 3.0e38f);
     bad = bad || b;
-    const float ljj = b ? 1.0f : sqrtf(piv);
-    const float lij = (lane > j) ? row[j] / ljj : ((lane == j) ? ljj : row[j]);
+    // one reciprocal square root per column: l_jj = piv * rsq(piv),
+    // l_ij = a_ij * rsq(piv)
+    const float inv = b ? 1.0f : __builtin_amdgcn_rsqf(piv);
+    const float ljj = b ? 1.0f : piv * inv;
+    const float lij = (lane > j) ? row[j] * inv : ((lane == j) ? ljj : row[j]);
     row[j] = lij;
+    if (lane < DM) col[lane] = lij;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int c = j + 1; c < DM; ++c) row[c] = fmaf(-lij, bcast(lij, c), row[c]);
+    for (int c = j + 1; c < DM; ++c) row[c] = fmaf(-lij, col[c], row[c]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (lane < D) {
 #pragma unroll
@@ -95,6 +106,11 @@ __device__ bool cholesky_wave(float* A, int D, int lane) {
   return !bad;
 }
 
+using f4 = __attribute__((ext_vector_type(4))) float;
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 // Stable selection of the k smallest keys among n (n <= T * IPT): writes the
 // values of ranks 0..k-1 to out[] in ascending (key, input position) order.
@@ -191,63 +207,81 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     // 4. mean and covariance from elite rows staged in LDS, CH rows at a time
     float* stage = reinterpret_cast<float*>(sm + l.stage);
     const int CH = kStageFloats / D;
-    float macc = 0.0f;
-    for (int m0 = 0; m0 < a.n_elite; m0 += CH) {
-      const int nm = min(CH, a.n_elite - m0);
+    const bool one_chunk = a.n_elite <= CH;
+    auto stage_rows = [&](int m0, int nm) {
       for (int i = tid; i < nm * D; i += T) {
         const int m = i / D;
         stage[i] = xb[static_cast<int64_t>(elite[m0 + m]) * D + (i - m * D)];
       }
+    };
+    // mean: coefficient d gets 4 partial sums (elites m = part mod 4), added
+    // in a fixed order; the partials live in A until the covariance is written
+    float macc = 0.0f;
+    const int part = tid / D, md = tid - part * D;
+    for (int m0 = 0; m0 < a.n_elite; m0 += CH) {
+      const int nm = min(CH, a.n_elite - m0);
+      stage_rows(m0, nm);
       __syncthreads();
-      if (tid < D) {
-#pragma unroll 8
-        for (int m = 0; m < nm; ++m) macc = fmaf(w[m0 + m], stage[m * D + tid], macc);
+      if (part < 4) {
+        for (int m = part; m < nm; m += 4) macc = fmaf(w[m0 + m], stage[m * D + md], macc);
       }
-      __syncthreads();
+      if (!one_chunk) __syncthreads();
     }
-    if (tid < D) muN[tid] = (1.0f - a.sigma) * mu[tid] + a.sigma * (macc * inv_sw);
+    if (part < 4) A[tid] = macc;
+    __syncthreads();
+    if (tid < D) {
+      const float sm4 = (A[tid] + A[D + tid]) + (A[2 * D + tid] + A[3 * D + tid]);
+      muN[tid] = (1.0f - a.sigma) * mu[tid] + a.sigma * (sm4 * inv_sw);
+    }
     __syncthreads();
     PRIEST_CEM_MARK(4);
-    // covariance about the new mean: thread tid owns lower-triangle entries
-    // e = tid + k T, k < kOwn
-    const int ntri = D * (D + 1) / 2;
-    int ti[kOwn], tj[kOwn];
-    float cacc[kOwn] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < kOwn; ++k) {
-      const int e = tid + k * T;
-      int i = 0;
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      ti[k] = i;
-      tj[k] = e - i * (i + 1) / 2;
+    // covariance about the new mean, sum_m w_m (x_m - mu')(x_m - mu')^T, on
+    // MFMA 16x16x4: wave v computes lower-triangle tile v of the ceil(D/16)^2
+    // tiles, elites four at a time (two accumulation chains, added at the end)
+    const int wv = tid >> 6, lane = tid & 63;
+    const int nt = (D + 15) / 16;
+    int ti = 0, tj = 0;
+    {
+      int v = wv;
+      while (ti < nt && v > ti) {
+        v -= ti + 1;
+        ++ti;
+      }
+      tj = v;
     }
+    const bool owner = ti < nt;
+    f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
     for (int m0 = 0; m0 < a.n_elite; m0 += CH) {
       const int nm = min(CH, a.n_elite - m0);
-      for (int i = tid; i < nm * D; i += T) {
-        const int m = i / D;
-        stage[i] = xb[static_cast<int64_t>(elite[m0 + m]) * D + (i - m * D)];
+      if (!one_chunk) {
+        stage_rows(m0, nm);
+        __syncthreads();
       }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kOwn; ++k) {
-        if (tid + k * T < ntri) {
-          const float mi = muN[ti[k]], mj = muN[tj[k]];
-          float acc = cacc[k];
-#pragma unroll 8
-          for (int m = 0; m < nm; ++m)
-            acc = fmaf(w[m0 + m] * (stage[m * D + ti[k]] - mi), stage[m * D + tj[k]] - mj, acc);
-          cacc[k] = acc;
+      if (owner) {
+        const int ii = ti * 16 + (lane & 15), jj = tj * 16 + (lane & 15);
+        const float mi = ii < D ? muN[ii] : 0.0f, mj = jj < D ? muN[jj] : 0.0f;
+        for (int s4 = 0; s4 < nm; s4 += 8) {
+          const int ma = s4 + (lane >> 4), mb = ma + 4;
+          const float av0 = (ma < nm && ii < D) ? w[m0 + ma] * (stage[ma * D + ii] - mi) : 0.0f;
+          const float bv0 = (ma < nm && jj < D) ? stage[ma * D + jj] - mj : 0.0f;
+          const float av1 = (mb < nm && ii < D) ? w[m0 + mb] * (stage[mb * D + ii] - mi) : 0.0f;
+          const float bv1 = (mb < nm && jj < D) ? stage[mb * D + jj] - mj : 0.0f;
+          acc0 = mfma(av0, bv0, acc0);
+          acc1 = mfma(av1, bv1, acc1);
         }
       }
-      __syncthreads();
+      if (!one_chunk) __syncthreads();
     }
+    if (owner) {
+      const f4 acc = acc0 + acc1;
 #pragma unroll
-    for (int k = 0; k < kOwn; ++k) {
-      if (tid + k * T < ntri) {
-        const int i = ti[k], j = tj[k];
-        const float v = (1.0f - a.sigma) * cov[i * D + j] + a.sigma * (cacc[k] * inv_sw);
-        A[i * D + j] = v;
-        A[j * D + i] = v;
+      for (int r = 0; r < 4; ++r) {
+        const int i = ti * 16 + 4 * (lane >> 4) + r, j = tj * 16 + (lane & 15);
+        if (i < D && j < D && i >= j) {
+          const float v = (1.0f - a.sigma) * cov[i * D + j] + a.sigma * (acc[r] * inv_sw);
+          A[i * D + j] = v;
+          A[j * D + i] = v;
+        }
       }
     }
     __syncthreads();
@@ -270,7 +304,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     tr = wave_sum(tr);
     const float eps = a.cov_jitter * tr / static_cast<float>(D);
     for (int d = tid; d < D; d += 64) A[d * D + d] += eps;
-    const bool ok = cholesky_wave<DM>(A, D, tid);
+    const bool ok = cholesky_wave<DM>(A, D, tid, red);
     if (tid == 0 && a.status) {
       bool fin = ok;
       if (!a.chol_only) fin = fin && (a.best_cost[prob] == a.best_cost[prob]);
