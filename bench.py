@@ -203,6 +203,82 @@ def batched(P, W, wl, steps: int, plain_problems: int):
             "roofline": roof}
 
 
+def dpriest_section(P, W, reps: int, seeds: int = 4):
+    """D-PRIEST on the headline scene: G Gaussians fanned out around the
+    straight line share N = 1000 samples (N/G each), every CEM step of all
+    groups in one launch (one plan_dpriest call), against the plain form of
+    G separate priest_plan calls.  Also the mean picked cost over a few
+    seeds, the quality side of Sec. III-C."""
+    import torch
+    dev = "cuda:0"
+    base = W.C2
+    bc_h, obs_h = W.scene(base, 0)
+    bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
+    obs = torch.tensor(obs_h, dtype=torch.float32, device=dev)
+    rows = []
+    for G in (1, 2, 4, 8):
+        n = base.n_samples // G
+        wl = W.with_changes(base, n_samples=n, n_proj=W.default_n_proj(n),
+                            n_elite=max(4, base.n_elite // G))
+        prob = P.Problem.from_workload(wl)
+        cem = P.Cem(n_samples=n, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters, n_proj=wl.n_proj,
+                    n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma, cov_jitter=wl.cov_jitter)
+        mu0 = torch.tensor(W.dpriest_means(wl, G), dtype=torch.float32, device=dev)
+        cov0 = torch.tensor(np.stack([W.initial_cov(wl)] * G), dtype=torch.float32, device=dev)
+        mu, cov = mu0.clone(), cov0.clone()
+        out = prob.plan_outputs(cem, G, full=False)
+        ws = prob.workspace(cem, G)
+        best = torch.empty(wl.D, device=dev)
+        bcost = torch.empty(1, device=dev)
+        bg = torch.empty(1, dtype=torch.int32, device=dev)
+
+        def run(seed):
+            mu.copy_(mu0)
+            cov.copy_(cov0)
+            P.priest_plan_dpriest(prob.handle, G, bc, obs, cem.c(), mu, cov, seed, 0, None, out,
+                                  best, bcost, bg, ws)
+
+        run(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            run(r)
+        torch.cuda.synchronize()
+        t_d = (time.perf_counter() - t0) / reps
+        costs = []
+        for sd in range(seeds):
+            run(1000 + sd)
+            costs.append(float(bcost.item()))
+        assert int(out["status"].abs().sum().item()) == 0
+        # plain: the G distributions as G separate plans, one launch each
+        prob.set_tiling((4, 1, 0))
+        out1 = prob.plan_outputs(cem, 1, full=False)
+        ws1 = prob.workspace(cem, 1)
+        ms = [mu0[g].clone() for g in range(G)]
+        cs = [cov0[g].clone() for g in range(G)]
+        for g in range(G):
+            prob.plan(bc, obs, cem, ms[g], cs[g], seed=0, stream_id=g, out=out1, workspace=ws1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            for g in range(G):
+                ms[g].copy_(mu0[g])
+                cs[g].copy_(cov0[g])
+                prob.plan(bc, obs, cem, ms[g], cs[g], seed=r, stream_id=g, out=out1,
+                          workspace=ws1)
+        torch.cuda.synchronize()
+        t_p = (time.perf_counter() - t0) / reps
+        prob.close()
+        rows.append({"groups": G, "samples_per_group": n,
+                     "ms_per_plan": round(t_d * 1e3, 3),
+                     "plain_separate_plans_ms": round(t_p * 1e3, 3),
+                     "speedup": round(t_p / t_d, 3),
+                     "mean_picked_cost": round(float(np.mean(costs)), 4),
+                     "seeds": seeds})
+    return {"workload": "c2 scene, N=1000 total split over G groups, n_cem=%d" % base.n_cem,
+            "rows": rows}
+
+
 def unfused_baseline(P, W, reps: int):
     """The projection at the headline shape (N=1000) and at N=64000 (the C2
     scene replicated x64) in the fused kernel and in the plain unfused form
@@ -436,8 +512,10 @@ def main():
         extra_3d = batched(P, W, W.C3, args.batch_steps, args.plain_problems)
 
     unfused = None
+    dpr = None
     if not args.no_extra:
         unfused = unfused_baseline(P, W, reps=3)
+        dpr = dpriest_section(P, W, reps=5)
 
     serve_line = None
     if not args.no_serve:
@@ -475,6 +553,7 @@ def main():
         "batched_2d": extra_2d,
         "batched_3d": extra_3d,
         "unfused_baseline": unfused,
+        "dpriest": dpr,
         "serving": serve_line,
     }
     print(json.dumps(line), flush=True)

@@ -238,6 +238,25 @@ int32_t priest_last_tiling(const priest_problem* p, priest_tiling* out, int32_t*
 int32_t priest_profile_enable(int32_t on);
 int32_t priest_profile_read(int32_t* n_launches, double* total_ms);
 
+/* D-PRIEST (Sec. III-C): n_groups Gaussians (mu [G][D], cov [G][D][D], read
+ * and overwritten like priest_plan) each draw c->n_samples samples on ONE
+ * scene (bc [dims][6], obs [n_obs][8] shared by all groups).  Every CEM
+ * iteration projects the samples of all groups in one launch, then each
+ * group selects and refits on its own samples; after n_cem iterations the
+ * group whose final best trajectory has the lowest c_aug is picked.
+ * out: per-group outputs stacked as for priest_plan_batch (out->best_xi
+ * [G][D] and out->best_cost [G] required).  best_xi [D], best_cost [1] and
+ * best_group [1] receive the pick (ties: lowest group index; NaN ranks last).
+ * Group g draws stream stream_base + g; noise [G][n_cem][N][D] nullable.
+ * workspace: priest_plan_workspace_size(p, c, n_groups) bytes.
+ * Errors as priest_plan. */
+int32_t priest_plan_dpriest(priest_problem* p, int32_t n_groups, const float* bc,
+                            const float* obs, const priest_cem_params* c, float* mu, float* cov,
+                            uint64_t seed, uint32_t stream_base, const float* noise,
+                            const priest_plan_out* out, float* best_xi, float* best_cost,
+                            int32_t* best_group, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
 /* Debug/parity hook for the closed-form alpha/beta/d step (Appendix eqs.
  * (15a)-(15c), (13)): for samples xi [N][D] writes the per-row push-outs
  * e(xi) - F xi, laid out [N][n_obs + 2][K][dims] (obstacle blocks, then the

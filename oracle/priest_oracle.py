@@ -488,6 +488,40 @@ def plan(prob: Problem, bc, obs, mu, Sigma, prm: CemParams, n_cem: int,
     return steps
 
 
+@dataclass
+class DPriestResult:
+    groups: list            # per distribution: the list of CemStep of plan()
+    best_group: int
+    best_xi: np.ndarray
+    best_cost: float
+
+
+def dpriest(prob: Problem, bc, obs, mus, Sigmas, prm: CemParams, n_cem: int,
+            noise=None, seed: int = 0, stream_base: int = 0) -> DPriestResult:
+    """D-PRIEST (Sec. III-C): M Gaussians, each drawing prm.n_samples samples;
+    all samples are projected (per sample, so the row-wise stacking of the
+    paper does not change any value), every distribution is refitted on its
+    own samples, and the lowest-cost final trajectory over the M instances is
+    returned (first index on ties).  Distribution g draws stream
+    stream_base + g, or noise[g] ([M, n_cem, N, D]) when given."""
+    groups = []
+    for g in range(len(mus)):
+        z = noise[g] if noise is not None else None
+        groups.append(plan(prob, bc, obs, np.asarray(mus[g], np.float64),
+                           np.asarray(Sigmas[g], np.float64), prm, n_cem, noise=z, seed=seed,
+                           stream=stream_base + g))
+    best = pick_group([st[-1].best_cost for st in groups])
+    return DPriestResult(groups, best, groups[best][-1].best_xi, float(groups[best][-1].best_cost))
+
+
+def pick_group(costs) -> int:
+    """Index of the lowest final cost over the distributions of D-PRIEST
+    (Sec. III-C); NaN ranks last, ties go to the lowest index."""
+    c = np.asarray(costs, np.float64)
+    c = np.where(np.isnan(c), np.inf, c)
+    return int(np.argmin(c))
+
+
 # ---------------------------------------------------------------------------
 # Counter-based normal draws: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
 # "Parallel random numbers: as easy as 1, 2, 3", SC'11) + Box-Muller.

@@ -396,6 +396,29 @@ int32_t resolve_tiling(priest_problem* p, const ProjArgs& a, int P, hipStream_t 
   return PRIEST_OK;
 }
 
+ProjArgs trial_args(const ProjArgs& a);
+
+// Picks (and applies) the projection tile shape of a plan loop: before any
+// capture, since timing synchronises the stream; the trial needs the first
+// draw's Cholesky factor, which the loop itself recomputes.
+int32_t plan_tiling(priest_problem* p, PlanArgs& pa, int32_t P, hipStream_t s, TileCfg* cfg) {
+  int32_t st = check_lds(p, pa.a);
+  if (st != PRIEST_OK) return st;
+  if (pa.a.n_iter > 0 && autotune_enabled() && !tiling_cached(p, pa.a, P) && !stream_capturing(s)) {
+    CemArgs chol = pa.ca;
+    chol.chol_only = 1;
+    chol.status = nullptr;
+    HIP_TRY(launch_cem(chol, P, s));
+    const ProjArgs t = trial_args(pa.a);
+    st = resolve_tiling(p, pa.a, P, s, &t, cfg);
+  } else {
+    st = resolve_tiling(p, pa.a, P, s, nullptr, cfg);
+  }
+  if (st != PRIEST_OK) return st;
+  apply_tiling(pa.a, *cfg);
+  return check_lds(p, pa.a);
+}
+
 // A shortened copy of `a` for timing: at most 8 iterations (keeping BF16
 // iterations if `a` has any, so that the same kernel instance runs).
 ProjArgs trial_args(const ProjArgs& a) {
@@ -662,24 +685,8 @@ static int32_t plan_common(priest_problem* p, int32_t P, const float* bc, const 
   if (use_graph && !s) return fail(PRIEST_ERR_INVALID, "graph capture needs a non-default stream");
   PlanArgs pa = plan_args(p, P, bc, obs, c, mu, cov, seed, stream_base, noise, out,
                           static_cast<char*>(workspace));
-  st = check_lds(p, pa.a);
-  if (st != PRIEST_OK) return st;
-  // tile shape (before any capture: timing synchronises the stream); the
-  // trial needs the first draw's Cholesky factor, which the loop recomputes
   TileCfg cfg{};
-  if (pa.a.n_iter > 0 && autotune_enabled() && !tiling_cached(p, pa.a, P) && !stream_capturing(s)) {
-    CemArgs chol = pa.ca;
-    chol.chol_only = 1;
-    chol.status = nullptr;
-    HIP_TRY(launch_cem(chol, P, s));
-    const ProjArgs t = trial_args(pa.a);
-    st = resolve_tiling(p, pa.a, P, s, &t, &cfg);
-  } else {
-    st = resolve_tiling(p, pa.a, P, s, nullptr, &cfg);
-  }
-  if (st != PRIEST_OK) return st;
-  apply_tiling(pa.a, cfg);
-  st = check_lds(p, pa.a);
+  st = plan_tiling(p, pa, P, s, &cfg);
   if (st != PRIEST_OK) return st;
   if (!use_graph) return enqueue_plan(P, pa, c, noise, out, s);
   std::vector<uint64_t> key = {
@@ -806,6 +813,44 @@ int32_t priest_last_tiling(const priest_problem* p, priest_tiling* out, int32_t*
   std::lock_guard<std::mutex> lk(const_cast<priest_problem*>(p)->tune_mu);
   *out = priest_tiling{p->last_cfg.axis_slots, p->last_cfg.row_tiles, p->last_cfg.persistent, 0};
   if (tuned) *tuned = p->last_tuned;
+  return PRIEST_OK;
+}
+
+int32_t priest_plan_dpriest(priest_problem* p, int32_t n_groups, const float* bc,
+                            const float* obs, const priest_cem_params* c, float* mu, float* cov,
+                            uint64_t seed, uint32_t stream_base, const float* noise,
+                            const priest_plan_out* out, float* best_xi, float* best_cost,
+                            int32_t* best_group, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  int32_t st = validate_cem(c);
+  if (st != PRIEST_OK) return st;
+  if (n_groups < 1) return fail(PRIEST_ERR_INVALID, "n_groups must be >= 1");
+  if (!bc || !mu || !cov || !out || !out->best_xi || !out->best_cost || !workspace || !best_xi ||
+      !best_cost || !best_group)
+    return fail(PRIEST_ERR_INVALID,
+                "bc, mu, cov, out->best_xi, out->best_cost, best_xi, best_cost, best_group and "
+                "workspace are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  size_t need = 0;
+  priest_plan_workspace_size(p, c, n_groups, &need);
+  if (workspace_bytes < need)
+    return fail(PRIEST_ERR_NOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+  if (cem_lds_bytes(c->n_samples, p->D, c->n_elite) > p->lds_limit)
+    return fail(PRIEST_ERR_INVALID, "n_samples too large for the selection kernel");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanArgs pa = plan_args(p, n_groups, bc, obs, c, mu, cov, seed, stream_base, noise, out,
+                          static_cast<char*>(workspace));
+  // one scene for every distribution
+  pa.a.bc_stride = 0;
+  pa.a.obs_stride = 0;
+  TileCfg cfg{};
+  st = plan_tiling(p, pa, n_groups, s, &cfg);
+  if (st != PRIEST_OK) return st;
+  st = enqueue_plan(n_groups, pa, c, noise, out, s);
+  if (st != PRIEST_OK) return st;
+  HIP_TRY(launch_pick_best(n_groups, p->D, out->best_xi, out->best_cost, best_xi, best_cost,
+                           best_group, s));
   return PRIEST_OK;
 }
 

@@ -360,6 +360,38 @@ hipError_t launch_cem_tasks(const CemTaskLaunch& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+// D-PRIEST pick: the group with the lowest final cost (NaN ranks last, ties
+// go to the lower group index) and a copy of its best trajectory.
+__global__ void pick_best_kernel(int G, int D, const float* xi, const float* cost, float* best_xi,
+                                 float* best_cost, int32_t* best_group) {
+  __shared__ int sb;
+  if (threadIdx.x == 0) {
+    int b = 0;
+    float bc = cost[0];
+    if (bc != bc) bc = INFINITY;
+    for (int g = 1; g < G; ++g) {
+      float c = cost[g];
+      if (c != c) c = INFINITY;
+      if (c < bc) {
+        bc = c;
+        b = g;
+      }
+    }
+    sb = b;
+    best_cost[0] = cost[b];
+    best_group[0] = b;
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < D; d += blockDim.x) best_xi[d] = xi[static_cast<int64_t>(sb) * D + d];
+}
+
+hipError_t launch_pick_best(int G, int D, const float* xi, const float* cost, float* best_xi,
+                            float* best_cost, int32_t* best_group, hipStream_t s) {
+  hipLaunchKernelGGL(pick_best_kernel, dim3(1), dim3(64), 0, s, G, D, xi, cost, best_xi, best_cost,
+                     best_group);
+  return hipGetLastError();
+}
+
 hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s) {
   const size_t lds = cem_layout(a.D, a.n_proj, a.n_elite).total;
   const dim3 grid(n_problems), block(kCemThreads);

@@ -100,6 +100,8 @@ void set_default_tiling(ProjArgs& a);  // 4 axis slots, 1 time block per wave, n
 hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s);
 size_t cem_lds_bytes(int N, int D, int n_elite);
 hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s);
+hipError_t launch_pick_best(int G, int D, const float* xi, const float* cost, float* best_xi,
+                            float* best_cost, int32_t* best_group, hipStream_t s);
 hipError_t launch_kkt(const double* Q, const double* A, int nv, int E, const int* rowsel,
                       double* out64, float* M11, float* Pi, float* M12, int* flag,
                       hipStream_t s);

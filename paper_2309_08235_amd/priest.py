@@ -40,7 +40,7 @@ EXPORTS = (
     "priest_server_stats_get", "priest_server_robot_state", "priest_server_destroy",
     "priest_tiling_candidates", "priest_set_tiling", "priest_last_tiling",
     "priest_profile_enable", "priest_profile_read", "priest_project_unfused_workspace_size",
-    "priest_project_unfused",
+    "priest_project_unfused", "priest_plan_dpriest",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -137,6 +137,9 @@ _SIGS = {
     "priest_plan_batch": (_I, [_P, _I, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
                                ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P, ctypes.c_size_t,
                                _I, _P]),
+    "priest_plan_dpriest": (_I, [_P, _I, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
+                                 ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P, _P, _P, _P,
+                                 ctypes.c_size_t, _P]),
     "priest_debug_offsets": (_I, [_P, _P, _P, _P, _I, _P, _P]),
     "priest_debug_normals": (_I, [ctypes.c_uint64, ctypes.c_uint32, _I, _I, _I, _P, _P]),
     "priest_debug_constants": (_I, [_P, _I, _P, _I]),
@@ -270,6 +273,16 @@ def priest_plan_batch(handle, n_problems, bc, obs, params: CemParams, mu, cov, s
                                    _ptr(mu), _ptr(cov), seed, stream_base, _ptr(noise),
                                    ctypes.byref(po), _ptr(workspace, torch.uint8),
                                    workspace.numel(), int(bool(use_graph)), _stream(stream)))
+
+
+def priest_plan_dpriest(handle, n_groups, bc, obs, params: CemParams, mu, cov, seed, stream_base,
+                        noise, out: dict, best_xi, best_cost, best_group, workspace, stream=None):
+    po = _plan_out(out)
+    _check(lib().priest_plan_dpriest(handle, n_groups, _ptr(bc), _ptr(obs), ctypes.byref(params),
+                                     _ptr(mu), _ptr(cov), seed, stream_base, _ptr(noise),
+                                     ctypes.byref(po), _ptr(best_xi), _ptr(best_cost),
+                                     _ptr(best_group, torch.int32), _ptr(workspace, torch.uint8),
+                                     workspace.numel(), _stream(stream)))
 
 
 def priest_debug_offsets(handle, bc, obs, xi, offsets, stream=None):
@@ -506,6 +519,20 @@ class Problem:
         ws = workspace if workspace is not None else self.workspace(cem)
         priest_plan(self.handle, bc, obs, cem.c(), mu, cov, seed, stream_id, noise, out, ws, stream)
         return out
+
+    def plan_dpriest(self, n_groups, bc, obs, cem: Cem, mu, cov, seed=0, stream_base=0,
+                     noise=None, out=None, workspace=None, stream=None, full=False):
+        """D-PRIEST on one scene: returns (best_xi [D], best_cost [1],
+        best_group [1], per-group outputs)."""
+        out = out if out is not None else self.plan_outputs(cem, n_groups, full=full)
+        ws = workspace if workspace is not None else self.workspace(cem, n_groups)
+        dev = mu.device
+        best_xi = torch.empty(self.D, device=dev, dtype=torch.float32)
+        best_cost = torch.empty(1, device=dev, dtype=torch.float32)
+        best_group = torch.empty(1, device=dev, dtype=torch.int32)
+        priest_plan_dpriest(self.handle, n_groups, bc, obs, cem.c(), mu, cov, seed, stream_base,
+                            noise, out, best_xi, best_cost, best_group, ws, stream)
+        return best_xi, best_cost, best_group, out
 
     def plan_batch(self, n_problems, bc, obs, cem: Cem, mu, cov, seed=0, stream_base=0,
                    noise=None, out=None, workspace=None, use_graph=False, stream=None):

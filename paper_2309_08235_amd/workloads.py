@@ -285,3 +285,24 @@ def serving_requests(wl: ServingWorkload = C5, n_requests: int | None = None,
                                   n_steps=K[r], horizon=T[r], n_proj=default_n_proj(n),
                                   n_elite=default_n_elite(n), bc=bc, obs=obs))
     return out
+
+
+def dpriest_means(wl: Workload, n_groups: int, spread: float = 1.5) -> np.ndarray:
+    """Initial means of D-PRIEST's distributions: the straight control
+    polygon of initial_mean() with its interior coefficients shifted
+    sideways (perpendicular to start->goal in the x-y plane) by
+    spread * (g - (G-1)/2), tapered to zero at both ends, so that the
+    distributions start in different homotopy classes.  [G, D]."""
+    base = initial_mean(wl).reshape(wl.dims, wl.n_coeff)
+    start = np.array(wl.start[:wl.dims], np.float64)
+    goal = np.array(wl.goal[:wl.dims], np.float64)
+    d = goal - start
+    nrm = np.zeros(wl.dims)
+    nrm[0], nrm[1] = -d[1], d[0]
+    nrm /= max(np.linalg.norm(nrm), 1e-12)
+    taper = np.sin(np.pi * np.arange(wl.n_coeff) / (wl.n_coeff - 1))
+    out = np.empty((n_groups, wl.D))
+    for g in range(n_groups):
+        off = spread * (g - (n_groups - 1) / 2.0)
+        out[g] = (base + off * nrm[:, None] * taper[None, :]).reshape(-1)
+    return out
