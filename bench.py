@@ -38,6 +38,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_kernel_c2_traffic.txt")
 KERNEL_SOURCES = ("paper_2309_08235_amd/csrc/project.hip", "paper_2309_08235_amd/csrc/priest_internal.h")
 
 
+def dense_flops(dims: int, nv: int, K: int) -> float:
+    """FLOPs of one projection iteration for one sample outside the obstacle
+    pairs: forward rows, velocity / acceleration push-outs, right-hand side,
+    multiplier and KKT product (see projection_flops)."""
+    return 12 * dims * nv * K + 2 * K * (2 * dims + 2) + dims * (5 * nv + 2 * nv * nv)
+
+
+def pair_flops(dims: int) -> float:
+    """FLOPs of one evaluated (sample, step, obstacle) pair."""
+    return 2 * dims + dims + 2 * dims + 1 + 1
+
+
 def projection_flops(dims: int, nv: int, K: int, M: int) -> float:
     """Algorithmic FLOPs of one projection iteration for one sample (every
     obstacle pair counted at its no-contact cost; pairs the kernel skips by
@@ -118,15 +130,29 @@ def cpu_baseline(wl, n_sample: int, gpu_results=None):
             "gpu_error_vs_oracle": errors}
 
 
-def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note):
-    flops = projection_flops(wl.dims, wl.n_coeff, wl.n_steps, wl.n_obs) * n_samples_per_launch * \
-        wl.n_proj_iters
+def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note, pairs_per_launch):
+    """Roofline of the fused projection kernel.  The work per launch is the
+    dense part (per sample and iteration, plus the forward rows of the final
+    residual pass) and the obstacle pairs the kernel evaluated, counted on
+    the device (pairs dropped by culling contribute exact zeros and are not
+    work the kernel does).  The brute-force figure, every pair at every step,
+    is reported beside it."""
+    n, it = n_samples_per_launch, wl.n_proj_iters
+    dense = dense_flops(wl.dims, wl.n_coeff, wl.n_steps) * n * it + \
+        6 * wl.dims * wl.n_coeff * wl.n_steps * n
+    flops = dense + pair_flops(wl.dims) * pairs_per_launch
+    brute = projection_flops(wl.dims, wl.n_coeff, wl.n_steps, wl.n_obs) * n * it
+    all_pairs = n * wl.n_steps * wl.n_obs * (it + 1)
     achieved = flops / (avg_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "kernel": f"project_kernel<{wl.dims}D, tiling {tuple(tiling)}>",
             "kernel_ms": round(avg_ms, 4), "launches": launches,
-            "flops_per_launch": flops, "timing": note}
+            "flops_per_launch": flops, "pairs_evaluated_per_launch": pairs_per_launch,
+            "pairs_evaluated_frac": round(pairs_per_launch / all_pairs, 5) if all_pairs else None,
+            "brute_force_flops_per_launch": brute,
+            "brute_force_equiv_tflops": round(brute / (avg_ms * 1e-3) / 1e12, 3),
+            "timing": note}
 
 
 def batched(P, W, wl, steps: int, plain_problems: int):
@@ -174,9 +200,15 @@ def batched(P, W, wl, steps: int, plain_problems: int):
         s.synchronize()
         P.priest_profile_enable(False)
         n_l, ms = P.priest_profile_read()
+        # evaluated pairs of the same launches (same draws: identical work)
+        P.priest_profile_count_pairs(True)
+        batch_step(graph=False)
+        pairs = P.priest_profile_read_pairs()
+        P.priest_profile_count_pairs(False)
     assert int(out["status"].abs().sum().item()) == 0
     roof = roofline_entry(wl, nP * wl.n_samples, ms / n_l, n_l, tiling[0],
-                          "HIP events around each projection launch of one batched plan (no graph)")
+                          "HIP events around each projection launch of one batched plan (no graph)",
+                          pairs / n_l)
     # plain: one problem per launch, no graph, default tile shape
     prob.set_tiling((4, 1, 0))
     out1 = prob.plan_outputs(cem, 1, full=False)
@@ -443,6 +475,13 @@ def main():
     P.priest_profile_enable(False)
     n_launch, k_total_ms = P.priest_profile_read()
     lat = np.array([a.elapsed_time(b) for a, b in ev])          # ms per plan
+    # evaluated obstacle pairs of the same plans, re-run outside the timed
+    # region with the same draws (the work is deterministic)
+    P.priest_profile_count_pairs(True)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    pairs_total = P.priest_profile_read_pairs()
+    P.priest_profile_count_pairs(False)
     status = int(out["status"][0].item())
     best = float(out["best_cost"][0].item())
     assert status == 0 and np.isfinite(best), (status, best)
@@ -452,7 +491,7 @@ def main():
     value = per_plan * args.steps / wall
     roofline = roofline_entry(wl, wl.n_samples, k_total_ms / n_launch, n_launch, tiling[0],
                               "HIP events on the plan's stream around every projection launch "
-                              "inside the timed region")
+                              "inside the timed region", pairs_total / n_launch)
     roofline["traffic"] = measured_traffic()
     roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE "
                                 "(profiles/project_kernel_c2_traffic.txt), null if the kernel "

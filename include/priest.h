@@ -238,6 +238,18 @@ int32_t priest_last_tiling(const priest_problem* p, priest_tiling* out, int32_t*
 int32_t priest_profile_enable(int32_t on);
 int32_t priest_profile_read(int32_t* n_launches, double* total_ms);
 
+/* Work counter of the same launches.  While on (process-wide, first enabled
+ * on the current device, which it stays bound to), every fused projection
+ * launch made outside graph capture adds to one device counter the number
+ * of (sample, time step, obstacle) pairs whose push-out it evaluated, over
+ * all its iterations and the final residual pass; pairs skipped by the
+ * obstacle culling (whose push-out is exactly zero) are not counted.
+ * Enabling zeroes the counter.  priest_profile_read_pairs synchronises the
+ * device, returns the count since the last read or enable (host pointer)
+ * and zeroes it.  Errors: INVALID, DEVICE. */
+int32_t priest_profile_count_pairs(int32_t on);
+int32_t priest_profile_read_pairs(uint64_t* pairs);
+
 /* D-PRIEST (Sec. III-C): n_groups Gaussians (mu [G][D], cov [G][D][D], read
  * and overwritten like priest_plan) each draw c->n_samples samples on ONE
  * scene (bc [dims][6], obs [n_obs][8] shared by all groups).  Every CEM

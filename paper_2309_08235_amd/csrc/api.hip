@@ -212,6 +212,9 @@ struct Profiler {
   std::mutex mu;
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, pool;
+  bool count_pairs = false;
+  unsigned long long* pairs_dev = nullptr;  // device counter, kept until exit
+  int pairs_device = -1;
 };
 Profiler& profiler() {
   static Profiler* p = new Profiler();  // lives until exit
@@ -223,8 +226,10 @@ Profiler& profiler() {
 hipError_t launch_project_timed(const ProjArgs& a, int P, hipStream_t s) {
   Profiler& pr = profiler();
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  ProjArgs b = a;
   {
     std::lock_guard<std::mutex> lk(pr.mu);
+    if (pr.count_pairs && !stream_capturing(s)) b.pair_count = pr.pairs_dev;
     if (pr.on && !stream_capturing(s)) {
       if (!pr.pool.empty()) {
         ev = pr.pool.back();
@@ -240,7 +245,7 @@ hipError_t launch_project_timed(const ProjArgs& a, int P, hipStream_t s) {
     const hipError_t e = hipEventRecord(ev.first, s);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = launch_project(a, P, s);
+  hipError_t e = launch_project(b, P, s);
   if (ev.first) {
     if (e == hipSuccess) e = hipEventRecord(ev.second, s);
     std::lock_guard<std::mutex> lk(pr.mu);
@@ -752,6 +757,38 @@ int32_t priest_profile_enable(int32_t on) {
   Profiler& pr = profiler();
   std::lock_guard<std::mutex> lk(pr.mu);
   pr.on = on != 0;
+  return PRIEST_OK;
+}
+
+int32_t priest_profile_count_pairs(int32_t on) {
+  Profiler& pr = profiler();
+  std::lock_guard<std::mutex> lk(pr.mu);
+  if (on) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (pr.pairs_dev && pr.pairs_device != dev)
+      return fail(PRIEST_ERR_INVALID, "pair counting was first enabled on device %d", pr.pairs_device);
+    if (!pr.pairs_dev) {
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&pr.pairs_dev), sizeof(unsigned long long)));
+      pr.pairs_device = dev;
+    }
+    HIP_TRY(hipMemset(pr.pairs_dev, 0, sizeof(unsigned long long)));
+  }
+  pr.count_pairs = on != 0;
+  return PRIEST_OK;
+}
+
+int32_t priest_profile_read_pairs(uint64_t* pairs) {
+  if (!pairs) return fail(PRIEST_ERR_INVALID, "pairs is required");
+  Profiler& pr = profiler();
+  std::lock_guard<std::mutex> lk(pr.mu);
+  *pairs = 0;
+  if (!pr.pairs_dev) return PRIEST_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  unsigned long long v = 0;
+  HIP_TRY(hipMemcpy(&v, pr.pairs_dev, sizeof(v), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(pr.pairs_dev, 0, sizeof(unsigned long long)));
+  *pairs = v;
   return PRIEST_OK;
 }
 

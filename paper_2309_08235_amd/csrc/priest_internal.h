@@ -56,6 +56,9 @@ struct ProjArgs {
   float* xi_src; int64_t xi_src_stride;    // drawn samples, nullable
   // optional second copies (caller outputs, dense [problem][N] / [problem][N][D])
   float* resid2; float* c12; float* xi_out2;
+  // profiling: (item, obstacle) pairs evaluated after culling, summed over
+  // the launch (nullable)
+  unsigned long long* pair_count;
 };
 
 // Arguments of the selection / refit / Cholesky kernel (one block per problem).

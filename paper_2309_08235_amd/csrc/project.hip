@@ -373,6 +373,8 @@ struct CullCache {
   float pref[NI][DIMS];
   float lim2;
   bool valid;
+  uint32_t nok;    // valid items of the wave (wave-uniform)
+  uint32_t pairs;  // (item, obstacle) pairs evaluated by the wave so far
 };
 
 // Growth of the candidate radius that lets a candidate set be reused: an
@@ -463,6 +465,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     cc.valid = true;
     wave_lds_sync();
   }
+  uint32_t ncand = 0;
   for (int base = 0, g = 0; base < M; base += 64, ++g) {
     const uint4 m4 = *reinterpret_cast<const uint4*>(wm + 4 * g);
     // (readfirstlane returns int: widen through uint32_t, not sign-extended)
@@ -472,6 +475,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
               << 32);
     };
     const unsigned long long cmask = u64(m4.x, m4.y);
+    ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
     if (!cmask) continue;
     const unsigned long long mvmask = u64(m4.z, m4.w);
     const int j = base + lane;
@@ -515,6 +519,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     run(cmask & ~mvmask, std::false_type{});
     run(mvmask, std::true_type{});
   }
+  cc.pairs += ncand * cc.nok;
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (!ok[i]) {
@@ -723,6 +728,10 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
     CullCache<NI, DIMS> cull;
     cull.valid = false;
+    cull.pairs = 0;
+    cull.nok = 0;
+#pragma unroll
+    for (int n = 0; n < NI; ++n) cull.nok += static_cast<uint32_t>(__builtin_popcountll(__ballot(item_ok[n])));
 
     // ---- projection iterations ---------------------------------------------------
     for (int k = 0; k < a.n_iter; ++k) {
@@ -881,6 +890,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       if (a.resid2) a.resid2[dense] = r;
       if (a.c12) a.c12[dense] = cc;
     }
+    if (a.pair_count && lane == 0) atomicAdd(a.pair_count, static_cast<unsigned long long>(cull.pairs));
     if (w == 0 && colok) {
       float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0 + cs) * D + cx * nv;
       float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0 + cs) * D + cx * nv

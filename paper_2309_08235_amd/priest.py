@@ -40,7 +40,8 @@ EXPORTS = (
     "priest_server_stats_get", "priest_server_robot_state", "priest_server_destroy",
     "priest_tiling_candidates", "priest_set_tiling", "priest_last_tiling",
     "priest_profile_enable", "priest_profile_read", "priest_project_unfused_workspace_size",
-    "priest_project_unfused", "priest_plan_dpriest",
+    "priest_project_unfused", "priest_plan_dpriest", "priest_profile_count_pairs",
+    "priest_profile_read_pairs",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -161,6 +162,8 @@ _SIGS = {
     "priest_project_unfused": (_I, [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "priest_profile_enable": (_I, [_I]),
     "priest_profile_read": (_I, [ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
+    "priest_profile_count_pairs": (_I, [_I]),
+    "priest_profile_read_pairs": (_I, [ctypes.POINTER(ctypes.c_uint64)]),
     "priest_last_error": (ctypes.c_char_p, []),
     "priest_version": (_I, []),
 }
@@ -335,6 +338,18 @@ def priest_profile_read():
     ms = ctypes.c_double()
     _check(lib().priest_profile_read(ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def priest_profile_count_pairs(on: bool):
+    _check(lib().priest_profile_count_pairs(1 if on else 0))
+
+
+def priest_profile_read_pairs() -> int:
+    """(sample, step, obstacle) pairs evaluated by fused projection launches
+    since the previous read (synchronises the device)."""
+    v = ctypes.c_uint64()
+    _check(lib().priest_profile_read_pairs(ctypes.byref(v)))
+    return v.value
 
 
 def priest_server_now() -> float:
