@@ -39,7 +39,12 @@ Readings of passages that are silent, ambiguous or garbled in the paper:
   (with the printed sign the worst elite would get the largest weight);
 * covariance Cholesky jitter: eps = cov_jitter * tr(Sigma)/D added to the
   diagonal before factorising (elites lie on {A xi = b}, so Sigma loses rank);
-* selection ties broken by sample index (stable sort), NaN ranked as +inf.
+* selection ties broken by sample index (stable sort), NaN ranked as +inf;
+* workspace bounds (Appendix, G xi_bar <= tau): G stacks -P over P for every
+  axis and tau stacks -s_min over s_max of that axis; the slack step and the
+  bound rows' targets use the same iterate as the other closed forms, so the
+  targets of the rows are min(tau, G xi_bar^k); the rows enter F (hence
+  I + rho F^T F) whenever bounds are enabled, also for infinite limits.
 
 Parity status: every function below is pinned by tests in tests/ against
 closed forms, brute force, invariances or published known answers.
@@ -125,13 +130,31 @@ class Problem:
     v_max: float = math.inf
     a_max: float = math.inf
     bc_mask: int = BC_DEFAULT
+    s_min: tuple = None     # workspace bounds per axis (Appendix, G xi <= tau); None: off
+    s_max: tuple = None
     P: np.ndarray = field(init=False, repr=False)
     Pd: np.ndarray = field(init=False, repr=False)
     Pdd: np.ndarray = field(init=False, repr=False)
 
     def __post_init__(self):
         assert self.dims in (2, 3)
+        assert (self.s_min is None) == (self.s_max is None)
         self.P, self.Pd, self.Pdd = basis_matrices(self.n_coeff, self.n_steps, self.horizon)
+
+    @property
+    def bounded(self) -> bool:
+        return self.s_min is not None
+
+    @property
+    def n_rows_axis(self) -> int:
+        """Rows of F per axis: n_obs position blocks, velocity, acceleration,
+        and the two blocks of G when workspace bounds are on."""
+        return (self.n_obs + 2 + (2 if self.bounded else 0)) * self.n_steps
+
+    def tau(self, ax: int) -> np.ndarray:
+        """tau of G xi <= tau for one axis: [-s_min] * K over [s_max] * K."""
+        K = self.n_steps
+        return np.concatenate([np.full(K, -float(self.s_min[ax])), np.full(K, float(self.s_max[ax]))])
 
     @property
     def D(self) -> int:
@@ -156,7 +179,10 @@ class Problem:
 
     # -- eq. (13) and the definition below eq. (14): dense F ----------------
     def F_axis(self) -> np.ndarray:
-        return np.vstack([self.P] * self.n_obs + [self.Pd, self.Pdd])
+        blocks = [self.P] * self.n_obs + [self.Pd, self.Pdd]
+        if self.bounded:
+            blocks += [-self.P, self.P]          # G
+        return np.vstack(blocks)
 
     def F(self) -> np.ndarray:
         return _block_diag(self.F_axis(), self.dims)
@@ -191,10 +217,10 @@ def split_rows(prob: Problem, y: np.ndarray):
     """Split F xi_bar ([..., R]) into per-axis obstacle rows [..., dims, n_obs, K],
     velocity rows [..., dims, K] and acceleration rows [..., dims, K]."""
     K, no = prob.n_steps, prob.n_obs
-    y = y.reshape(y.shape[:-1] + (prob.dims, (no + 2) * K))
+    y = y.reshape(y.shape[:-1] + (prob.dims, prob.n_rows_axis))
     yo = y[..., :no * K].reshape(y.shape[:-1] + (no, K))
     yv = y[..., no * K:(no + 1) * K]
-    ya = y[..., (no + 1) * K:]
+    ya = y[..., (no + 1) * K:(no + 2) * K]
     return yo, yv, ya
 
 
@@ -250,7 +276,7 @@ def targets(prob: Problem, obs: np.ndarray, xi_bar: np.ndarray) -> np.ndarray:
     N = xi_bar.shape[0]
     dims, K, no = prob.dims, prob.n_steps, prob.n_obs
     yo, yv, ya = split_rows(prob, y)
-    e = np.zeros((N, dims, (no + 2) * K))
+    e = np.zeros((N, dims, prob.n_rows_axis))
     obs = np.asarray(obs, np.float64).reshape(-1, 8)
     if no > 0:
         p = yo[:, :, 0, :]  # every F_o block row reproduces the position P c
@@ -270,6 +296,14 @@ def targets(prob: Problem, obs: np.ndarray, xi_bar: np.ndarray) -> np.ndarray:
         u = _direction(alpha, beta, dims)
         for ax in range(dims):
             e[:, ax, rows] = d * wmax * u[ax]
+    if prob.bounded:
+        # slack s = max(0, tau - G xi_bar) (the minimiser over s >= 0), and the
+        # rows' targets tau - s
+        yg = y.reshape(N, dims, prob.n_rows_axis)[:, :, (no + 2) * K:]
+        for ax in range(dims):
+            tau = prob.tau(ax)
+            slack = np.maximum(0.0, tau[None, :] - yg[:, ax])
+            e[:, ax, (no + 2) * K:] = tau[None, :] - slack
     return e.reshape(N, -1)
 
 
@@ -352,7 +386,8 @@ def residual(prob: Problem, obs: np.ndarray, xi_bar: np.ndarray) -> np.ndarray:
     zero when every constraint of eq. (1) holds on the grid:
 
       r^2 = sum_{j,k} ||p_k - o_j(t_k)||^2 max(0, 1/n_jk - 1)^2
-          + sum_k max(0, ||v_k|| - v_max)^2 + sum_k max(0, ||a_k|| - a_max)^2,
+          + sum_k max(0, ||v_k|| - v_max)^2 + sum_k max(0, ||a_k|| - a_max)^2
+          [+ sum_{k,x} max(0, s_min,x - p_k,x)^2 + max(0, p_k,x - s_max,x)^2],
 
     with n_jk the scaled distance sqrt((dx^2+dy^2)/a^2 + dz^2/b^2).  Each term
     is the squared length of one row block of F xi_bar - e(xi_bar); a zero
@@ -384,6 +419,10 @@ def residual(prob: Problem, obs: np.ndarray, xi_bar: np.ndarray) -> np.ndarray:
     for w, wmax in ((v, prob.v_max), (a, prob.a_max)):
         nrm = np.sqrt(np.sum(w ** 2, axis=1))
         r2 += np.sum(np.maximum(0.0, nrm - wmax) ** 2, axis=1)
+    if prob.bounded:
+        lo = np.asarray(prob.s_min, np.float64)[None, :, None]
+        hi = np.asarray(prob.s_max, np.float64)[None, :, None]
+        r2 += np.sum(np.maximum(0.0, lo - p) ** 2 + np.maximum(0.0, p - hi) ** 2, axis=(1, 2))
     return np.sqrt(r2)
 
 
