@@ -83,7 +83,11 @@ typedef struct priest_problem_desc {
   uint32_t bc_mask;      /* PRIEST_BC_* rows; at most n_coeff rows, full rank */
   int32_t precision;     /* PRIEST_FP32 or PRIEST_BF16_MIXED */
   int32_t n_refine_fp32; /* PRIEST_BF16_MIXED: trailing iterations run in FP32 */
-  int32_t reserved;      /* must be 0 */
+  int32_t use_bounds;    /* 0 or 1: workspace bounds s_min <= p(t_k) <= s_max per axis
+                            (Appendix, G xi <= tau with G = [-P; P]); their rows enter
+                            I + rho F^T F, so they are part of the problem */
+  double s_min[3];       /* use_bounds: lower limits per axis (-inf allowed), <= s_max */
+  double s_max[3];       /* use_bounds: upper limits per axis (+inf allowed) */
 } priest_problem_desc;
 
 /* Sampling-loop settings (Alg. 1, eqs. (9a)-(9c)). */

@@ -129,7 +129,11 @@ int32_t validate_desc(const priest_problem_desc* d) {
   if (d->precision != PRIEST_FP32 && d->precision != PRIEST_BF16_MIXED)
     return fail(PRIEST_ERR_INVALID, "unknown precision");
   if (d->n_refine_fp32 < 0) return fail(PRIEST_ERR_INVALID, "n_refine_fp32 must be >= 0");
-  if (d->reserved != 0) return fail(PRIEST_ERR_INVALID, "reserved must be 0");
+  if (d->use_bounds != 0 && d->use_bounds != 1) return fail(PRIEST_ERR_INVALID, "use_bounds must be 0 or 1");
+  if (d->use_bounds)
+    for (int x = 0; x < d->dims; ++x)
+      if (std::isnan(d->s_min[x]) || std::isnan(d->s_max[x]) || !(d->s_min[x] <= d->s_max[x]))
+        return fail(PRIEST_ERR_INVALID, "workspace bounds of axis %d need s_min <= s_max", x);
   int E = 0;
   for (int i = 0; i < 6; ++i) E += (d->bc_mask >> i) & 1;
   if (E > d->n_coeff)
@@ -167,6 +171,11 @@ ProjArgs base_args(const priest_problem* p) {
   a.dt = static_cast<float>(d.horizon / (d.n_steps - 1));
   a.vmax = static_cast<float>(d.v_max);
   a.amax = static_cast<float>(d.a_max);
+  a.box.on = d.use_bounds;
+  for (int x = 0; x < 3; ++x) {
+    a.box.lo[x] = d.use_bounds ? static_cast<float>(d.s_min[x]) : -INFINITY;
+    a.box.hi[x] = d.use_bounds ? static_cast<float>(d.s_max[x]) : INFINITY;
+  }
   a.bf16_iters = 0;
   a.W = p->dW;
   a.M11 = p->dM11;
@@ -486,13 +495,15 @@ int32_t priest_init_problem(const priest_problem_desc* desc, void* stream, pries
                                  : 0.0;
     }
   }
-  // Q = I + rho (n_obs P^T P + Pdot^T Pdot + Pddot^T Pddot)
+  // Q = I + rho (n_pos P^T P + Pdot^T Pdot + Pddot^T Pddot): n_pos counts the
+  // position blocks of F, one per obstacle plus -P and P of the bounds
+  const double n_pos = d.n_obs + (d.use_bounds ? 2.0 : 0.0);
   std::vector<double> Q(nv * nv, 0.0);
   for (int i = 0; i < nv; ++i)
     for (int j = 0; j < nv; ++j) {
       double s = 0.0;
       for (int k = 0; k < K; ++k)
-        s += d.n_obs * P[k * nv + i] * P[k * nv + j] + Pd[k * nv + i] * Pd[k * nv + j] +
+        s += n_pos * P[k * nv + i] * P[k * nv + j] + Pd[k * nv + i] * Pd[k * nv + j] +
              Pdd[k * nv + i] * Pdd[k * nv + j];
       Q[i * nv + j] = (i == j ? 1.0 : 0.0) + d.rho * s;
     }

@@ -24,6 +24,12 @@ enum SampleMode : int32_t {
 // Arguments of the fused projection kernel.  One launch covers
 // n_problems * blocks_per_problem tiles; tile b works on problem
 // b / blocks_per_problem, samples [tile*S, tile*S + S) of it.
+// Workspace bounds s_min <= p <= s_max per axis (Appendix, G xi <= tau).
+struct Box {
+  int32_t on;
+  float lo[3], hi[3];
+};
+
 struct ProjArgs {
   int32_t dims, nv, K, M, N;
   int32_t S;                   // samples per block = 16 / axis_slots
@@ -38,6 +44,7 @@ struct ProjArgs {
   uint32_t stream_base;        // Philox counter word 3 = stream_base + problem
   uint64_t seed;               // Philox key
   float rho, dt, vmax, amax;   // vmax/amax may be +inf
+  Box box;                     // workspace bounds (box.on = 0: none)
   // problem constants (shared by all problems of the launch)
   const float* W;    // [K][3][nv] rows of P, Pdot, Pddot
   const float* M11;  // [nv][nv]

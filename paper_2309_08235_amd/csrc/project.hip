@@ -533,9 +533,10 @@ template <int DIMS, bool LAST, int NI>
 __device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI], float tmid,
                                           float thalf, const bool ok[NI], const float p[NI][DIMS],
                                           const float v[NI][DIMS], const float ac[NI][DIMS],
-                                          float vmax, float amax, float S[NI][DIMS],
-                                          float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
-                                          int lane, CullCache<NI, DIMS>& cc, uint32_t* wm) {
+                                          float vmax, float amax, const Box& box,
+                                          float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS],
+                                          float r2[NI], int lane, CullCache<NI, DIMS>& cc,
+                                          uint32_t* wm) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
@@ -549,6 +550,20 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
       r2[i] += bound_push<DIMS>(v[i], vmax, dv[i]);
       r2[i] += bound_push<DIMS>(ac[i], amax, da[i]);
     }
+  // workspace bounds: rows -P and P of G, whose targets min(tau, G xi_bar)
+  // add clamp(p, lo, hi) - p to the position rows
+  if (box.on) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      if (ok[i]) {
+#pragma unroll
+        for (int x = 0; x < DIMS; ++x) {
+          const float e = fminf(fmaxf(p[i][x], box.lo[x]), box.hi[x]) - p[i][x];
+          S[i][x] += e;
+          r2[i] = fmaf(e, e, r2[i]);
+        }
+      }
+  }
 }
 
 // One block's work: whole projections of tiles first, first + stride, ...
@@ -740,7 +755,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       forward(p, v, ac);
       PRIEST_PROJ_MARK(1);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-      item_push<DIMS, false, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv,
+      item_push<DIMS, false, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
                                  da, r2, lane, cull, wm);
       PRIEST_PROJ_MARK(2);
       // back to the column layout: slot AS*i + x of the lane's f4 holds axis x
@@ -860,7 +875,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS];
       forward(p, v, ac);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-      item_push<DIMS, true, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, S, dv,
+      item_push<DIMS, true, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
                                 da, r2, lane, cull, wm);
       float* fin = sm + l.fin;
   #pragma unroll

@@ -51,8 +51,8 @@ __global__ void uf_forward(const float* __restrict__ W, const float* __restrict_
 
 template <int DIMS, bool LAST>
 __global__ void uf_push(const float* __restrict__ pva, const float* __restrict__ obs, int N, int K,
-                        int M, float dt, float vmax, float amax, float* __restrict__ delta,
-                        float* __restrict__ r2out) {
+                        int M, float dt, float vmax, float amax, Box box,
+                        float* __restrict__ delta, float* __restrict__ r2out) {
   extern __shared__ ORec orec[];
   for (int j = threadIdx.x; j < M; j += blockDim.x) {
     const float* o = obs + 8 * j;
@@ -108,6 +108,12 @@ __global__ void uf_push(const float* __restrict__ pva, const float* __restrict__
       }
     }
   }
+  if (box.on)  // workspace bounds: clamp(p, lo, hi) - p on the position rows
+    for (int x = 0; x < DIMS; ++x) {
+      const float e = fminf(fmaxf(p[x], box.lo[x]), box.hi[x]) - p[x];
+      S[x] += e;
+      if (LAST) r2 = fmaf(e, e, r2);
+    }
   float* out = delta + static_cast<int64_t>(sm) * 3 * DIMS * K + t;
   for (int x = 0; x < DIMS; ++x) out[x * K] = S[x];
   for (int k = 0; k < 2; ++k) {
@@ -264,11 +270,11 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
   hipLaunchKernelGGL(uf_init, g_nD, b256, 0, s, xi_in, xb, lam, nD);
   auto push = [&](bool last) {
     if (dims == 2) {
-      if (last) hipLaunchKernelGGL((uf_push<2, true>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, delta, r2);
-      else hipLaunchKernelGGL((uf_push<2, false>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, delta, r2);
+      if (last) hipLaunchKernelGGL((uf_push<2, true>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
+      else hipLaunchKernelGGL((uf_push<2, false>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
     } else {
-      if (last) hipLaunchKernelGGL((uf_push<3, true>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, delta, r2);
-      else hipLaunchKernelGGL((uf_push<3, false>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, delta, r2);
+      if (last) hipLaunchKernelGGL((uf_push<3, true>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
+      else hipLaunchKernelGGL((uf_push<3, false>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
     }
   };
   for (int k = 0; k < a.n_iter; ++k) {

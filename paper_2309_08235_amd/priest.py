@@ -54,7 +54,8 @@ class ProblemDesc(ctypes.Structure):
                 ("horizon", ctypes.c_double), ("rho", ctypes.c_double),
                 ("v_max", ctypes.c_double), ("a_max", ctypes.c_double),
                 ("bc_mask", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("n_refine_fp32", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_refine_fp32", ctypes.c_int32), ("use_bounds", ctypes.c_int32),
+                ("s_min", ctypes.c_double * 3), ("s_max", ctypes.c_double * 3)]
 
 
 class CemParams(ctypes.Structure):
@@ -439,9 +440,15 @@ class Problem:
 
     def __init__(self, dims, n_coeff, n_steps, horizon, n_obs, rho=1.0, v_max=math.inf,
                  a_max=math.inf, bc_mask=BC_DEFAULT, precision=FP32, n_refine_fp32=10,
-                 stream=None):
+                 s_min=None, s_max=None, stream=None):
+        """s_min / s_max (per axis, both or neither): workspace bounds."""
+        if (s_min is None) != (s_max is None):
+            raise ValueError("give both s_min and s_max, or neither")
+        lo = (ctypes.c_double * 3)(*(list(s_min or ()) + [0.0] * 3)[:3])
+        hi = (ctypes.c_double * 3)(*(list(s_max or ()) + [0.0] * 3)[:3])
         self.desc = ProblemDesc(dims, n_coeff, n_steps, n_obs, horizon, rho, v_max, a_max,
-                                bc_mask, precision, n_refine_fp32, 0)
+                                bc_mask, precision, n_refine_fp32, 0 if s_min is None else 1,
+                                lo, hi)
         self.dims, self.n_coeff, self.n_steps, self.n_obs = dims, n_coeff, n_steps, n_obs
         self.D = dims * n_coeff
         self.handle = priest_init_problem(self.desc, stream)

@@ -34,8 +34,11 @@ def test_exports_every_declared_symbol(P):
 
 
 def _desc(P, **kw):
+    for k in ("s_min", "s_max"):
+        if k in kw:
+            kw[k] = (ctypes.c_double * 3)(*kw[k])
     d = dict(dims=2, n_coeff=11, n_steps=50, n_obs=4, horizon=10.0, rho=1.0, v_max=1.5,
-             a_max=2.0, bc_mask=P.BC_DEFAULT, precision=0, n_refine_fp32=0, reserved=0)
+             a_max=2.0, bc_mask=P.BC_DEFAULT, precision=0, n_refine_fp32=0, use_bounds=0)
     d.update(kw)
     return P.ProblemDesc(**d)
 
@@ -45,8 +48,10 @@ def _desc(P, **kw):
     (dict(n_steps=257), -1), (dict(n_obs=-1), -1), (dict(horizon=0.0), -1),
     (dict(horizon=math.nan), -1), (dict(rho=-1.0), -1), (dict(rho=math.inf), -1),
     (dict(v_max=0.0), -1), (dict(v_max=math.nan), -1), (dict(a_max=-2.0), -1),
-    (dict(bc_mask=64), -1), (dict(precision=7), -1), (dict(reserved=1), -1),
+    (dict(bc_mask=64), -1), (dict(precision=7), -1), (dict(use_bounds=2), -1),
     (dict(n_coeff=3, bc_mask=63), -2),
+    (dict(use_bounds=1, s_min=(1.0, 0.0, 0.0), s_max=(0.0, 1.0, 1.0)), -1),
+    (dict(use_bounds=1, s_min=(0.0, math.nan, 0.0), s_max=(1.0, 1.0, 1.0)), -1),
 ])
 def test_init_rejects_invalid_desc_on_host(P, bad, code):
     h = ctypes.c_void_p()
