@@ -34,7 +34,11 @@ Readings of passages that are silent, ambiguous or garbled in the paper:
   F xi_bar - e(xi_bar), evaluated with max(0, .) violation terms so that it is
   exactly zero for a trajectory that satisfies every constraint on the grid;
 * cost: c1 = sum_k ||a_k||^2 (point-to-point smoothness, Sec. V-A) and
-  c_aug = c1 + r (Alg. 1);
+  c_aug = c1 + r (Alg. 1); the optional navigation terms (Sec. V) are a
+  curvature |v x a| / (|v|^2 + eps)^(3/2) squared, the Euclidean distance of
+  each way-point to the start-goal segment (projection clamped to the
+  segment, not squared), and the squared steering angle atan(L kappa) of a
+  car-like robot (2D, signed curvature), summed over the grid;
 * weight sign in eq. (9c): exp(-(c_aug - delta)/gamma), the MPPI convention
   (with the printed sign the worst elite would get the largest weight);
 * covariance Cholesky jitter: eps = cov_jitter * tr(Sigma)/D added to the
@@ -435,6 +439,76 @@ def smoothness_cost(prob: Problem, xi_bar: np.ndarray) -> np.ndarray:
     return np.sum(a ** 2, axis=(1, 2))
 
 
+@dataclass
+class Cost:
+    """Weights of c1 (Sec. II remark that c1 need not be smooth; the navigation
+    and steering costs of Sec. V).  kind 0: the smoothness cost sum ||a||^2;
+    kind 1: the weighted sum of the terms of trajectory_cost."""
+    kind: int = 0
+    w_acc: float = 1.0
+    w_curv: float = 0.0
+    w_path: float = 0.0
+    w_steer: float = 0.0
+    wheelbase: float = 1.0
+    eps: float = 1e-2
+
+
+def curvature(v: np.ndarray, a: np.ndarray, eps: float, signed: bool = False) -> np.ndarray:
+    """kappa_k of a trajectory from its velocity and acceleration rows
+    ([N, dims, K]): |v x a| / (|v|^2 + eps)^(3/2), with eps keeping it finite
+    at rest.  signed (2D): (v_x a_y - v_y a_x) / (|v|^2 + eps)^(3/2)."""
+    s2 = np.sum(v ** 2, axis=1) + eps
+    if v.shape[1] == 2:
+        cr = v[:, 0] * a[:, 1] - v[:, 1] * a[:, 0]
+        num = cr if signed else np.abs(cr)
+    else:
+        assert not signed
+        cr = np.cross(np.moveaxis(v, 1, -1), np.moveaxis(a, 1, -1))
+        num = np.linalg.norm(cr, axis=-1)
+    return num / s2 ** 1.5
+
+
+def segment_distance(p: np.ndarray, start: np.ndarray, goal: np.ndarray) -> np.ndarray:
+    """Euclidean distance of every way-point p [N, dims, K] to the segment
+    start -> goal: the projection onto the line, clamped to the segment."""
+    u = goal - start
+    uu = float(np.dot(u, u))
+    rel = p - start[None, :, None]
+    if uu == 0.0:
+        return np.sqrt(np.sum(rel ** 2, axis=1))
+    lam = np.clip(np.einsum('ndk,d->nk', rel, u) / uu, 0.0, 1.0)
+    q = rel - lam[:, None, :] * u[None, :, None]
+    return np.sqrt(np.sum(q ** 2, axis=1))
+
+
+def trajectory_cost(prob: Problem, bc: np.ndarray, xi_bar: np.ndarray, cost: Cost = None) -> np.ndarray:
+    """c1 of every projected sample.  kind 0 (or no cost): sum_k ||a_k||^2.
+    kind 1: sum_k [w_acc ||a_k||^2 + w_curv kappa_k^2 + w_path dist(p_k, segment)
+    + w_steer atan(wheelbase * kappa_signed,k)^2], the last in 2D only (car-like
+    steering angle from differential flatness); start and goal of the segment
+    are the boundary values p0 and pf of bc."""
+    if cost is None or cost.kind == 0:
+        return smoothness_cost(prob, xi_bar)
+    N = xi_bar.shape[0]
+    C = np.asarray(xi_bar, np.float64).reshape(N, prob.dims, prob.n_coeff)
+    p = np.einsum('kc,nac->nak', prob.P, C)
+    v = np.einsum('kc,nac->nak', prob.Pd, C)
+    a = np.einsum('kc,nac->nak', prob.Pdd, C)
+    bc = np.asarray(bc, np.float64)
+    out = np.zeros(N)
+    if cost.w_acc:
+        out += cost.w_acc * np.sum(a ** 2, axis=(1, 2))
+    if cost.w_curv:
+        out += cost.w_curv * np.sum(curvature(v, a, cost.eps) ** 2, axis=1)
+    if cost.w_path:
+        out += cost.w_path * np.sum(segment_distance(p, bc[:, 0], bc[:, 3]), axis=1)
+    if cost.w_steer:
+        assert prob.dims == 2
+        delta = np.arctan(cost.wheelbase * curvature(v, a, cost.eps, signed=True))
+        out += cost.w_steer * np.sum(delta ** 2, axis=1)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Alg. 1 selection and eqs. (9a)-(9c) refit
 # ---------------------------------------------------------------------------
@@ -476,6 +550,7 @@ class CemParams:
     sigma: float = 0.5
     gamma: float = 1.0
     cov_jitter: float = 1e-5
+    cost: Cost = None
 
 
 @dataclass
@@ -500,7 +575,7 @@ def cem_iteration(prob: Problem, bc, obs, mu, Sigma, noise, prm: CemParams) -> C
     xi = np.asarray(mu, np.float64)[None, :] + np.asarray(noise, np.float64) @ L.T
     pr = project(prob, bc, obs, xi, prm.n_proj_iters)
     r = pr.resid
-    c1 = smoothness_cost(prob, pr.xi_bar)
+    c1 = trajectory_cost(prob, bc, pr.xi_bar, prm.cost)
     c_aug = c1 + r
     proj_idx = select_lowest(r, prm.n_proj)
     order = select_lowest(c_aug[proj_idx], prm.n_elite)
