@@ -90,7 +90,30 @@ typedef struct priest_problem_desc {
   double s_max[3];       /* use_bounds: upper limits per axis (+inf allowed) */
 } priest_problem_desc;
 
-/* Sampling-loop settings (Alg. 1, eqs. (9a)-(9c)). */
+/* Trajectory cost c1 of Alg. 1 (the remark of Sec. II that c1 need not be
+ * convex, smooth or analytic; the navigation and steering costs of Sec. V).
+ * kind PRIEST_COST_SMOOTH: c1 = sum_k ||a_k||^2 (the point-to-point cost; the
+ * weights are ignored).  kind PRIEST_COST_WEIGHTED: c1 = sum_k of
+ *   w_acc   ||a_k||^2
+ * + w_curv  kappa_k^2,  kappa = |v x a| / (||v||^2 + eps)^(3/2)
+ * + w_path  distance of p_k to the segment from p0 to pf of bc (projection
+ *           onto the line clamped to the segment; not squared)
+ * + w_steer atan(wheelbase * kappa_signed)^2 (2D only: steering angle of a
+ *           car-like robot by differential flatness, kappa_signed =
+ *           (v_x a_y - v_y a_x) / (||v||^2 + eps)^(3/2)).
+ * Weights finite and >= 0; eps > 0; wheelbase > 0 when w_steer > 0. */
+#define PRIEST_COST_SMOOTH 0
+#define PRIEST_COST_WEIGHTED 1
+typedef struct priest_cost {
+  int32_t kind;
+  float w_acc, w_curv, w_path, w_steer;
+  float wheelbase;
+  float eps;
+  int32_t reserved;  /* must be 0 */
+} priest_cost;
+
+/* Sampling-loop settings (Alg. 1, eqs. (9a)-(9c)).  A zero-initialised cost
+ * is the smoothness cost. */
 typedef struct priest_cem_params {
   int32_t n_samples;    /* N_b: samples per CEM iteration, 1..PRIEST_MAX_SAMPLES */
   int32_t n_cem;        /* CEM iterations */
@@ -102,6 +125,7 @@ typedef struct priest_cem_params {
   float gamma;          /* temperature of eq. (9c), > 0 */
   float cov_jitter;     /* eps = cov_jitter * tr(Sigma)/D added before Cholesky, >= 0 */
   float reserved_f;     /* must be 0 */
+  priest_cost cost;     /* c1 (computed in the projection's final pass) */
 } priest_cem_params;
 
 /* Outputs of priest_plan; every pointer but best_xi/best_cost may be NULL.

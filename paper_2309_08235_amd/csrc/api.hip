@@ -141,8 +141,21 @@ int32_t validate_desc(const priest_problem_desc* d) {
   return PRIEST_OK;
 }
 
-int32_t validate_cem(const priest_cem_params* c) {
+int32_t validate_cem(const priest_cem_params* c, int dims) {
   if (!c) return fail(PRIEST_ERR_INVALID, "cem params are NULL");
+  const priest_cost& k = c->cost;
+  if (k.reserved != 0) return fail(PRIEST_ERR_INVALID, "cost.reserved must be 0");
+  if (k.kind != PRIEST_COST_SMOOTH && k.kind != PRIEST_COST_WEIGHTED)
+    return fail(PRIEST_ERR_INVALID, "unknown cost kind");
+  if (k.kind == PRIEST_COST_WEIGHTED) {
+    const float w[4] = {k.w_acc, k.w_curv, k.w_path, k.w_steer};
+    for (float x : w)
+      if (!(std::isfinite(x) && x >= 0.0f)) return fail(PRIEST_ERR_INVALID, "cost weights must be finite and >= 0");
+    if (!(std::isfinite(k.eps) && k.eps > 0.0f)) return fail(PRIEST_ERR_INVALID, "cost.eps must be > 0");
+    if (k.w_steer > 0.0f && dims != 2) return fail(PRIEST_ERR_INVALID, "the steering cost is 2D only");
+    if (k.w_steer > 0.0f && !(std::isfinite(k.wheelbase) && k.wheelbase > 0.0f))
+      return fail(PRIEST_ERR_INVALID, "cost.wheelbase must be > 0");
+  }
   if (c->n_samples < 1 || c->n_samples > 8192)
     return fail(PRIEST_ERR_INVALID, "n_samples must be in [1, 8192] for planning");
   if (c->n_cem < 1) return fail(PRIEST_ERR_INVALID, "n_cem must be >= 1");
@@ -334,6 +347,8 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
   a.c1 = wc;
   a.n_stride = wstride;
   a.xi_src_stride = static_cast<int64_t>(N) * D;
+  a.cost = CostArgs{c->cost.kind, c->cost.w_acc, c->cost.w_curv, c->cost.w_path,
+                    c->cost.w_steer, c->cost.wheelbase, c->cost.eps};
   apply_tiling(a, tile_candidates(a.dims)[0]);
   return pa;
 }
@@ -672,7 +687,7 @@ int32_t priest_project_unfused(priest_problem* p, const float* bc, const float* 
 int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_params* c,
                                    int32_t n_problems, size_t* bytes) {
   if (!p || !bytes) return fail(PRIEST_ERR_INVALID, "problem and bytes are required");
-  const int32_t st = validate_cem(c);
+  const int32_t st = validate_cem(c, p->desc.dims);
   if (st != PRIEST_OK) return st;
   if (n_problems < 1) return fail(PRIEST_ERR_INVALID, "n_problems must be >= 1");
   *bytes = plan_layout(p->D, c->n_samples).per_problem * static_cast<size_t>(n_problems);
@@ -685,7 +700,7 @@ static int32_t plan_common(priest_problem* p, int32_t P, const float* bc, const 
                            void* workspace, size_t workspace_bytes, int32_t use_graph,
                            void* stream) {
   if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
-  int32_t st = validate_cem(c);
+  int32_t st = validate_cem(c, p->desc.dims);
   if (st != PRIEST_OK) return st;
   if (P < 1) return fail(PRIEST_ERR_INVALID, "n_problems must be >= 1");
   if (!bc || !mu || !cov || !out || !out->best_xi || !out->best_cost || !workspace)
@@ -871,7 +886,7 @@ int32_t priest_plan_dpriest(priest_problem* p, int32_t n_groups, const float* bc
                             int32_t* best_group, void* workspace, size_t workspace_bytes,
                             void* stream) {
   if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
-  int32_t st = validate_cem(c);
+  int32_t st = validate_cem(c, p->desc.dims);
   if (st != PRIEST_OK) return st;
   if (n_groups < 1) return fail(PRIEST_ERR_INVALID, "n_groups must be >= 1");
   if (!bc || !mu || !cov || !out || !out->best_xi || !out->best_cost || !workspace || !best_xi ||

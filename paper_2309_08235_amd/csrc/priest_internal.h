@@ -30,6 +30,12 @@ struct Box {
   float lo[3], hi[3];
 };
 
+// Trajectory cost of the final pass (priest_cost; kind 0 = sum ||a||^2).
+struct CostArgs {
+  int32_t kind;
+  float w_acc, w_curv, w_path, w_steer, wheelbase, eps;
+};
+
 struct ProjArgs {
   int32_t dims, nv, K, M, N;
   int32_t S;                   // samples per block = 16 / axis_slots
@@ -45,6 +51,7 @@ struct ProjArgs {
   uint64_t seed;               // Philox key
   float rho, dt, vmax, amax;   // vmax/amax may be +inf
   Box box;                     // workspace bounds (box.on = 0: none)
+  CostArgs cost;               // c1 of the final pass
   // problem constants (shared by all problems of the launch)
   const float* W;    // [K][3][nv] rows of P, Pdot, Pddot
   const float* M11;  // [nv][nv]

@@ -348,6 +348,63 @@ __device__ __forceinline__ float bound_push(const float w[DIMS], float wmax, flo
   return ww * f * f;
 }
 
+// Weighted trajectory cost of one (sample, step) item: acceleration,
+// regularised curvature, distance to the start-goal segment (clamped
+// projection; s = start, u = goal - start, iuu = 1 / |u|^2 or 0) and the
+// squared steering angle of a car-like robot (2D).
+template <int DIMS>
+__device__ __forceinline__ float weighted_cost(const float p[DIMS], const float v[DIMS],
+                                               const float ac[DIMS], const CostArgs& k,
+                                               const float s[DIMS], const float u[DIMS], float iuu) {
+  float c = 0.0f;
+  if (k.w_acc != 0.0f) {
+    float aa = 0.0f;
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) aa = fmaf(ac[x], ac[x], aa);
+    c = fmaf(k.w_acc, aa, c);
+  }
+  if (k.w_curv != 0.0f || k.w_steer != 0.0f) {
+    float vv = k.eps;
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) vv = fmaf(v[x], v[x], vv);
+    const float inv = 1.0f / (vv * sqrtf(vv));  // (|v|^2 + eps)^(-3/2)
+    float cr2, crs = 0.0f;
+    if constexpr (DIMS == 2) {
+      crs = v[0] * ac[1] - v[1] * ac[0];
+      cr2 = crs * crs;
+    } else {
+      const float c0 = v[1] * ac[2] - v[2] * ac[1];
+      const float c1 = v[2] * ac[0] - v[0] * ac[2];
+      const float c2 = v[0] * ac[1] - v[1] * ac[0];
+      cr2 = c0 * c0 + c1 * c1 + c2 * c2;
+    }
+    if (k.w_curv != 0.0f) c = fmaf(k.w_curv, cr2 * inv * inv, c);
+    if constexpr (DIMS == 2) {
+      if (k.w_steer != 0.0f) {
+        const float d = atanf(k.wheelbase * crs * inv);
+        c = fmaf(k.w_steer, d * d, c);
+      }
+    }
+  }
+  if (k.w_path != 0.0f) {
+    float rel[DIMS], ru = 0.0f;
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) {
+      rel[x] = p[x] - s[x];
+      ru = fmaf(rel[x], u[x], ru);
+    }
+    const float lam = fminf(fmaxf(ru * iuu, 0.0f), 1.0f);
+    float qq = 0.0f;
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) {
+      const float q = fmaf(-lam, u[x], rel[x]);
+      qq = fmaf(q, q, qq);
+    }
+    c = fmaf(k.w_path, sqrtf(qq), c);
+  }
+  return c;
+}
+
 // Record table of one scene (any number of threads).
 template <int DIMS>
 __device__ void build_records(const float* obs, int M, int t, int nt, float4* rec) {
@@ -878,11 +935,27 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       item_push<DIMS, true, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
                                 da, r2, lane, cull, wm);
       float* fin = sm + l.fin;
+      // segment of the path-following term: start p0 -> goal pf of this problem
+      float sg[DIMS], ug[DIMS], iuu = 0.0f;
+      if (a.cost.kind != 0) {
+        float uu = 0.0f;
+  #pragma unroll
+        for (int x = 0; x < DIMS; ++x) {
+          sg[x] = bc[x * 6 + 0];
+          ug[x] = bc[x * 6 + 3] - sg[x];
+          uu = fmaf(ug[x], ug[x], uu);
+        }
+        iuu = uu > 0.0f ? 1.0f / uu : 0.0f;
+      }
   #pragma unroll
       for (int n = 0; n < NI; ++n) {
         float cc = 0.0f;
+        if (a.cost.kind == 0) {
   #pragma unroll
-        for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[n][x], ac[n][x], cc);
+          for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[n][x], ac[n][x], cc);
+        } else {
+          cc = weighted_cost<DIMS>(p[n], v[n], ac[n], a.cost, sg, ug, iuu);
+        }
         float* f = fin + 2 * (t_item[n] * SPB + cs);
         f[0] = item_ok[n] ? r2[n] : 0.0f;
         f[1] = item_ok[n] ? cc : 0.0f;

@@ -58,12 +58,40 @@ class ProblemDesc(ctypes.Structure):
                 ("s_min", ctypes.c_double * 3), ("s_max", ctypes.c_double * 3)]
 
 
+class CostParams(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("w_acc", ctypes.c_float), ("w_curv", ctypes.c_float),
+                ("w_path", ctypes.c_float), ("w_steer", ctypes.c_float),
+                ("wheelbase", ctypes.c_float), ("eps", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
 class CemParams(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int32), ("n_cem", ctypes.c_int32),
                 ("n_proj_iters", ctypes.c_int32), ("n_proj", ctypes.c_int32),
                 ("n_elite", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("sigma", ctypes.c_float), ("gamma", ctypes.c_float),
-                ("cov_jitter", ctypes.c_float), ("reserved_f", ctypes.c_float)]
+                ("cov_jitter", ctypes.c_float), ("reserved_f", ctypes.c_float),
+                ("cost", CostParams)]
+
+
+COST_SMOOTH, COST_WEIGHTED = 0, 1
+
+
+@dataclass
+class Cost:
+    """c1 of Alg. 1: kind COST_SMOOTH (sum ||a||^2) or COST_WEIGHTED (the
+    weighted navigation terms of priest_cost)."""
+    kind: int = COST_SMOOTH
+    w_acc: float = 1.0
+    w_curv: float = 0.0
+    w_path: float = 0.0
+    w_steer: float = 0.0
+    wheelbase: float = 1.0
+    eps: float = 1e-2
+
+    def c(self) -> CostParams:
+        return CostParams(self.kind, self.w_acc, self.w_curv, self.w_path, self.w_steer,
+                          self.wheelbase, self.eps, 0)
 
 
 class PlanOut(ctypes.Structure):
@@ -429,10 +457,12 @@ class Cem:
     sigma: float = 0.5
     gamma: float = 1.0
     cov_jitter: float = 1e-5
+    cost: Cost = None
 
     def c(self) -> CemParams:
         return CemParams(self.n_samples, self.n_cem, self.n_proj_iters, self.n_proj,
-                         self.n_elite, 0, self.sigma, self.gamma, self.cov_jitter, 0.0)
+                         self.n_elite, 0, self.sigma, self.gamma, self.cov_jitter, 0.0,
+                         (self.cost or Cost()).c())
 
 
 class Problem:

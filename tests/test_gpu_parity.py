@@ -250,10 +250,12 @@ def _cem(wl, n_cem=1, **kw):
     return Cem(**d)
 
 
-def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, label):
+def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, label, cost=None):
+    """One CEM iteration of the GPU against the oracle; ``cost`` is the
+    oracle's Cost matching cem.cost (None: the smoothness cost)."""
     prm = O.CemParams(n_samples=cem.n_samples, n_proj_iters=cem.n_proj_iters, n_proj=cem.n_proj,
                       n_elite=cem.n_elite, sigma=cem.sigma, gamma=cem.gamma,
-                      cov_jitter=cem.cov_jitter)
+                      cov_jitter=cem.cov_jitter, cost=cost)
     st = O.cem_iteration(op, bc, obs, mu, cov, noise, prm)
     xi_g = np64(out["xi"][0])
     np.testing.assert_allclose(xi_g, st.xi, atol=2e-5 * max(1, np.abs(st.xi).max()))
@@ -271,7 +273,10 @@ def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, 
     caug_g = (c1_g.astype(np.float32) + r_g.astype(np.float32)).astype(np.float64)
     np.testing.assert_array_equal(elite, proj[O.select_lowest(caug_g[proj], cem.n_elite)])
     check_selection(pr.resid, proj, cem.n_proj, label=f"{label} proj")
-    c_aug = O.smoothness_cost(op, pr.xi_bar) + pr.resid
+    c_aug = O.trajectory_cost(op, bc, pr.xi_bar, cost) + pr.resid
+    # c1 of the GPU's own projected samples
+    c1_o = O.trajectory_cost(op, bc, xb_g, cost)
+    np.testing.assert_allclose(c1_g, c1_o, rtol=2e-3, atol=2e-3 * max(1.0, np.abs(c1_o).mean()))
     # refit of the GPU's elites with the oracle's arithmetic
     mu2, S2, _ = O.refit(mu, cov, xb_g[elite], caug_g[elite], cem.sigma, cem.gamma)
     np.testing.assert_allclose(mu_gpu, mu2, atol=1e-4 * max(1, np.abs(mu2).max()))
