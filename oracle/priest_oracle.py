@@ -41,6 +41,11 @@ Readings of passages that are silent, ambiguous or garbled in the paper:
   car-like robot (2D, signed curvature), summed over the grid;
 * weight sign in eq. (9c): exp(-(c_aug - delta)/gamma), the MPPI convention
   (with the printed sign the worst elite would get the largest weight);
+* CMA-ES-style update (the remark that the update rule is free): eq. (9a)
+  for the mean; the covariance by the rank-one and rank-mu updates of CMA-ES
+  with the eq. (9c) weights normalised, y about the current mean, Hansen's
+  default rates for n = D, an evolution path that starts at zero on every
+  plan call, and no step-size adaptation;
 * covariance Cholesky jitter: eps = cov_jitter * tr(Sigma)/D added to the
   diagonal before factorising (elites lie on {A xi = b}, so Sigma loses rank);
 * selection ties broken by sample index (stable sort), NaN ranked as +inf;
@@ -535,6 +540,40 @@ def refit(mu: np.ndarray, Sigma: np.ndarray, elites: np.ndarray, c_aug: np.ndarr
     return mu_new, Sigma_new, w
 
 
+def cma_rates(n: int, mu_eff: float):
+    """Learning rates of the covariance adaptation (Hansen's CMA-ES tutorial
+    defaults for dimension n and variance-effective selection mass mu_eff):
+    c_c of the evolution path, c_1 of the rank-one and c_mu of the rank-mu
+    update."""
+    cc = (4.0 + mu_eff / n) / (n + 4.0 + 2.0 * mu_eff / n)
+    c1 = 2.0 / ((n + 1.3) ** 2 + mu_eff)
+    cmu = min(1.0 - c1, 2.0 * (mu_eff - 2.0 + 1.0 / mu_eff) / ((n + 2.0) ** 2 + mu_eff))
+    return cc, c1, cmu
+
+
+def refit_cma(mu: np.ndarray, Sigma: np.ndarray, pc: np.ndarray, elites: np.ndarray,
+              c_aug: np.ndarray, sigma: float, gamma: float):
+    """A CMA-ES-style covariance update in place of eq. (9b) (the remark after
+    eqs. (9a)-(9c) that Alg. 1 is agnostic to the update rule).  The weights
+    are those of eq. (9c), normalised; the mean follows eq. (9a); with
+    y_m = xi_bar_m - mu (the current mean) and y_w = sum_m w_m y_m:
+      p_c'     = (1 - c_c) p_c + sqrt(c_c (2 - c_c) mu_eff) y_w,
+      Sigma'   = (1 - c_1 - c_mu) Sigma + c_1 p_c' p_c'^T + c_mu sum_m w_m y_m y_m^T,
+    mu_eff = 1 / sum_m w_m^2.  No step-size adaptation: Sigma carries the scale."""
+    c_aug = np.asarray(c_aug, np.float64)
+    w = np.exp(-(c_aug - np.min(c_aug)) / gamma)
+    wn = w / np.sum(w)
+    mu_eff = 1.0 / np.sum(wn ** 2)
+    mu_new = (1.0 - sigma) * mu + sigma * (wn @ elites)
+    y = elites - mu[None, :]
+    yw = wn @ y
+    cc, c1, cmu = cma_rates(mu.shape[0], mu_eff)
+    pc_new = (1.0 - cc) * pc + math.sqrt(cc * (2.0 - cc) * mu_eff) * yw
+    rank_mu = (y * wn[:, None]).T @ y
+    Sigma_new = (1.0 - c1 - cmu) * Sigma + c1 * np.outer(pc_new, pc_new) + cmu * rank_mu
+    return mu_new, Sigma_new, pc_new
+
+
 def jittered_cholesky(Sigma: np.ndarray, cov_jitter: float) -> np.ndarray:
     D = Sigma.shape[0]
     eps = cov_jitter * np.trace(Sigma) / D
@@ -551,6 +590,7 @@ class CemParams:
     gamma: float = 1.0
     cov_jitter: float = 1e-5
     cost: Cost = None
+    update: str = "mppi"    # "mppi": eqs. (9a)-(9c); "cma": refit_cma
 
 
 @dataclass
@@ -566,11 +606,13 @@ class CemStep:
     Sigma: np.ndarray
     best_xi: np.ndarray
     best_cost: float
+    pc: np.ndarray = None   # evolution path after the step (update "cma")
 
 
-def cem_iteration(prob: Problem, bc, obs, mu, Sigma, noise, prm: CemParams) -> CemStep:
+def cem_iteration(prob: Problem, bc, obs, mu, Sigma, noise, prm: CemParams, pc=None) -> CemStep:
     """One pass of the loop body of Alg. 1 with the standard-normal draws
-    ``noise`` ([N, D]) supplied: xi_i = mu + L z_i with L L^T = Sigma + eps I."""
+    ``noise`` ([N, D]) supplied: xi_i = mu + L z_i with L L^T = Sigma + eps I.
+    ``pc``: the evolution path of the "cma" update (zeros when None)."""
     L = jittered_cholesky(np.asarray(Sigma, np.float64), prm.cov_jitter)
     xi = np.asarray(mu, np.float64)[None, :] + np.asarray(noise, np.float64) @ L.T
     pr = project(prob, bc, obs, xi, prm.n_proj_iters)
@@ -580,12 +622,21 @@ def cem_iteration(prob: Problem, bc, obs, mu, Sigma, noise, prm: CemParams) -> C
     proj_idx = select_lowest(r, prm.n_proj)
     order = select_lowest(c_aug[proj_idx], prm.n_elite)
     elite_idx = proj_idx[order]
-    mu_new, Sigma_new, _ = refit(np.asarray(mu, np.float64), np.asarray(Sigma, np.float64),
-                                 pr.xi_bar[elite_idx], c_aug[elite_idx], prm.sigma, prm.gamma)
+    pc_new = None
+    if prm.update == "cma":
+        pc0 = np.zeros(prob.D) if pc is None else np.asarray(pc, np.float64)
+        mu_new, Sigma_new, pc_new = refit_cma(np.asarray(mu, np.float64),
+                                              np.asarray(Sigma, np.float64), pc0,
+                                              pr.xi_bar[elite_idx], c_aug[elite_idx],
+                                              prm.sigma, prm.gamma)
+    else:
+        assert prm.update == "mppi"
+        mu_new, Sigma_new, _ = refit(np.asarray(mu, np.float64), np.asarray(Sigma, np.float64),
+                                     pr.xi_bar[elite_idx], c_aug[elite_idx], prm.sigma, prm.gamma)
     best = elite_idx[0]
     return CemStep(xi=xi, xi_bar=pr.xi_bar, resid=r, c1=c1, c_aug=c_aug, proj_idx=proj_idx,
                    elite_idx=elite_idx, mu=mu_new, Sigma=Sigma_new,
-                   best_xi=pr.xi_bar[best].copy(), best_cost=float(c_aug[best]))
+                   best_xi=pr.xi_bar[best].copy(), best_cost=float(c_aug[best]), pc=pc_new)
 
 
 def plan(prob: Problem, bc, obs, mu, Sigma, prm: CemParams, n_cem: int,
@@ -594,10 +645,11 @@ def plan(prob: Problem, bc, obs, mu, Sigma, prm: CemParams, n_cem: int,
     iteration plus the updated (mu, Sigma).  ``noise`` is [n_cem, N, D] or None,
     in which case draws come from :func:`normals` (Philox4x32-10 + Box-Muller)."""
     steps = []
+    pc = None   # the "cma" evolution path starts at zero on every call
     for l in range(n_cem):
         z = noise[l] if noise is not None else normals(seed, stream, l, prm.n_samples, prob.D)
-        st = cem_iteration(prob, bc, obs, mu, Sigma, z, prm)
-        mu, Sigma = st.mu, st.Sigma
+        st = cem_iteration(prob, bc, obs, mu, Sigma, z, prm, pc)
+        mu, Sigma, pc = st.mu, st.Sigma, st.pc
         steps.append(st)
     return steps
 
