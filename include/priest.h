@@ -102,6 +102,8 @@ typedef struct priest_problem_desc {
  *           car-like robot by differential flatness, kappa_signed =
  *           (v_x a_y - v_y a_x) / (||v||^2 + eps)^(3/2)).
  * Weights finite and >= 0; eps > 0; wheelbase > 0 when w_steer > 0. */
+#define PRIEST_UPDATE_MPPI 0
+#define PRIEST_UPDATE_CMA 1
 #define PRIEST_COST_SMOOTH 0
 #define PRIEST_COST_WEIGHTED 1
 typedef struct priest_cost {
@@ -120,7 +122,17 @@ typedef struct priest_cem_params {
   int32_t n_proj_iters; /* projection iterations per CEM iteration */
   int32_t n_proj;       /* N_proj: size of the lowest-residual set, 1..n_samples */
   int32_t n_elite;      /* N_elite: size of the elite set, 1..n_proj */
-  int32_t reserved;     /* must be 0 */
+  int32_t update;       /* PRIEST_UPDATE_MPPI: eqs. (9a)-(9c); PRIEST_UPDATE_CMA: eq. (9a)
+                           for the mean and a CMA-ES-style covariance update in place of
+                           eq. (9b) (the remark that Alg. 1 is agnostic to the rule):
+                           weights w = c_m / sum c_m of eq. (9c), mu_eff = 1 / sum w^2,
+                           y_m = xi_bar_m - mu, y_w = sum w y,
+                           p_c' = (1 - c_c) p_c + sqrt(c_c (2 - c_c) mu_eff) y_w,
+                           Sigma' = (1 - c_1 - c_mu) Sigma + c_1 p_c' p_c'^T
+                                    + c_mu sum w y y^T,
+                           c_c, c_1, c_mu at the CMA-ES defaults for n = D; the path
+                           p_c starts at zero on every plan call (it lives in the
+                           workspace); no step-size adaptation */
   float sigma;          /* learning rate of eqs. (9a)/(9b), in [0, 1] */
   float gamma;          /* temperature of eq. (9c), > 0 */
   float cov_jitter;     /* eps = cov_jitter * tr(Sigma)/D added before Cholesky, >= 0 */

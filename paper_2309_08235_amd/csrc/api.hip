@@ -169,7 +169,9 @@ int32_t validate_cem(const priest_cem_params* c, int dims) {
   if (!(std::isfinite(c->gamma) && c->gamma > 0)) return fail(PRIEST_ERR_INVALID, "gamma must be > 0");
   if (!(std::isfinite(c->cov_jitter) && c->cov_jitter >= 0))
     return fail(PRIEST_ERR_INVALID, "cov_jitter must be finite and >= 0");
-  if (c->reserved != 0 || c->reserved_f != 0.0f) return fail(PRIEST_ERR_INVALID, "reserved must be 0");
+  if (c->update != PRIEST_UPDATE_MPPI && c->update != PRIEST_UPDATE_CMA)
+    return fail(PRIEST_ERR_INVALID, "unknown update rule");
+  if (c->reserved_f != 0.0f) return fail(PRIEST_ERR_INVALID, "reserved_f must be 0");
   return PRIEST_OK;
 }
 
@@ -214,7 +216,7 @@ int32_t check_lds(const priest_problem* p, const ProjArgs& a) {
 }
 
 struct PlanLayout {
-  size_t xb, resid, c1, L, status, per_problem;
+  size_t xb, resid, c1, L, pc, status, per_problem;
 };
 
 PlanLayout plan_layout(int D, int N) {
@@ -224,6 +226,7 @@ PlanLayout plan_layout(int D, int N) {
   l.resid = o;  o += align256(sizeof(float) * N);
   l.c1 = o;     o += align256(sizeof(float) * N);
   l.L = o;      o += align256(sizeof(float) * D * D);
+  l.pc = o;     o += align256(sizeof(float) * D);
   l.status = o; o += align256(sizeof(int32_t));
   l.per_problem = o;
   return l;
@@ -322,6 +325,10 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
   ca.proj_idx = out->proj_idx;
   ca.status = out->status;
   ca.chol_only = 0;
+  ca.rule = c->update;
+  ca.first = 1;
+  ca.pc = reinterpret_cast<float*>(ws + pl.pc);
+  ca.pc_stride = wstride;
 
   ProjArgs& a = pa.a;
   a = base_args(p);
@@ -376,6 +383,7 @@ int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const f
     a.c12 = last ? out->c1 : nullptr;
     a.xi_out2 = last ? out->xi_bar : nullptr;
     HIP_TRY(launch_project_timed(a, P, s));
+    ca.first = (l == 0) ? 1 : 0;
     HIP_TRY(launch_cem(ca, P, s));
   }
   return PRIEST_OK;

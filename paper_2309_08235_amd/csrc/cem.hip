@@ -29,7 +29,7 @@ constexpr int kStageFloats = 4096;  // elite rows staged in LDS per chunk
 __host__ __device__ inline size_t align16(size_t n) { return (n + 15) & ~static_cast<size_t>(15); }
 
 struct CemLayout {
-  size_t proj, elite, w, red, mu, A, stage, total;
+  size_t proj, elite, w, red, mu, pc, A, stage, total;
 };
 
 __host__ __device__ inline CemLayout cem_layout(int D, int n_proj, int n_elite) {
@@ -40,6 +40,7 @@ __host__ __device__ inline CemLayout cem_layout(int D, int n_proj, int n_elite) 
   l.w = o;     o += align16(sizeof(float) * (n_elite > 0 ? n_elite : 1));
   l.red = o;   o += align16(sizeof(float) * 64);
   l.mu = o;    o += align16(sizeof(float) * D);
+  l.pc = o;    o += align16(sizeof(float) * D);
   l.A = o;     o += align16(sizeof(float) * D * D);
   l.stage = o; o += align16(sizeof(float) * kStageFloats);
   l.total = o;
@@ -151,6 +152,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   float* w = reinterpret_cast<float*>(sm + l.w);
   float* red = reinterpret_cast<float*>(sm + l.red);
   float* muN = reinterpret_cast<float*>(sm + l.mu);
+  float* pcN = reinterpret_cast<float*>(sm + l.pc);
   float* A = reinterpret_cast<float*>(sm + l.A);
   float* mu = a.mu + prob * a.mu_stride;
   float* cov = a.cov + prob * a.cov_stride;
@@ -196,13 +198,30 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     }
     __syncthreads();
     if (tid < 64) {
-      float part = 0.0f;
-      for (int m = tid; m < a.n_elite; m += 64) part += w[m];
+      float part = 0.0f, part2 = 0.0f;
+      for (int m = tid; m < a.n_elite; m += 64) {
+        part += w[m];
+        part2 = fmaf(w[m], w[m], part2);
+      }
       part = wave_sum(part);
-      if (tid == 0) red[0] = part;
+      part2 = wave_sum(part2);
+      if (tid == 0) {
+        red[0] = part;
+        red[1] = part2;
+      }
     }
     __syncthreads();
     const float inv_sw = 1.0f / red[0];
+    // CMA-ES-style rates (rule 1): variance-effective selection mass and the
+    // default learning rates for dimension n = D
+    float cc = 0.0f, c1r = 0.0f, cmu = 0.0f, mu_eff = 1.0f;
+    if (a.rule == 1) {
+      const float n = static_cast<float>(D);
+      mu_eff = red[0] * red[0] / red[1];
+      cc = (4.0f + mu_eff / n) / (n + 4.0f + 2.0f * mu_eff / n);
+      c1r = 2.0f / ((n + 1.3f) * (n + 1.3f) + mu_eff);
+      cmu = fminf(1.0f - c1r, 2.0f * (mu_eff - 2.0f + 1.0f / mu_eff) / ((n + 2.0f) * (n + 2.0f) + mu_eff));
+    }
     PRIEST_CEM_MARK(3);
     // 4. mean and covariance from elite rows staged in LDS, CH rows at a time
     float* stage = reinterpret_cast<float*>(sm + l.stage);
@@ -231,13 +250,20 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     __syncthreads();
     if (tid < D) {
       const float sm4 = (A[tid] + A[D + tid]) + (A[2 * D + tid] + A[3 * D + tid]);
-      muN[tid] = (1.0f - a.sigma) * mu[tid] + a.sigma * (sm4 * inv_sw);
+      const float mw = sm4 * inv_sw;
+      muN[tid] = (1.0f - a.sigma) * mu[tid] + a.sigma * mw;
+      if (a.rule == 1) {
+        const float p0 = a.first ? 0.0f : a.pc[prob * a.pc_stride + tid];
+        pcN[tid] = fmaf(sqrtf(cc * (2.0f - cc) * mu_eff), mw - mu[tid], (1.0f - cc) * p0);
+      }
     }
     __syncthreads();
     PRIEST_CEM_MARK(4);
-    // covariance about the new mean, sum_m w_m (x_m - mu')(x_m - mu')^T, on
-    // MFMA 16x16x4: wave v computes lower-triangle tile v of the ceil(D/16)^2
-    // tiles, elites four at a time (two accumulation chains, added at the end)
+    // covariance about the new mean, sum_m w_m (x_m - mu')(x_m - mu')^T (rule
+    // 1: about the current mean), on MFMA 16x16x4: wave v computes
+    // lower-triangle tile v of the ceil(D/16)^2 tiles, elites four at a time
+    // (two accumulation chains, added at the end)
+    const float* cen = (a.rule == 1) ? mu : muN;
     const int wv = tid >> 6, lane = tid & 63;
     const int nt = (D + 15) / 16;
     int ti = 0, tj = 0;
@@ -259,7 +285,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       }
       if (owner) {
         const int ii = ti * 16 + (lane & 15), jj = tj * 16 + (lane & 15);
-        const float mi = ii < D ? muN[ii] : 0.0f, mj = jj < D ? muN[jj] : 0.0f;
+        const float mi = ii < D ? cen[ii] : 0.0f, mj = jj < D ? cen[jj] : 0.0f;
         for (int s4 = 0; s4 < nm; s4 += 8) {
           const int ma = s4 + (lane >> 4), mb = ma + 4;
           const float av0 = (ma < nm && ii < D) ? w[m0 + ma] * (stage[ma * D + ii] - mi) : 0.0f;
@@ -278,7 +304,12 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       for (int r = 0; r < 4; ++r) {
         const int i = ti * 16 + 4 * (lane >> 4) + r, j = tj * 16 + (lane & 15);
         if (i < D && j < D && i >= j) {
-          const float v = (1.0f - a.sigma) * cov[i * D + j] + a.sigma * (acc[r] * inv_sw);
+          float v;
+          if (a.rule == 1)
+            v = fmaf(cmu, acc[r] * inv_sw,
+                     fmaf(c1r, pcN[i] * pcN[j], (1.0f - c1r - cmu) * cov[i * D + j]));
+          else
+            v = (1.0f - a.sigma) * cov[i * D + j] + a.sigma * (acc[r] * inv_sw);
           A[i * D + j] = v;
           A[j * D + i] = v;
         }
@@ -288,6 +319,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     for (int e = tid; e < D * D; e += T) cov[e] = A[e];
     for (int d = tid; d < D; d += T) {
       mu[d] = muN[d];
+      if (a.rule == 1) a.pc[prob * a.pc_stride + d] = pcN[d];
       a.best_xi[prob * a.best_stride + d] = xb[static_cast<int64_t>(e0) * D + d];
     }
     if (tid == 0) a.best_cost[prob] = delta;

@@ -89,6 +89,9 @@ struct CemArgs {
   float* best_cost;                        // [1] per problem
   int32_t* elite_idx; int32_t* proj_idx;   // nullable
   int32_t* status;                         // nullable, [1] per problem
+  int32_t rule;                            // 0: eqs. (9a)-(9c); 1: CMA-ES-style covariance
+  int32_t first;                           // 1: the evolution path starts at zero
+  float* pc; int64_t pc_stride;            // evolution path [D] per problem (rule 1)
 };
 
 // Launch descriptions of the descriptor-table kernels (serving path): all

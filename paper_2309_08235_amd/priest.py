@@ -68,13 +68,14 @@ class CostParams(ctypes.Structure):
 class CemParams(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int32), ("n_cem", ctypes.c_int32),
                 ("n_proj_iters", ctypes.c_int32), ("n_proj", ctypes.c_int32),
-                ("n_elite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_elite", ctypes.c_int32), ("update", ctypes.c_int32),
                 ("sigma", ctypes.c_float), ("gamma", ctypes.c_float),
                 ("cov_jitter", ctypes.c_float), ("reserved_f", ctypes.c_float),
                 ("cost", CostParams)]
 
 
 COST_SMOOTH, COST_WEIGHTED = 0, 1
+UPDATE_MPPI, UPDATE_CMA = 0, 1
 
 
 @dataclass
@@ -458,11 +459,12 @@ class Cem:
     gamma: float = 1.0
     cov_jitter: float = 1e-5
     cost: Cost = None
+    update: int = UPDATE_MPPI
 
     def c(self) -> CemParams:
         return CemParams(self.n_samples, self.n_cem, self.n_proj_iters, self.n_proj,
-                         self.n_elite, 0, self.sigma, self.gamma, self.cov_jitter, 0.0,
-                         (self.cost or Cost()).c())
+                         self.n_elite, self.update, self.sigma, self.gamma, self.cov_jitter,
+                         0.0, (self.cost or Cost()).c())
 
 
 class Problem:

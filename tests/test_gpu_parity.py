@@ -250,13 +250,16 @@ def _cem(wl, n_cem=1, **kw):
     return Cem(**d)
 
 
-def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, label, cost=None):
+def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, label, cost=None,
+                    pc=None):
     """One CEM iteration of the GPU against the oracle; ``cost`` is the
-    oracle's Cost matching cem.cost (None: the smoothness cost)."""
+    oracle's Cost matching cem.cost (None: the smoothness cost); ``pc`` the
+    evolution path entering the step when cem.update is the CMA rule."""
+    update = "cma" if getattr(cem, "update", 0) == 1 else "mppi"
     prm = O.CemParams(n_samples=cem.n_samples, n_proj_iters=cem.n_proj_iters, n_proj=cem.n_proj,
                       n_elite=cem.n_elite, sigma=cem.sigma, gamma=cem.gamma,
-                      cov_jitter=cem.cov_jitter, cost=cost)
-    st = O.cem_iteration(op, bc, obs, mu, cov, noise, prm)
+                      cov_jitter=cem.cov_jitter, cost=cost, update=update)
+    st = O.cem_iteration(op, bc, obs, mu, cov, noise, prm, pc)
     xi_g = np64(out["xi"][0])
     np.testing.assert_allclose(xi_g, st.xi, atol=2e-5 * max(1, np.abs(st.xi).max()))
     # projection of the GPU's own draws, compared element by element
@@ -278,7 +281,11 @@ def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, 
     c1_o = O.trajectory_cost(op, bc, xb_g, cost)
     np.testing.assert_allclose(c1_g, c1_o, rtol=2e-3, atol=2e-3 * max(1.0, np.abs(c1_o).mean()))
     # refit of the GPU's elites with the oracle's arithmetic
-    mu2, S2, _ = O.refit(mu, cov, xb_g[elite], caug_g[elite], cem.sigma, cem.gamma)
+    if update == "cma":
+        pc0 = np.zeros(op.D) if pc is None else pc
+        mu2, S2, _ = O.refit_cma(mu, cov, pc0, xb_g[elite], caug_g[elite], cem.sigma, cem.gamma)
+    else:
+        mu2, S2, _ = O.refit(mu, cov, xb_g[elite], caug_g[elite], cem.sigma, cem.gamma)
     np.testing.assert_allclose(mu_gpu, mu2, atol=1e-4 * max(1, np.abs(mu2).max()))
     np.testing.assert_allclose(cov_gpu, S2, atol=2e-4 * max(1, np.abs(S2).max()))
     np.testing.assert_allclose(np64(out["best_xi"][0]), xb_g[elite[0]], atol=0)
