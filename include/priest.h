@@ -250,8 +250,9 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
  * shape (4, 1, 0) is used.
  * ------------------------------------------------------------------------ */
 typedef struct priest_tiling {
-  int32_t axis_slots; /* MFMA columns per sample: 4, or 2 (2D only) */
-  int32_t row_tiles;  /* 16-step time blocks per wave: 1 or 2 */
+  int32_t axis_slots; /* MFMA columns per sample: 4; 2 (2D only); or 8 (two samples per
+                         block, half the lanes idle in the push-out: more blocks for small N) */
+  int32_t row_tiles;  /* 16-step time blocks per wave: 1 or 2 (8 axis slots: 1 only) */
   int32_t persistent; /* 1: grid of resident blocks looping over tiles */
   int32_t reserved;   /* must be 0 */
 } priest_tiling;

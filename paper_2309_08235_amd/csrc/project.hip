@@ -93,12 +93,20 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Transpose buffers: each lane's float4 at 4 * (lane + lane / 4) floats, i.e.
+// 16 bytes of padding after every 4 lanes, so that the reads of one item's
+// axes (lanes 4i..4i+3 of a quad, same slot) and of one column's rows fall in
+// distinct banks across the quads of a half-wave.
+constexpr int kXtRow = 320;            // one row type: 64 lanes x 4 + 16 x 4 padding
+constexpr int kXtBlock = 3 * kXtRow;   // p, v, a (or their push-outs)
+__device__ __forceinline__ int xt_at(int lane) { return 4 * (lane + (lane >> 2)); }
+
 struct Layout {  // offsets into dynamic LDS, in floats
   int rec, xt, gp, fin, cm, mu, L, z, xs, total;
 };
 
-// rec: obstacle records (12 floats each); xt: per-wave transpose buffers (768
-// floats per 16-step block); gp: double-buffered partial right-hand sides
+// rec: obstacle records (three float4 arrays of M, structure of arrays); xt:
+// per-wave transpose buffers (kXtBlock floats per 16-step block); gp: double-buffered partial right-hand sides
 // (256 per block); fin: per-(t, sample) residual^2 and c1 of the final pass;
 // cm: per-wave obstacle candidate masks (4 words per 64 obstacles); xs: the
 // block's samples; mu/L/z: sampler staging.  NB = 16-step blocks of the
@@ -108,7 +116,7 @@ __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SP
   const int D = dims * nv, D4 = round4(D);
   int o = 0;
   l.rec = o; o += 12 * M;
-  l.xt = o;  o += NB * 768;
+  l.xt = o;  o += NB * kXtBlock;
   l.gp = o;  o += 2 * NB * 256;
   l.fin = o; o += 2 * 16 * NB * SPB;
   l.cm = o;  o += NB * 4 * ((M + 63) / 64);
@@ -198,8 +206,8 @@ __device__ __forceinline__ Rec rec_from_lane(const float4& R0, const float4& R1,
   return r;
 }
 
-__device__ __forceinline__ Rec rec_from_lds(const float4* rec, int j) {
-  const float4 R0 = rec[3 * j], R1 = rec[3 * j + 1], R2 = rec[3 * j + 2];
+__device__ __forceinline__ Rec rec_from_lds(const float4* rec, int M, int j) {
+  const float4 R0 = rec[j], R1 = rec[M + j], R2 = rec[2 * M + j];
   Rec r;
   r.cx = R0.x; r.cy = R0.y; r.cz = R0.z;
   r.vx = R1.x; r.vy = R1.y; r.vz = R1.z;
@@ -413,11 +421,11 @@ __device__ void build_records(const float* obs, int M, int t, int nt, float4* re
     const float a = o[6], b = (DIMS == 3) ? o[7] : o[6];
     const float cz = (DIMS == 3) ? o[2] : 0.0f, vz = (DIMS == 3) ? o[5] : 0.0f;
     const float sp = sqrtf(o[3] * o[3] + o[4] * o[4] + vz * vz);
-    rec[3 * j] = make_float4(o[0], o[1], cz, fmaxf(a, b) * 1.001f + 1.0e-4f);
-    rec[3 * j + 1] = make_float4(o[3], o[4], vz, sp);
+    rec[j] = make_float4(o[0], o[1], cz, fmaxf(a, b) * 1.001f + 1.0e-4f);
+    rec[M + j] = make_float4(o[3], o[4], vz, sp);
     // 3D keeps rsq(1/b^2), the canonical zero-offset push-out, in place of a^2
     const float ib2 = 1.0f / (b * b);
-    rec[3 * j + 2] = make_float4(a, (DIMS == 3) ? rsq(ib2) : a * a, 1.0f / (a * a), ib2);
+    rec[2 * M + j] = make_float4(a, (DIMS == 3) ? rsq(ib2) : a * a, 1.0f / (a * a), ib2);
   }
 }
 
@@ -490,7 +498,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       const int j = base + lane;
       bool cand = false, mv = false;
       if (j < M) {
-        const float4 R0 = rec[3 * j], R1 = rec[3 * j + 1];
+        const float4 R0 = rec[j], R1 = rec[M + j];
         const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y),
                              fmaf(R1.z, tmid, R0.z)};
         float d2 = 0.0f;
@@ -522,6 +530,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     cc.valid = true;
     wave_lds_sync();
   }
+  PRIEST_PROJ_MARK(7);
   uint32_t ncand = 0;
   for (int base = 0, g = 0; base < M; base += 64, ++g) {
     const uint4 m4 = *reinterpret_cast<const uint4*>(wm + 4 * g);
@@ -538,9 +547,9 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     const int j = base + lane;
     float4 R0 = make_float4(0, 0, 0, 0), R1 = R0, R2 = R0;
     if (j < M) {
-      R0 = rec[3 * j];
-      R1 = rec[3 * j + 1];
-      R2 = rec[3 * j + 2];
+      R0 = rec[j];
+      R1 = rec[M + j];
+      R2 = rec[2 * M + j];
     }
     // kCandUnroll candidates at a time (their offsets and factors are
     // independent), added in the canonical order, the tail one at a time
@@ -577,6 +586,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     run(mvmask, std::true_type{});
   }
   cc.pairs += ncand * cc.nok;
+  PRIEST_PROJ_MARK(8);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (!ok[i]) {
@@ -631,9 +641,11 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
 // blocks per wave; MAXT: the launch bound.
 template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP>
 __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int stride, int total) {
-  static_assert(AS == 4 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
+  static_assert(AS == 4 || AS == 8 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
   constexpr int SPB = 16 / AS;           // samples per block
-  constexpr int IPR = 4 / AS;            // items per lane per time block
+  // items per lane per time block; with 8 slots per sample only the lanes of
+  // slots 0..3 carry an item (a wave holds 2 samples x 16 steps)
+  constexpr int IPR = AS <= 4 ? 4 / AS : 1;
   constexpr int NI = RT * IPR;           // items per lane
   constexpr int MB = (MAXT / 64) * RT;   // 16-step block slots (power of two)
   extern __shared__ float4 sm4[];
@@ -693,7 +705,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     Mlo = pack_bf16(Am[0] - from_bf16(Mhi[0]), Am[1] - from_bf16(Mhi[1]),
                     Am[2] - from_bf16(Mhi[2]), Am[3] - from_bf16(Mhi[3]));
   }
-  float* xt = sm + l.xt + w * RT * 768;
+  float* xt = sm + l.xt + w * RT * kXtBlock;
   uint32_t* wm = reinterpret_cast<uint32_t*>(sm + l.cm) + w * 4 * ((M + 63) / 64);
 
   // Forward rows of this wave's time blocks, transposed to the item layout.
@@ -708,10 +720,10 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
                     mfma(Af[rt][1][3], xb[3], mfma(Af[rt][1][2], xb[2], z));
       const f4 Y2 = mfma(Af[rt][2][1], xb[1], mfma(Af[rt][2][0], xb[0], z)) +
                     mfma(Af[rt][2][3], xb[3], mfma(Af[rt][2][2], xb[2], z));
-      float* x0 = xt + rt * 768;
-      *reinterpret_cast<f4*>(x0 + lane * 4) = Y0;
-      *reinterpret_cast<f4*>(x0 + 256 + lane * 4) = Y1;
-      *reinterpret_cast<f4*>(x0 + 512 + lane * 4) = Y2;
+      float* x0 = xt + rt * kXtBlock + xt_at(lane);
+      *reinterpret_cast<f4*>(x0) = Y0;
+      *reinterpret_cast<f4*>(x0 + kXtRow) = Y1;
+      *reinterpret_cast<f4*>(x0 + 2 * kXtRow) = Y2;
     }
     wave_lds_sync();
 #pragma unroll
@@ -720,10 +732,10 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       for (int i = 0; i < IPR; ++i)
 #pragma unroll
         for (int x = 0; x < DIMS; ++x) {
-          const int src = rt * 768 + (lane - cx + x) * 4 + IPR * cx + i;
+          const int src = rt * kXtBlock + xt_at(lane - cx + x) + IPR * cx + i;
           p[rt * IPR + i][x] = xt[src];
-          v[rt * IPR + i][x] = xt[256 + src];
-          ac[rt * IPR + i][x] = xt[512 + src];
+          v[rt * IPR + i][x] = xt[kXtRow + src];
+          ac[rt * IPR + i][x] = xt[2 * kXtRow + src];
         }
     wave_lds_sync();
   };
@@ -735,7 +747,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     const int ns = min(SPB, a.N - s0);
     bool item_ok[NI];
 #pragma unroll
-    for (int n = 0; n < NI; ++n) item_ok[n] = (t_item[n] < K) && (cs < ns);
+    for (int n = 0; n < NI; ++n) item_ok[n] = (t_item[n] < K) && (cs < ns) && (AS <= 4 || cx < 4);
     // ---- scene records, samples ---------------------------------------------
     // (every reader of the previous tile's records passed the barrier that
     // precedes its epilogue)
@@ -828,10 +840,10 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
             T1[AS * i + x] = dv[rt * IPR + i][x];
             T2[AS * i + x] = da[rt * IPR + i][x];
           }
-        float* x0 = xt + rt * 768;
-        *reinterpret_cast<f4*>(x0 + lane * 4) = T0;
-        *reinterpret_cast<f4*>(x0 + 256 + lane * 4) = T1;
-        *reinterpret_cast<f4*>(x0 + 512 + lane * 4) = T2;
+        float* x0 = xt + rt * kXtBlock + xt_at(lane);
+        *reinterpret_cast<f4*>(x0) = T0;
+        *reinterpret_cast<f4*>(x0 + kXtRow) = T1;
+        *reinterpret_cast<f4*>(x0 + 2 * kXtRow) = T2;
       }
       wave_lds_sync();
       float B[RT][3][4];
@@ -839,10 +851,12 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       for (int rt = 0; rt < RT; ++rt)
   #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int src = rt * 768 + (lane - cx + r / IPR) * 4 + AS * (r % IPR) + cx;
-          B[rt][0][r] = xt[src];
-          B[rt][1][r] = xt[256 + src];
-          B[rt][2][r] = xt[512 + src];
+          const int src = rt * kXtBlock + xt_at(lane - cx + r / IPR) + AS * (r % IPR) + cx;
+          // (8 slots: columns 4..7 of a sample are padding and stay zero)
+          const bool pad = (AS == 8) && (cx >= 4);
+          B[rt][0][r] = pad ? 0.0f : xt[src];
+          B[rt][1][r] = pad ? 0.0f : xt[kXtRow + src];
+          B[rt][2][r] = pad ? 0.0f : xt[2 * kXtRow + src];
         }
       const f4 zb = {0.0f, 0.0f, 0.0f, 0.0f};
       const bool lowp = BF16 && (k < a.bf16_iters);
@@ -957,8 +971,10 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
           cc = weighted_cost<DIMS>(p[n], v[n], ac[n], a.cost, sg, ug, iuu);
         }
         float* f = fin + 2 * (t_item[n] * SPB + cs);
-        f[0] = item_ok[n] ? r2[n] : 0.0f;
-        f[1] = item_ok[n] ? cc : 0.0f;
+        if (AS <= 4 || cx < 4) {  // lanes without items own no slot
+          f[0] = item_ok[n] ? r2[n] : 0.0f;
+          f[1] = item_ok[n] ? cc : 0.0f;
+        }
       }
     }
     __syncthreads();
@@ -1057,7 +1073,7 @@ __global__ void offsets_kernel(ProjArgs a, const float* xi, float* out) {
   const float tt = a.dt * static_cast<float>(t);
   float* o = out + static_cast<int64_t>(s) * (M + 2) * K * DIMS;
   for (int j = 0; j < M; ++j) {
-    const Rec r = rec_from_lds(rec, j);
+    const Rec r = rec_from_lds(rec, M, j);
     float S[DIMS], r2 = 0.0f;
     for (int x = 0; x < DIMS; ++x) S[x] = 0.0f;
     if (pair_push<DIMS, false>(r, tt, p, S, r2)) zero_push<DIMS, false>(r, S, r2);
@@ -1147,16 +1163,19 @@ hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hi
   if (threads <= 512) {
     if constexpr (DIMS == 2)
       if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 512, BF16>(a, total, threads, lds, s);
+    if (a.axis_slots == 8) return launch_shape<DIMS, 8, 1, 512, BF16>(a, total, threads, lds, s);
     return launch_shape<DIMS, 4, 1, 512, BF16>(a, total, threads, lds, s);
   }
   if constexpr (DIMS == 2)
     if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 1024, BF16>(a, total, threads, lds, s);
+  if (a.axis_slots == 8) return launch_shape<DIMS, 8, 1, 1024, BF16>(a, total, threads, lds, s);
   return launch_shape<DIMS, 4, 1, 1024, BF16>(a, total, threads, lds, s);
 }
 
 }  // namespace
 
 bool tiling_valid(int dims, int axis_slots, int row_tiles) {
+  if (axis_slots == 8) return row_tiles == 1;  // 2 samples per block, more blocks for small N
   return (axis_slots == 4 || (axis_slots == 2 && dims == 2)) && (row_tiles == 1 || row_tiles == 2);
 }
 

@@ -1,7 +1,8 @@
 // Autotuner of the projection kernel's tile shape.
 //
 // Candidates differ in how samples map to MFMA columns (4 axis slots per
-// sample, or 2 in 2D so that 8 samples fill the 16 columns), in how many
+// sample; 2 in 2D so that 8 samples fill the 16 columns; or 8, two samples
+// per block, which doubles the block count for small batches), in how many
 // 16-step time blocks one wave carries (1 or 2: more independent items per
 // lane, fewer waves per block), and in the grid (one block per tile, or a
 // persistent grid of resident blocks looping over tiles).  All candidates
@@ -18,7 +19,7 @@ namespace priest {
 
 std::vector<TileCfg> tile_candidates(int dims) {
   std::vector<TileCfg> out;
-  const int slots[2] = {4, 2};
+  const int slots[3] = {4, 2, 8};
   for (int rt = 1; rt <= 2; ++rt)
     for (int s : slots)
       for (int pers = 0; pers <= 1; ++pers)

@@ -55,6 +55,7 @@ def test_projection_identical_across_tilings(P, label, wl, changes, N, precision
     cands = prob.tiling_candidates()
     assert cands[0] == (4, 1, 0)
     assert ((2, 1, 0) in cands) == (w.dims == 2)
+    assert (8, 1, 0) in cands and (8, 1, 1) in cands
     outs = {}
     for c in cands:
         prob.set_tiling(c)
@@ -148,7 +149,7 @@ def test_autotuner_picks_a_candidate_and_keeps_results(P):
 
 def test_set_tiling_rejects_non_candidates(P):
     prob = P.Problem.from_workload(W.C3)
-    for bad in [(2, 1, 0), (3, 1, 0), (4, 3, 0), (4, 1, 2)]:
+    for bad in [(2, 1, 0), (3, 1, 0), (4, 3, 0), (4, 1, 2), (8, 2, 0), (16, 1, 0)]:
         with pytest.raises(P.PriestError):
             prob.set_tiling(bad)
     prob.close()
