@@ -429,10 +429,15 @@ __device__ void build_records(const float* obs, int M, int t, int nt, float4* re
   }
 }
 
+// Groups of 64 obstacles whose candidate masks stay in (scalar) registers;
+// the masks of further groups live in LDS.
+constexpr int kRegGroups = 2;
+
 // Per-wave memory of the last obstacle cull: every item's position when the
-// candidate sets were built, and the displacement (squared) up to which they
-// stay valid.  The candidate masks themselves live in LDS (4 words per group
-// of 64 obstacles: candidate and moving bits).
+// candidate sets were built, the displacement (squared) up to which they stay
+// valid, and the candidate and moving bits of the first kRegGroups groups of
+// 64 obstacles (wave-uniform).  Masks of later groups live in LDS (4 words
+// per group).
 template <int NI, int DIMS>
 struct CullCache {
   float pref[NI][DIMS];
@@ -440,6 +445,7 @@ struct CullCache {
   bool valid;
   uint32_t nok;    // valid items of the wave (wave-uniform)
   uint32_t pairs;  // (item, obstacle) pairs evaluated by the wave so far
+  unsigned long long cm[kRegGroups], mv[kRegGroups];
 };
 
 // Growth of the candidate radius that lets a candidate set be reused: an
@@ -449,7 +455,7 @@ struct CullCache {
 // A skipped obstacle then stays farther than its cull radius from every item,
 // where its push-out is exactly zero.
 #ifndef PRIEST_CULL_SLACK
-#define PRIEST_CULL_SLACK 0.5f
+#define PRIEST_CULL_SLACK 0.25f
 #endif
 constexpr float kSlack = PRIEST_CULL_SLACK;
 
@@ -463,6 +469,10 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
                                                 const float p[NI][DIMS], float S[NI][DIMS],
                                                 float r2[NI], int lane, CullCache<NI, DIMS>& cc,
                                                 uint32_t* wm) {
+  // records of the first group, issued before anything waits on LDS
+  const float4 zr = make_float4(0, 0, 0, 0);
+  const float4 G0 = lane < M ? rec[lane] : zr, G1 = lane < M ? rec[M + lane] : zr,
+               G2 = lane < M ? rec[2 * M + lane] : zr;
   // reuse the candidate sets if every item is still within the slack
   bool reuse = false;
   if (cc.valid) {
@@ -494,11 +504,11 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     }
     PRIEST_PROJ_MARK(6);
     float cmin = INFINITY;
-    for (int base = 0, g = 0; base < M; base += 64, ++g) {
-      const int j = base + lane;
+    auto cull_group = [&](int g, float4 R0, float4 R1, unsigned long long& mask,
+                          unsigned long long& moving) {
+      const int j = 64 * g + lane;
       bool cand = false, mv = false;
       if (j < M) {
-        const float4 R0 = rec[j], R1 = rec[M + j];
         const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y),
                              fmaf(R1.z, tmid, R0.z)};
         float d2 = 0.0f;
@@ -512,8 +522,24 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
         mv = R1.w != 0.0f;
         cmin = fminf(cmin, R0.w);
       }
-      const unsigned long long mask = __ballot(cand);
-      const unsigned long long moving = __ballot(cand && mv);
+      mask = __ballot(cand);
+      moving = __ballot(cand && mv);
+    };
+#pragma unroll
+    for (int g = 0; g < kRegGroups; ++g) {
+      cc.cm[g] = 0ull;
+      cc.mv[g] = 0ull;
+      if (64 * g < M) {
+        const int j = 64 * g + lane;
+        const float4 R0 = g == 0 ? G0 : (j < M ? rec[j] : zr);
+        const float4 R1 = g == 0 ? G1 : (j < M ? rec[M + j] : zr);
+        cull_group(g, R0, R1, cc.cm[g], cc.mv[g]);
+      }
+    }
+    for (int g = kRegGroups; 64 * g < M; ++g) {
+      const int j = 64 * g + lane;
+      unsigned long long mask, moving;
+      cull_group(g, j < M ? rec[j] : zr, j < M ? rec[M + j] : zr, mask, moving);
       if (lane == 0) {
         wm[4 * g + 0] = static_cast<uint32_t>(mask);
         wm[4 * g + 1] = static_cast<uint32_t>(mask >> 32);
@@ -528,31 +554,15 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
 #pragma unroll
       for (int x = 0; x < DIMS; ++x) cc.pref[i][x] = p[i][x];
     cc.valid = true;
-    wave_lds_sync();
+    if (M > 64 * kRegGroups) wave_lds_sync();
   }
   PRIEST_PROJ_MARK(7);
   uint32_t ncand = 0;
-  for (int base = 0, g = 0; base < M; base += 64, ++g) {
-    const uint4 m4 = *reinterpret_cast<const uint4*>(wm + 4 * g);
-    // (readfirstlane returns int: widen through uint32_t, not sign-extended)
-    auto u64 = [](uint32_t lo, uint32_t hi) {
-      return static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo))) |
-             (static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi)))
-              << 32);
-    };
-    const unsigned long long cmask = u64(m4.x, m4.y);
-    ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
-    if (!cmask) continue;
-    const unsigned long long mvmask = u64(m4.z, m4.w);
-    const int j = base + lane;
-    float4 R0 = make_float4(0, 0, 0, 0), R1 = R0, R2 = R0;
-    if (j < M) {
-      R0 = rec[j];
-      R1 = rec[M + j];
-      R2 = rec[2 * M + j];
-    }
-    // kCandUnroll candidates at a time (their offsets and factors are
-    // independent), added in the canonical order, the tail one at a time
+  // the candidates of one group, kCandUnroll at a time (their offsets and
+  // factors are independent), added in the canonical order, the tail one at a
+  // time; R0..R2 hold the group's records, obstacle 64 g + lane in this lane
+  auto group = [&](unsigned long long cmask, unsigned long long mvmask, float4 R0, float4 R1,
+                   float4 R2) {
     auto run = [&](unsigned long long mask, auto moving_tag) {
       constexpr bool MV = decltype(moving_tag)::value;
       PRIEST_PROJ_COUNT(__builtin_popcountll(mask));
@@ -584,6 +594,34 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     };
     run(cmask & ~mvmask, std::false_type{});
     run(mvmask, std::true_type{});
+  };
+#pragma unroll
+  for (int g = 0; g < kRegGroups; ++g) {
+    const unsigned long long cmask = cc.cm[g];
+    ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
+    if (!cmask) continue;
+    if (g == 0) {
+      group(cmask, cc.mv[0], G0, G1, G2);
+    } else {
+      const int j = 64 * g + lane;
+      group(cmask, cc.mv[g], j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
+            j < M ? rec[2 * M + j] : zr);
+    }
+  }
+  for (int g = kRegGroups; 64 * g < M; ++g) {
+    const uint4 m4 = *reinterpret_cast<const uint4*>(wm + 4 * g);
+    // (readfirstlane returns int: widen through uint32_t, not sign-extended)
+    auto u64 = [](uint32_t lo, uint32_t hi) {
+      return static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo))) |
+             (static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi)))
+              << 32);
+    };
+    const unsigned long long cmask = u64(m4.x, m4.y);
+    ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
+    if (!cmask) continue;
+    const int j = 64 * g + lane;
+    group(cmask, u64(m4.z, m4.w), j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
+          j < M ? rec[2 * M + j] : zr);
   }
   cc.pairs += ncand * cc.nok;
   PRIEST_PROJ_MARK(8);
