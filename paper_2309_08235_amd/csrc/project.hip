@@ -111,13 +111,15 @@ struct Layout {  // offsets into dynamic LDS, in floats
 // cm: per-wave obstacle candidate masks (4 words per 64 obstacles); xs: the
 // block's samples; mu/L/z: sampler staging.  NB = 16-step blocks of the
 // launch, SPB = samples per block.
-__host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int SPB, int mode) {
+// MB: partial slots per buffer, the power of two >= NB the sum tree runs over
+// (slots NB..MB-1 hold zeros).
+__host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int MB, int SPB, int mode) {
   Layout l{};
   const int D = dims * nv, D4 = round4(D);
   int o = 0;
   l.rec = o; o += 12 * M;
   l.xt = o;  o += NB * kXtBlock;
-  l.gp = o;  o += 2 * NB * 256;
+  l.gp = o;  o += 2 * MB * 256;
   l.fin = o; o += 2 * 16 * NB * SPB;
   l.cm = o;  o += NB * 4 * ((M + 63) / 64);
   l.xs = o;  o += SPB * D4;
@@ -429,6 +431,12 @@ __device__ void build_records(const float* obs, int M, int t, int nt, float4* re
   }
 }
 
+// Coefficient held at row slot 4 q + r of the MFMA layouts (coefficient rows
+// of xi_bar, lambda, g and the KKT blocks): slots r = 0..2 of the four q carry
+// coefficients 0..11 and slot r = 3 carries 12..15, so for n_coeff <= 12 the
+// k-chunk r = 3 of every product over coefficients is zero and is skipped.
+__device__ __forceinline__ int coef_of(int q, int r) { return r < 3 ? 3 * q + r : 12 + q; }
+
 // Groups of 64 obstacles whose candidate masks stay in (scalar) registers;
 // the masks of further groups live in LDS.
 constexpr int kRegGroups = 2;
@@ -691,7 +699,16 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, TW = blockDim.x >> 6;
   const int NB = TW * RT;
   const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv, D4 = round4(D);
-  const Layout l = layout(DIMS, nv, M, NB, SPB, a.mode);
+  const Layout l = layout(DIMS, nv, M, NB, MB, SPB, a.mode);
+  {
+    // partial slots NB..MB-1 of both buffers stay zero (every reader passes
+    // the barrier after the first tile's staging first)
+    float* gz = sm + l.gp;
+    for (int i = tid; i < (MB - NB) * 256; i += blockDim.x) {
+      gz[NB * 256 + i] = 0.0f;
+      gz[(MB + NB) * 256 + i] = 0.0f;
+    }
+  }
   // MFMA column layout: q = row group, col = AS*cs + cx
   const int q = lane >> 4, col = lane & 15, cs = col / AS, cx = col % AS;
   // items after the transpose: sample cs, step t0 + 16 rt + 4q + IPR cx + i
@@ -717,18 +734,20 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int tf = t0 + 16 * rt + col, cf = 4 * q + r;
+        const int tf = t0 + 16 * rt + col, cf = coef_of(q, r);
         Af[rt][d][r] = (tf < K && cf < nv) ? a.W[(tf * 3 + d) * nv + cf] : 0.0f;
-        const int tb = t0 + 16 * rt + 4 * q + r;
-        Ab[rt][d][r] = (tb < K && col < nv) ? a.W[(tb * 3 + d) * nv + col] : 0.0f;
+        const int tb = t0 + 16 * rt + 4 * q + r, cb = coef_of(col >> 2, col & 3);
+        Ab[rt][d][r] = (tb < K && cb < nv) ? a.W[(tb * 3 + d) * nv + cb] : 0.0f;
       }
+  const int crow = coef_of(col >> 2, col & 3);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int cr = 4 * q + r;
-    const bool ok = (col < nv) && (cr < nv);
-    Am[r] = ok ? a.M11[col * nv + cr] : 0.0f;
-    Ap[r] = ok ? a.Pi[col * nv + cr] : 0.0f;
+    const int ck = coef_of(q, r);
+    const bool ok = (crow < nv) && (ck < nv);
+    Am[r] = ok ? a.M11[crow * nv + ck] : 0.0f;
+    Ap[r] = ok ? a.Pi[crow * nv + ck] : 0.0f;
   }
+  const bool chunk3 = nv > 12;  // slot r = 3 holds coefficients 12..15
   const float rho = a.rho;
   f4 xb;
   // mixed precision: W^T rows as BF16, M11 as a BF16 hi/lo pair
@@ -751,13 +770,17 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      // two independent depth-2 chains per row type, summed
-      const f4 Y0 = mfma(Af[rt][0][1], xb[1], mfma(Af[rt][0][0], xb[0], z)) +
-                    mfma(Af[rt][0][3], xb[3], mfma(Af[rt][0][2], xb[2], z));
-      const f4 Y1 = mfma(Af[rt][1][1], xb[1], mfma(Af[rt][1][0], xb[0], z)) +
-                    mfma(Af[rt][1][3], xb[3], mfma(Af[rt][1][2], xb[2], z));
-      const f4 Y2 = mfma(Af[rt][2][1], xb[1], mfma(Af[rt][2][0], xb[0], z)) +
-                    mfma(Af[rt][2][3], xb[3], mfma(Af[rt][2][2], xb[2], z));
+      // two independent chains per row type (k-chunks 0, 1 and 2[, 3]), summed
+      f4 T0 = mfma(Af[rt][0][2], xb[2], z), T1 = mfma(Af[rt][1][2], xb[2], z),
+         T2 = mfma(Af[rt][2][2], xb[2], z);
+      if (chunk3) {
+        T0 = mfma(Af[rt][0][3], xb[3], T0);
+        T1 = mfma(Af[rt][1][3], xb[3], T1);
+        T2 = mfma(Af[rt][2][3], xb[3], T2);
+      }
+      const f4 Y0 = mfma(Af[rt][0][1], xb[1], mfma(Af[rt][0][0], xb[0], z)) + T0;
+      const f4 Y1 = mfma(Af[rt][1][1], xb[1], mfma(Af[rt][1][0], xb[0], z)) + T1;
+      const f4 Y2 = mfma(Af[rt][2][1], xb[1], mfma(Af[rt][2][0], xb[0], z)) + T2;
       float* x0 = xt + rt * kXtBlock + xt_at(lane);
       *reinterpret_cast<f4*>(x0) = Y0;
       *reinterpret_cast<f4*>(x0 + kXtRow) = Y1;
@@ -838,7 +861,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     f4 xi, c0v;
   #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int c = 4 * q + r;
+      const int c = coef_of(q, r);
       const bool ok = colok && (c < nv);
       xi[r] = ok ? xs[cs * D4 + cx * nv + c] : 0.0f;
       float s = 0.0f;
@@ -898,7 +921,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
         }
       const f4 zb = {0.0f, 0.0f, 0.0f, 0.0f};
       const bool lowp = BF16 && (k < a.bf16_iters);
-      float* gp = sm + l.gp + (k & 1) * NB * 256;
+      float* gp = sm + l.gp + (k & 1) * MB * 256;
       if (lowp) {
         // right-hand side with BF16 operands, FP32 accumulation: one K = 16
         // MFMA per row type covers a whole 16-step block
@@ -940,7 +963,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
   #pragma unroll
         for (int b = 0; b < MB; ++b) {
           f4 v = zg;
-          if (b < NB) v = *reinterpret_cast<const f4*>(gp + b * 256 + lane * 4);
+          v = *reinterpret_cast<const f4*>(gp + b * 256 + lane * 4);
   #pragma unroll
           for (int e = 0; e < 6; ++e) {
             if ((b >> e) & 1) {
@@ -959,9 +982,13 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       if (k == 0) {
         const f4 u = lam + rho * g;
         const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
-        const f4 h1 = mfma(Ap[3], xi[3], mfma(Ap[2], xi[2], z));
+        f4 h1 = mfma(Ap[2], xi[2], z);
         const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
-        const f4 h3 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
+        f4 h3 = mfma(Am[2], u[2], z);
+        if (chunk3) {
+          h1 = mfma(Ap[3], xi[3], h1);
+          h3 = mfma(Am[3], u[3], h3);
+        }
         xb = (h0 + h1) + (h2 + h3);
       } else if (lowp) {
         // KKT product with BF16 hi/lo splits of M11 and u (three K = 16 MFMAs)
@@ -973,7 +1000,8 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       } else {
         const f4 u = (xi - xb) + lam + rho * g;
         const f4 h0 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
-        const f4 h1 = mfma(Am[3], u[3], mfma(Am[2], u[2], z));
+        f4 h1 = mfma(Am[2], u[2], z);
+        if (chunk3) h1 = mfma(Am[3], u[3], h1);
         xb = xb + (h0 + h1);
       }
       PRIEST_PROJ_MARK(5);
@@ -1039,7 +1067,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
                               : nullptr;
   #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = 4 * q + r;
+        const int c = coef_of(q, r);
         if (c < nv) {
           dst[c] = xb[r];
           if (dst2) dst2[c] = xb[r];
@@ -1143,6 +1171,10 @@ __global__ void normals_kernel(uint64_t seed, uint32_t stream, int iter, int N, 
 // ---------------------------------------------------------------------------
 int waves_for(int K, int RT) { return (K + 16 * RT - 1) / (16 * RT); }
 
+// Partial slots of the sum tree: (launch bound / 64) * RT, the bound being
+// 512 threads up to 8 waves and 1024 above.
+int partial_slots(int K, int RT) { return (waves_for(K, RT) <= 8 ? 8 : 16) * RT; }
+
 // Resident blocks per CU of one kernel instance for a block size and LDS
 // size, cached (the query is not free and launches repeat).
 struct OccKey {
@@ -1224,7 +1256,8 @@ int project_threads(int K, int row_tiles) { return 64 * waves_for(K, row_tiles);
 size_t project_lds_bytes(const ProjArgs& a) {
   const int NB = waves_for(a.K, a.row_tiles) * a.row_tiles;
   return sizeof(float) *
-         static_cast<size_t>(layout(a.dims, a.nv, a.M, NB, samples_per_block(a.axis_slots), a.mode).total);
+         static_cast<size_t>(layout(a.dims, a.nv, a.M, NB, partial_slots(a.K, a.row_tiles),
+                                    samples_per_block(a.axis_slots), a.mode).total);
 }
 
 void set_default_tiling(ProjArgs& a) {
