@@ -93,13 +93,14 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Transpose buffers: each lane's float4 at 4 * (lane + lane / 4) floats, i.e.
-// 16 bytes of padding after every 4 lanes, so that the reads of one item's
-// axes (lanes 4i..4i+3 of a quad, same slot) and of one column's rows fall in
-// distinct banks across the quads of a half-wave.
-constexpr int kXtRow = 320;            // one row type: 64 lanes x 4 + 16 x 4 padding
+// Transpose buffers: each lane's float4 at 4 * (lane + lane / 8) floats, i.e.
+// 16 bytes of padding after every 8 lanes.  The float4 writes (8 lanes per
+// pass) then cover all 32 banks once, and so do the quad reads of the
+// transposes (one slot of lane 4 q + x for the 8 quads q of a half-wave, x
+// fixed): slot indices 4 q + x + q / 2 are distinct modulo 8.
+constexpr int kXtRow = 288;            // one row type: 64 lanes x 4 + 8 x 4 padding
 constexpr int kXtBlock = 3 * kXtRow;   // p, v, a (or their push-outs)
-__device__ __forceinline__ int xt_at(int lane) { return 4 * (lane + (lane >> 2)); }
+__device__ __forceinline__ int xt_at(int lane) { return 4 * (lane + (lane >> 3)); }
 
 struct Layout {  // offsets into dynamic LDS, in floats
   int rec, xt, gp, fin, cm, mu, L, z, xs, total;
