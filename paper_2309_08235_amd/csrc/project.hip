@@ -176,6 +176,23 @@ __device__ __forceinline__ float wave_min(float v) {
   v = fminf(v, dpp<0x128>(v));  // row_ror:8
   return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
 }
+// Minimum / maximum over each row of 16 lanes, returned for all four rows.
+__device__ __forceinline__ void row_min4(float v, float out[4]) {
+  v = fminf(v, dpp<0xB1>(v));
+  v = fminf(v, dpp<0x4E>(v));
+  v = fminf(v, dpp<0x124>(v));
+  v = fminf(v, dpp<0x128>(v));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = lane_f(v, 16 * q);
+}
+__device__ __forceinline__ void row_max4(float v, float out[4]) {
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x124>(v));
+  v = fmaxf(v, dpp<0x128>(v));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = lane_f(v, 16 * q);
+}
 __device__ __forceinline__ float wave_max(float v) {
   v = fmaxf(v, dpp<0xB1>(v));
   v = fmaxf(v, dpp<0x4E>(v));
@@ -474,7 +491,8 @@ constexpr float kSlack = PRIEST_CULL_SLACK;
 // static obstacles by index, then the moving ones by index.
 template <int DIMS, bool LAST, int NI>
 __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const float tt[NI],
-                                                float tmid, float thalf, const bool ok[NI],
+                                                const float tmid[4], const float thalf[4],
+                                                const bool ok[NI],
                                                 const float p[NI][DIMS], float S[NI][DIMS],
                                                 float r2[NI], int lane, CullCache<NI, DIMS>& cc,
                                                 uint32_t* wm) {
@@ -499,7 +517,9 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     reuse = __ballot(far) == 0ull;
   }
   if (!reuse) {
-    float lo[DIMS], hi[DIMS];
+    // one box per row of 16 lanes (the items of 4 time steps): an obstacle is
+    // a candidate if it may come near any of the four
+    float lo[DIMS][4], hi[DIMS][4];
 #pragma unroll
     for (int x = 0; x < DIMS; ++x) {
       float mn = INFINITY, mx = -INFINITY;
@@ -508,8 +528,8 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
         mn = fminf(mn, ok[i] ? p[i][x] : INFINITY);
         mx = fmaxf(mx, ok[i] ? p[i][x] : -INFINITY);
       }
-      lo[x] = wave_min(mn);
-      hi[x] = wave_max(mx);
+      row_min4(mn, lo[x]);
+      row_max4(mx, hi[x]);
     }
     PRIEST_PROJ_MARK(6);
     float cmin = INFINITY;
@@ -518,16 +538,19 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       const int j = 64 * g + lane;
       bool cand = false, mv = false;
       if (j < M) {
-        const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y),
-                             fmaf(R1.z, tmid, R0.z)};
-        float d2 = 0.0f;
 #pragma unroll
-        for (int x = 0; x < DIMS; ++x) {
-          const float e = fmaxf(fmaxf(lo[x] - oc[x], oc[x] - hi[x]), 0.0f);
-          d2 = fmaf(e, e, d2);
+        for (int q = 0; q < 4; ++q) {
+          const float oc[3] = {fmaf(R1.x, tmid[q], R0.x), fmaf(R1.y, tmid[q], R0.y),
+                               fmaf(R1.z, tmid[q], R0.z)};
+          float d2 = 0.0f;
+#pragma unroll
+          for (int x = 0; x < DIMS; ++x) {
+            const float e = fmaxf(fmaxf(lo[x][q] - oc[x], oc[x] - hi[x][q]), 0.0f);
+            d2 = fmaf(e, e, d2);
+          }
+          const float rr = fmaf(R1.w, thalf[q], R0.w * (1.0f + kSlack));
+          cand = cand || (d2 < rr * rr);
         }
-        const float rr = fmaf(R1.w, thalf, R0.w * (1.0f + kSlack));
-        cand = d2 < rr * rr;
         mv = R1.w != 0.0f;
         cmin = fminf(cmin, R0.w);
       }
@@ -644,8 +667,9 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
 }
 
 template <int DIMS, bool LAST, int NI>
-__device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI], float tmid,
-                                          float thalf, const bool ok[NI], const float p[NI][DIMS],
+__device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI],
+                                          const float tmid[4], const float thalf[4],
+                                          const bool ok[NI], const float p[NI][DIMS],
                                           const float v[NI][DIMS], const float ac[NI][DIMS],
                                           float vmax, float amax, const Box& box,
                                           float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS],
@@ -721,8 +745,13 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     t_item[n] = t0 + 16 * (n / IPR) + 4 * q + IPR * cx + (n % IPR);
     tt[n] = a.dt * static_cast<float>(t_item[n]);
   }
-  const float thalf = a.dt * (8.0f * RT - 0.5f);
-  const float tmid = a.dt * (static_cast<float>(t0) + (8.0f * RT - 0.5f));
+  // time window of each row of 16 lanes: steps t0 + 16 rt + 4 q + 0..3
+  float tmid[4], thalf[4];
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    thalf[qq] = a.dt * (8.0f * (RT - 1) + 1.5f);
+    tmid[qq] = a.dt * (static_cast<float>(t0 + 4 * qq) + 8.0f * (RT - 1) + 1.5f);
+  }
 
   float4* rec = reinterpret_cast<float4*>(sm + l.rec);
   float* xs = sm + l.xs;

@@ -63,10 +63,11 @@ def test_pair_count_exact_when_obstacles_cover_or_avoid_everything(P, wl, N):
     for c in prob.tiling_candidates():
         prob.set_tiling(c)
         assert _count(P, prob, bc, big, xi, n_iter) == want, c
-    # bounded by the brute-force count on the real scene; off means no count
+    # bounded by the brute-force count on the real scene (which may cull
+    # every pair); off means no count
     prob.set_tiling(None)
     n = _count(P, prob, bc, obs, xi, n_iter)
-    assert 0 < n <= want
+    assert 0 <= n <= want
     prob.project(t32(bc), t32(obs), t32(xi), n_iter)
     torch.cuda.synchronize()
     assert P.priest_profile_read_pairs() == 0
