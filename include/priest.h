@@ -179,6 +179,18 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs,
                        const float* xi_in, int32_t N, int32_t n_iter,
                        float* xi_out, float* resid, float* c1, void* stream);
 
+/* priest_project with the residual history of Alg. 1's projection: resid_hist
+ * [n_iter][N] receives, for every iteration k and sample i, the norm
+ * ||F xi_bar^k - e^{k+1}||_2 of the push-outs that iteration computes from
+ * its iterate (Appendix eqs. (15a)-(15f)), i.e. the residual of xi_bar^k;
+ * resid (nullable) is that of the returned iterate as in priest_project.
+ * Runs the default tile shape (no autotuning); xi_out equals priest_project's
+ * output under that shape bit for bit.  Errors as priest_project, and
+ * INVALID when resid_hist is NULL. */
+int32_t priest_project_hist(priest_problem* p, const float* bc, const float* obs,
+                            const float* xi_in, int32_t N, int32_t n_iter, float* xi_out,
+                            float* resid, float* c1, float* resid_hist, void* stream);
+
 /* The same projection as priest_project in its plain, unfused form, kept as
  * the baseline the fused kernel is measured against: per iteration three
  * kernels - forward rows p, v, a of every (sample, t) to HBM; closed-form

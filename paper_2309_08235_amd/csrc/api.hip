@@ -659,6 +659,36 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   return PRIEST_OK;
 }
 
+int32_t priest_project_hist(priest_problem* p, const float* bc, const float* obs,
+                            const float* xi_in, int32_t N, int32_t n_iter, float* xi_out,
+                            float* resid, float* c1, float* resid_hist, void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);
+  if (n_iter < 0) return fail(PRIEST_ERR_INVALID, "n_iter must be >= 0");
+  if (!bc || !xi_in || !xi_out || !resid_hist)
+    return fail(PRIEST_ERR_INVALID, "bc, xi_in, xi_out and resid_hist are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  if (N == 0) return PRIEST_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProjArgs a = base_args(p);
+  a.N = N;
+  a.n_iter = n_iter;
+  a.bf16_iters = bf16_iters(p, n_iter);
+  a.mode = kFromInput;
+  a.bc = bc;
+  a.obs = obs;
+  a.xi_in = xi_in;
+  a.xi_out = xi_out;
+  a.resid = resid;
+  a.c1 = c1;
+  a.resid_hist = resid_hist;
+  apply_tiling(a, tile_candidates(a.dims)[0]);  // the default shape
+  const int32_t st = check_lds(p, a);
+  if (st != PRIEST_OK) return st;
+  HIP_TRY(launch_project_timed(a, 1, s));
+  return PRIEST_OK;
+}
+
 int32_t priest_project_unfused_workspace_size(const priest_problem* p, int32_t N, size_t* bytes) {
   if (!p || !bytes) return fail(PRIEST_ERR_INVALID, "problem and bytes are required");
   if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);

@@ -73,6 +73,9 @@ struct ProjArgs {
   // profiling: (item, obstacle) pairs evaluated after culling, summed over
   // the launch (nullable)
   unsigned long long* pair_count;
+  // per-iteration residual history [n_iter][N] (nullable; default shape, one
+  // problem)
+  float* resid_hist;
 };
 
 // Arguments of the selection / refit / Cholesky kernel (one block per problem).

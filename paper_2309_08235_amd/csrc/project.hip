@@ -103,7 +103,7 @@ constexpr int kXtBlock = 3 * kXtRow;   // p, v, a (or their push-outs)
 __device__ __forceinline__ int xt_at(int lane) { return 4 * (lane + (lane >> 3)); }
 
 struct Layout {  // offsets into dynamic LDS, in floats
-  int rec, xt, gp, fin, cm, mu, L, z, xs, total;
+  int rec, xt, gp, fin, hist, cm, mu, L, z, xs, total;
 };
 
 // rec: obstacle records (three float4 arrays of M, structure of arrays); xt:
@@ -122,6 +122,7 @@ __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int MB
   l.xt = o;  o += NB * kXtBlock;
   l.gp = o;  o += 2 * MB * 256;
   l.fin = o; o += 2 * 16 * NB * SPB;
+  l.hist = o; o += 2 * 16 * NB * SPB;
   l.cm = o;  o += NB * 4 * ((M + 63) / 64);
   l.xs = o;  o += SPB * D4;
   l.mu = o;
@@ -316,9 +317,11 @@ __device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, cons
   return r;
 }
 
-template <int DIMS, bool LAST>
+// ACC: also accumulate the squared push-out length into r2.
+template <int DIMS, bool ACC>
 __device__ __forceinline__ void pair_add(const Rec& o, const PairTerm<DIMS>& t, float s[DIMS],
                                          float& r2) {
+  constexpr bool LAST = ACC;
 #pragma unroll
   for (int x = 0; x < DIMS; ++x) s[x] = fmaf(t.d[x], t.f, s[x]);
   if (LAST) r2 = fmaf(t.len2 * t.f, t.f, r2);
@@ -489,7 +492,7 @@ constexpr float kSlack = PRIEST_CULL_SLACK;
 // wave-level culling.  tmid / thalf: centre and half-width of the wave's time
 // window.  Candidates are added in one canonical order: per group of 64, the
 // static obstacles by index, then the moving ones by index.
-template <int DIMS, bool LAST, int NI>
+template <int DIMS, bool LAST, int NI, bool HIST = false>
 __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const float tt[NI],
                                                 const float tmid[4], const float thalf[4],
                                                 const bool ok[NI],
@@ -614,13 +617,13 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
 #pragma unroll
           for (int u = 0; u < kCandUnroll; ++u)
 #pragma unroll
-            for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o[u], tm[u][i], S[i], r2[i]);
+            for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST || HIST>(o[u], tm[u][i], S[i], r2[i]);
         } else {
           const Rec o0 = rec_of_lane<DIMS, MV>(R0, R1, R2, __builtin_ctzll(mask));
           mask &= mask - 1;
 #pragma unroll
           for (int i = 0; i < NI; ++i)
-            pair_add<DIMS, LAST>(o0, pair_term<DIMS, LAST, MV>(o0, tt[i], p[i]), S[i], r2[i]);
+            pair_add<DIMS, LAST || HIST>(o0, pair_term<DIMS, LAST, MV>(o0, tt[i], p[i]), S[i], r2[i]);
         }
       }
     };
@@ -666,7 +669,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     }
 }
 
-template <int DIMS, bool LAST, int NI>
+template <int DIMS, bool LAST, int NI, bool HIST = false>
 __device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI],
                                           const float tmid[4], const float thalf[4],
                                           const bool ok[NI], const float p[NI][DIMS],
@@ -681,7 +684,7 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
     for (int x = 0; x < DIMS; ++x) { S[i][x] = 0.0f; dv[i][x] = 0.0f; da[i][x] = 0.0f; }
     r2[i] = 0.0f;
   }
-  obstacle_pushes<DIMS, LAST, NI>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc, wm);
+  obstacle_pushes<DIMS, LAST, NI, HIST>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc, wm);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (ok[i]) {
@@ -710,7 +713,7 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
 // the problem.  The problem constants (W rows, M11, Pi) are loaded once per
 // block.  AS: MFMA column slots per sample (4, or 2 in 2D); RT: 16-step time
 // blocks per wave; MAXT: the launch bound.
-template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP>
+template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP, bool HIST = false>
 __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int stride, int total) {
   static_assert(AS == 4 || AS == 8 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
   constexpr int SPB = 16 / AS;           // samples per block
@@ -915,9 +918,17 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       forward(p, v, ac);
       PRIEST_PROJ_MARK(1);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-      item_push<DIMS, false, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
+      item_push<DIMS, false, NI, HIST>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
                                  da, r2, lane, cull, wm);
       PRIEST_PROJ_MARK(2);
+      if constexpr (HIST) {
+        // squared push-outs of this iteration per (t, sample), summed per
+        // sample after the barrier below (double-buffered by iteration)
+        float* hb = sm + l.hist + (k & 1) * 16 * NB * SPB;
+  #pragma unroll
+        for (int n = 0; n < NI; ++n)
+          if (AS <= 4 || cx < 4) hb[t_item[n] * SPB + cs] = item_ok[n] ? r2[n] : 0.0f;
+      }
       // back to the column layout: slot AS*i + x of the lane's f4 holds axis x
       // of item i
   #pragma unroll
@@ -1007,6 +1018,15 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
         }
       }
       PRIEST_PROJ_MARK(4);
+      if constexpr (HIST) {
+        // ||F xi_bar^k - e^{k+1}|| per sample, summed over t in order
+        if (tid < ns) {
+          const float* hb = sm + l.hist + (k & 1) * 16 * NB * SPB;
+          float h = 0.0f;
+          for (int t = 0; t < K; ++t) h += hb[t * SPB + tid];
+          a.resid_hist[static_cast<int64_t>(k) * a.N + s0 + tid] = sqrtf(h);
+        }
+      }
       lam += rho * g;
       const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
       if (k == 0) {
@@ -1124,6 +1144,13 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a, int total) {
   int lb = blockIdx.x;
   if ((G & 7) == 0) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   project_block<DIMS, AS, RT, MAXT, BF16, LOOP>(a, lb, G, total);
+}
+
+// The default shape with the per-iteration residual history (one problem,
+// one block per tile).
+template <int DIMS, int MAXT, bool BF16>
+__global__ __launch_bounds__(MAXT) void project_hist_kernel(ProjArgs a, int total) {
+  project_block<DIMS, 4, 1, MAXT, BF16, false, true>(a, blockIdx.x, 1, total);
 }
 
 // Descriptor table (heterogeneous requests sharing n_steps): task t owns
@@ -1255,6 +1282,13 @@ hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, h
 
 template <int DIMS, bool BF16>
 hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s) {
+  if (a.resid_hist) {  // default shape only (checked by the caller)
+    if (threads <= 512)
+      hipLaunchKernelGGL((project_hist_kernel<DIMS, 512, BF16>), dim3(total), dim3(threads), lds, s, a, total);
+    else
+      hipLaunchKernelGGL((project_hist_kernel<DIMS, 1024, BF16>), dim3(total), dim3(threads), lds, s, a, total);
+    return hipGetLastError();
+  }
   if (a.row_tiles == 2) {
     if constexpr (DIMS == 2)
       if (a.axis_slots == 2) return launch_shape<DIMS, 2, 2, 512, BF16>(a, total, threads, lds, s);
@@ -1300,6 +1334,8 @@ void set_default_tiling(ProjArgs& a) {
 hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
   if (!tiling_valid(a.dims, a.axis_slots, a.row_tiles) || a.S != samples_per_block(a.axis_slots) ||
       a.blocks_per_problem != (a.N + a.S - 1) / a.S)
+    return hipErrorInvalidValue;
+  if (a.resid_hist && (a.axis_slots != 4 || a.row_tiles != 1 || a.persistent || n_problems != 1))
     return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(a);
   const int threads = project_threads(a.K, a.row_tiles);
