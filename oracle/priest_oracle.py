@@ -141,6 +141,7 @@ class Problem:
     bc_mask: int = BC_DEFAULT
     s_min: tuple = None     # workspace bounds per axis (Appendix, G xi <= tau); None: off
     s_max: tuple = None
+    obs_model: int = 0      # 0: rows (centre, velocity, a, b); 1: per-step positions (traj)
     P: np.ndarray = field(init=False, repr=False)
     Pd: np.ndarray = field(init=False, repr=False)
     Pdd: np.ndarray = field(init=False, repr=False)
@@ -212,9 +213,27 @@ class Problem:
 # ---------------------------------------------------------------------------
 # Appendix, eqs. (10), (11a), (11b), (13), (15a)-(15c), (15f)
 # ---------------------------------------------------------------------------
+def obstacle_width(prob: Problem) -> int:
+    """Floats per obstacle row: 8 (centre at t = 0, velocity, a, b), or
+    K * dims + 2 (the position at every planning step, then a, b) when the
+    obstacles are given by their trajectories (the stacked x_o, y_o, z_o of
+    eq. (13) at every time stamp)."""
+    return 8 if prob.obs_model == 0 else prob.n_steps * prob.dims + 2
+
+
+def semi_axes(prob: Problem, obs: np.ndarray):
+    """(a, b) of every obstacle ([n_obs] each)."""
+    obs = np.asarray(obs, np.float64).reshape(-1, obstacle_width(prob))
+    return obs[:, -2], obs[:, -1]
+
+
 def obstacle_positions(prob: Problem, obs: np.ndarray) -> np.ndarray:
     """x_o,j(t_k) for constant-velocity obstacles: [n_obs, K, dims].
     ``obs`` rows are (cx, cy, cz, vx, vy, vz, a, b)."""
+    if prob.obs_model == 1:
+        w = obstacle_width(prob)
+        obs = np.asarray(obs, np.float64).reshape(-1, w)
+        return obs[:, :prob.n_steps * prob.dims].reshape(-1, prob.n_steps, prob.dims)
     obs = np.asarray(obs, np.float64).reshape(-1, 8)
     t = time_grid(prob.n_steps, prob.horizon)
     c = obs[:, 0:prob.dims]
@@ -238,14 +257,14 @@ def polar_obstacle(prob: Problem, p: np.ndarray, opos: np.ndarray, obs: np.ndarr
 
     p: [N, dims, K] robot positions; opos: [n_obs, K, dims].
     Returns alpha, beta, d with shape [N, n_obs, K]."""
-    obs = np.asarray(obs, np.float64).reshape(-1, 8)
-    a = obs[:, 6][None, :, None]
+    sa, sb = semi_axes(prob, obs)
+    a = sa[None, :, None]
     delta = p[:, None, :, :] - np.transpose(opos, (0, 2, 1))[None]  # [N, no, dims, K]
     dx, dy = delta[:, :, 0], delta[:, :, 1]
     alpha = np.arctan2(dy, dx)
     rxy = np.sqrt(dx * dx + dy * dy)
     if prob.dims == 3:
-        b = obs[:, 7][None, :, None]
+        b = sb[None, :, None]
         dz = delta[:, :, 2]
         beta = np.arctan2(rxy / a, dz / b)
         d = np.maximum(1.0, np.sqrt((dx * dx + dy * dy) / a ** 2 + dz * dz / b ** 2))
@@ -286,13 +305,13 @@ def targets(prob: Problem, obs: np.ndarray, xi_bar: np.ndarray) -> np.ndarray:
     dims, K, no = prob.dims, prob.n_steps, prob.n_obs
     yo, yv, ya = split_rows(prob, y)
     e = np.zeros((N, dims, prob.n_rows_axis))
-    obs = np.asarray(obs, np.float64).reshape(-1, 8)
     if no > 0:
         p = yo[:, :, 0, :]  # every F_o block row reproduces the position P c
         opos = obstacle_positions(prob, obs)
         alpha, beta, d = polar_obstacle(prob, p, opos, obs)
         u = _direction(alpha, beta, dims)
-        semi = [obs[:, 6], obs[:, 6], obs[:, 7]]
+        sa, sb = semi_axes(prob, obs)
+        semi = [sa, sa, sb]
         for ax in range(dims):
             eo = opos[None, :, :, ax] + semi[ax][None, :, None] * d * u[ax]
             e[:, ax, :no * K] = eo.reshape(N, no * K)
@@ -409,12 +428,12 @@ def residual(prob: Problem, obs: np.ndarray, xi_bar: np.ndarray) -> np.ndarray:
     v = np.einsum('kc,nac->nak', prob.Pd, C)
     a = np.einsum('kc,nac->nak', prob.Pdd, C)
     r2 = np.zeros(N)
-    obs = np.asarray(obs, np.float64).reshape(-1, 8)
     if prob.n_obs:
         opos = obstacle_positions(prob, obs)
+        sas, sbs = semi_axes(prob, obs)
         for j in range(prob.n_obs):
             delta = p - opos[j].T[None]  # [N, dims, K]
-            sa, sb = obs[j, 6], obs[j, 7]
+            sa, sb = sas[j], sbs[j]
             n2 = (delta[:, 0] ** 2 + delta[:, 1] ** 2) / sa ** 2
             if dims == 3:
                 n2 = n2 + delta[:, 2] ** 2 / sb ** 2

@@ -134,6 +134,36 @@ def obstacles(wl: Workload, seed: int) -> np.ndarray:
     return obs
 
 
+def time_stamps(wl: Workload) -> np.ndarray:
+    """The planning time stamps of a scene, k T / (K - 1)."""
+    return np.arange(wl.n_steps) * (wl.horizon / (wl.n_steps - 1))
+
+
+def trajectory_obstacles(wl: Workload, obs: np.ndarray, swirl: float = 0.0,
+                         seed: int = 0) -> np.ndarray:
+    """Obstacles of ``obs`` ([M, 8] rows) given by their positions at every
+    time stamp: [M, K * dims + 2] rows (positions step by step, then a, b).
+    swirl = 0 reproduces the constant-velocity motion of ``obs``; swirl > 0
+    adds a circular motion of that radius (random phase and angular speed
+    up to 1 rad/s) on top, a path no constant velocity follows."""
+    d, K = wl.dims, wl.n_steps
+    t = time_stamps(wl)
+    M = obs.shape[0]
+    pos = obs[:, None, :d] + obs[:, None, 3:3 + d] * t[None, :, None]
+    if swirl > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        ph = rng.uniform(0.0, 2.0 * np.pi, M)
+        om = rng.uniform(-1.0, 1.0, M)
+        ang = ph[:, None] + om[:, None] * t[None, :]
+        pos[:, :, 0] += swirl * (np.cos(ang) - np.cos(ph)[:, None])
+        pos[:, :, 1] += swirl * (np.sin(ang) - np.sin(ph)[:, None])
+    out = np.zeros((M, K * d + 2))
+    out[:, :K * d] = pos.reshape(M, K * d)
+    out[:, -2] = obs[:, 6]
+    out[:, -1] = obs[:, 7]
+    return out
+
+
 def initial_mean(wl: Workload) -> np.ndarray:
     """mu^0: coefficients spaced evenly on the start-goal segment, per axis."""
     n = wl.n_coeff - 1
