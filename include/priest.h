@@ -25,6 +25,8 @@
  *      obs [n_obs][8] (cx, cy, cz, vx, vy, vz, a, b): obstacle centre at t=0,
  *                     constant velocity, semi-axes (a, a, b) of eq. (1e);
  *                     in 2D cz, vz and b are ignored (circles of radius a).
+ *                     With obs_model PRIEST_OBS_PATH the rows are
+ *                     [n_obs][K * dims + 2] instead (positions per step, a, b).
  *  - Return value: PRIEST_OK or a negative status; no exception or abort
  *    crosses the ABI.  priest_last_error() returns a thread-local message
  *    describing the last failure on the calling thread.
@@ -59,6 +61,14 @@ extern "C" {
 /* The four rows of the paper's block of A. */
 #define PRIEST_BC_DEFAULT (PRIEST_BC_P0 | PRIEST_BC_V0 | PRIEST_BC_A0 | PRIEST_BC_PF)
 
+/* Obstacle models (layout of the obs rows). */
+#define PRIEST_OBS_VELOCITY 0 /* obs [n_obs][8]: centre at t = 0, constant velocity, a, b */
+#define PRIEST_OBS_PATH 1     /* obs [n_obs][K * dims + 2]: the obstacle's position at every
+                                 planning step t_k (x, y[, z] per step), then a, b: the
+                                 stacked obstacle positions of eq. (13) given directly.
+                                 Projections of such problems use the default tile shape;
+                                 the unfused form and the server do not take them. */
+
 #define PRIEST_FP32 0        /* every product in FP32 */
 #define PRIEST_BF16_MIXED 1  /* BF16 operands for the right-hand-side assembly F^T(e - F xi),
                                 FP32 accumulation, last n_refine_fp32 iterations in FP32 */
@@ -88,6 +98,8 @@ typedef struct priest_problem_desc {
                             I + rho F^T F, so they are part of the problem */
   double s_min[3];       /* use_bounds: lower limits per axis (-inf allowed), <= s_max */
   double s_max[3];       /* use_bounds: upper limits per axis (+inf allowed) */
+  int32_t obs_model;     /* PRIEST_OBS_VELOCITY or PRIEST_OBS_PATH: layout of obs rows */
+  int32_t reserved2;     /* must be 0 */
 } priest_problem_desc;
 
 /* Trajectory cost c1 of Alg. 1 (the remark of Sec. II that c1 need not be

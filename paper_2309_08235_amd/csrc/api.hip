@@ -130,6 +130,9 @@ int32_t validate_desc(const priest_problem_desc* d) {
     return fail(PRIEST_ERR_INVALID, "unknown precision");
   if (d->n_refine_fp32 < 0) return fail(PRIEST_ERR_INVALID, "n_refine_fp32 must be >= 0");
   if (d->use_bounds != 0 && d->use_bounds != 1) return fail(PRIEST_ERR_INVALID, "use_bounds must be 0 or 1");
+  if (d->obs_model != PRIEST_OBS_VELOCITY && d->obs_model != PRIEST_OBS_PATH)
+    return fail(PRIEST_ERR_INVALID, "unknown obstacle model");
+  if (d->reserved2 != 0) return fail(PRIEST_ERR_INVALID, "reserved2 must be 0");
   if (d->use_bounds)
     for (int x = 0; x < d->dims; ++x)
       if (std::isnan(d->s_min[x]) || std::isnan(d->s_max[x]) || !(d->s_min[x] <= d->s_max[x]))
@@ -186,6 +189,7 @@ ProjArgs base_args(const priest_problem* p) {
   a.dt = static_cast<float>(d.horizon / (d.n_steps - 1));
   a.vmax = static_cast<float>(d.v_max);
   a.amax = static_cast<float>(d.a_max);
+  a.traj = d.obs_model == PRIEST_OBS_PATH ? 1 : 0;
   a.box.on = d.use_bounds;
   for (int x = 0; x < 3; ++x) {
     a.box.lo[x] = d.use_bounds ? static_cast<float>(d.s_min[x]) : -INFINITY;
@@ -341,7 +345,7 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
   a.bc = bc;
   a.bc_stride = static_cast<int64_t>(a.dims) * 6;
   a.obs = obs;
-  a.obs_stride = static_cast<int64_t>(a.M) * 8;
+  a.obs_stride = static_cast<int64_t>(a.M) * (a.traj ? a.K * a.dims + 2 : 8);
   a.mu = mu;
   a.mu_stride = D;
   a.L = wL;
@@ -504,6 +508,10 @@ int32_t priest_init_problem(const priest_problem_desc* desc, void* stream, pries
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
   p->lds_limit = prop.sharedMemPerBlock;
+  if (d.obs_model == PRIEST_OBS_PATH) {  // obstacle paths run the default shape only
+    p->forced = true;
+    p->force_cfg = TileCfg{4, 1, 0};
+  }
 
   // Bernstein rows (FP64): P, Pdot, Pddot at t_k = k T/(K-1)
   std::vector<double> P(K * nv), Pd(K * nv), Pdd(K * nv);
@@ -707,6 +715,8 @@ int32_t priest_project_unfused(priest_problem* p, const float* bc, const float* 
   if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
   if (p->desc.precision != PRIEST_FP32)
     return fail(PRIEST_ERR_INVALID, "the unfused form is FP32 only");
+  if (p->desc.obs_model != PRIEST_OBS_VELOCITY)
+    return fail(PRIEST_ERR_INVALID, "the unfused form takes constant-velocity obstacles only");
   if (N == 0) return PRIEST_OK;
   size_t need = 0;
   priest_project_unfused_workspace_size(p, N, &need);
@@ -896,6 +906,11 @@ int32_t priest_tiling_candidates(const priest_problem* p, priest_tiling* out, in
 int32_t priest_set_tiling(priest_problem* p, const priest_tiling* t) {
   if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
   std::lock_guard<std::mutex> lk(p->tune_mu);
+  if (p->desc.obs_model == PRIEST_OBS_PATH) {
+    if (t && (t->axis_slots != 4 || t->row_tiles != 1 || t->persistent != 0 || t->reserved != 0))
+      return fail(PRIEST_ERR_INVALID, "problems with obstacle paths use the default tile shape");
+    return PRIEST_OK;
+  }
   if (!t) {
     p->forced = false;
     return PRIEST_OK;

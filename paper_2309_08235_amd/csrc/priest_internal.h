@@ -51,6 +51,7 @@ struct ProjArgs {
   uint64_t seed;               // Philox key
   float rho, dt, vmax, amax;   // vmax/amax may be +inf
   Box box;                     // workspace bounds (box.on = 0: none)
+  int32_t traj;                // 1: obstacle rows are paths [K * dims] + (a, b)
   CostArgs cost;               // c1 of the final pass
   // problem constants (shared by all problems of the launch)
   const float* W;    // [K][3][nv] rows of P, Pdot, Pddot

@@ -437,15 +437,44 @@ __device__ __forceinline__ float weighted_cost(const float p[DIMS], const float 
 }
 
 // Record table of one scene (any number of threads).
-template <int DIMS>
-__device__ void build_records(const float* obs, int M, int t, int nt, float4* rec) {
+template <int DIMS, bool TRAJ = false>
+__device__ void build_records(const float* obs, int M, int t, int nt, float4* rec, int K = 0) {
+  // TRAJ: rows of K positions then (a, b); the record holds the centre and
+  // radius of a sphere around the whole path (R1 = (radius, 0, 0, 0)), which
+  // the cull test treats as a static obstacle grown by that radius
+  const int width = TRAJ ? K * DIMS + 2 : 8;
   for (int j = t; j < M; j += nt) {
-    const float* o = obs + 8 * j;
-    const float a = o[6], b = (DIMS == 3) ? o[7] : o[6];
-    const float cz = (DIMS == 3) ? o[2] : 0.0f, vz = (DIMS == 3) ? o[5] : 0.0f;
-    const float sp = sqrtf(o[3] * o[3] + o[4] * o[4] + vz * vz);
-    rec[j] = make_float4(o[0], o[1], cz, fmaxf(a, b) * 1.001f + 1.0e-4f);
-    rec[M + j] = make_float4(o[3], o[4], vz, sp);
+    const float* o = obs + static_cast<int64_t>(width) * j;
+    const float a = o[width - 2], b = (DIMS == 3) ? o[width - 1] : o[width - 2];
+    float c[3] = {o[0], o[1], DIMS == 3 ? o[2] : 0.0f}, v[3] = {0.0f, 0.0f, 0.0f};
+    float sp = 0.0f;
+    if constexpr (TRAJ) {
+      float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (int k = 0; k < K; ++k)
+        for (int x = 0; x < DIMS; ++x) {
+          lo[x] = fminf(lo[x], o[k * DIMS + x]);
+          hi[x] = fmaxf(hi[x], o[k * DIMS + x]);
+        }
+      for (int x = 0; x < DIMS; ++x) c[x] = 0.5f * (lo[x] + hi[x]);
+      for (int k = 0; k < K; ++k) {
+        float d2 = 0.0f;
+        for (int x = 0; x < DIMS; ++x) {
+          const float e = o[k * DIMS + x] - c[x];
+          d2 = fmaf(e, e, d2);
+        }
+        sp = fmaxf(sp, d2);
+      }
+      sp = sqrtf(sp) * 1.0001f + 1.0e-5f;  // rounding margin of the bound
+      rec[j] = make_float4(c[0], c[1], c[2], fmaxf(a, b) * 1.001f + 1.0e-4f);
+      rec[M + j] = make_float4(sp, 0.0f, 0.0f, 0.0f);
+    } else {
+      v[0] = o[3];
+      v[1] = o[4];
+      v[2] = (DIMS == 3) ? o[5] : 0.0f;
+      sp = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      rec[j] = make_float4(c[0], c[1], c[2], fmaxf(a, b) * 1.001f + 1.0e-4f);
+      rec[M + j] = make_float4(v[0], v[1], v[2], sp);
+    }
     // 3D keeps rsq(1/b^2), the canonical zero-offset push-out, in place of a^2
     const float ib2 = 1.0f / (b * b);
     rec[2 * M + j] = make_float4(a, (DIMS == 3) ? rsq(ib2) : a * a, 1.0f / (a * a), ib2);
@@ -492,13 +521,14 @@ constexpr float kSlack = PRIEST_CULL_SLACK;
 // wave-level culling.  tmid / thalf: centre and half-width of the wave's time
 // window.  Candidates are added in one canonical order: per group of 64, the
 // static obstacles by index, then the moving ones by index.
-template <int DIMS, bool LAST, int NI, bool HIST = false>
+template <int DIMS, bool LAST, int NI, bool HIST = false, bool TRAJ = false>
 __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const float tt[NI],
                                                 const float tmid[4], const float thalf[4],
                                                 const bool ok[NI],
                                                 const float p[NI][DIMS], float S[NI][DIMS],
                                                 float r2[NI], int lane, CullCache<NI, DIMS>& cc,
-                                                uint32_t* wm) {
+                                                uint32_t* wm, const float* opath = nullptr,
+                                                const int* tstep = nullptr, int K = 0) {
   // records of the first group, issued before anything waits on LDS
   const float4 zr = make_float4(0, 0, 0, 0);
   const float4 G0 = lane < M ? rec[lane] : zr, G1 = lane < M ? rec[M + lane] : zr,
@@ -543,18 +573,21 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       if (j < M) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float oc[3] = {fmaf(R1.x, tmid[q], R0.x), fmaf(R1.y, tmid[q], R0.y),
-                               fmaf(R1.z, tmid[q], R0.z)};
+          // (paths: the sphere around the whole path, grown by its radius)
+          const float oc[3] = {TRAJ ? R0.x : fmaf(R1.x, tmid[q], R0.x),
+                               TRAJ ? R0.y : fmaf(R1.y, tmid[q], R0.y),
+                               TRAJ ? R0.z : fmaf(R1.z, tmid[q], R0.z)};
           float d2 = 0.0f;
 #pragma unroll
           for (int x = 0; x < DIMS; ++x) {
             const float e = fmaxf(fmaxf(lo[x][q] - oc[x], oc[x] - hi[x][q]), 0.0f);
             d2 = fmaf(e, e, d2);
           }
-          const float rr = fmaf(R1.w, thalf[q], R0.w * (1.0f + kSlack));
+          const float rr = TRAJ ? fmaf(R0.w, 1.0f + kSlack, R1.x)
+                                : fmaf(R1.w, thalf[q], R0.w * (1.0f + kSlack));
           cand = cand || (d2 < rr * rr);
         }
-        mv = R1.w != 0.0f;
+        mv = !TRAJ && R1.w != 0.0f;
         cmin = fminf(cmin, R0.w);
       }
       mask = __ballot(cand);
@@ -596,8 +629,27 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
   // the candidates of one group, kCandUnroll at a time (their offsets and
   // factors are independent), added in the canonical order, the tail one at a
   // time; R0..R2 hold the group's records, obstacle 64 g + lane in this lane
-  auto group = [&](unsigned long long cmask, unsigned long long mvmask, float4 R0, float4 R1,
-                   float4 R2) {
+  auto group = [&](int base, unsigned long long cmask, unsigned long long mvmask, float4 R0,
+                   float4 R1, float4 R2) {
+    if constexpr (TRAJ) {
+      // obstacle positions at each item's own time step, read from the path
+      unsigned long long mask = cmask;
+      while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        Rec o = rec_of_lane<DIMS, false>(R0, R1, R2, b);
+        const float* path = opath + static_cast<int64_t>(base + b) * (K * DIMS + 2);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          const float* pt = path + min(tstep[i], K - 1) * DIMS;
+          o.cx = pt[0];
+          o.cy = pt[1];
+          if constexpr (DIMS == 3) o.cz = pt[2];
+          pair_add<DIMS, LAST || HIST>(o, pair_term<DIMS, LAST, false>(o, tt[i], p[i]), S[i], r2[i]);
+        }
+      }
+      return;
+    }
     auto run = [&](unsigned long long mask, auto moving_tag) {
       constexpr bool MV = decltype(moving_tag)::value;
       PRIEST_PROJ_COUNT(__builtin_popcountll(mask));
@@ -636,10 +688,10 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
     if (!cmask) continue;
     if (g == 0) {
-      group(cmask, cc.mv[0], G0, G1, G2);
+      group(0, cmask, cc.mv[0], G0, G1, G2);
     } else {
       const int j = 64 * g + lane;
-      group(cmask, cc.mv[g], j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
+      group(64 * g, cmask, cc.mv[g], j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
             j < M ? rec[2 * M + j] : zr);
     }
   }
@@ -655,7 +707,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
     if (!cmask) continue;
     const int j = 64 * g + lane;
-    group(cmask, u64(m4.z, m4.w), j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
+    group(64 * g, cmask, u64(m4.z, m4.w), j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
           j < M ? rec[2 * M + j] : zr);
   }
   cc.pairs += ncand * cc.nok;
@@ -669,7 +721,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     }
 }
 
-template <int DIMS, bool LAST, int NI, bool HIST = false>
+template <int DIMS, bool LAST, int NI, bool HIST = false, bool TRAJ = false>
 __device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI],
                                           const float tmid[4], const float thalf[4],
                                           const bool ok[NI], const float p[NI][DIMS],
@@ -677,14 +729,16 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
                                           float vmax, float amax, const Box& box,
                                           float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS],
                                           float r2[NI], int lane, CullCache<NI, DIMS>& cc,
-                                          uint32_t* wm) {
+                                          uint32_t* wm, const float* opath = nullptr,
+                                          const int* tstep = nullptr, int K = 0) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
     for (int x = 0; x < DIMS; ++x) { S[i][x] = 0.0f; dv[i][x] = 0.0f; da[i][x] = 0.0f; }
     r2[i] = 0.0f;
   }
-  obstacle_pushes<DIMS, LAST, NI, HIST>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc, wm);
+  obstacle_pushes<DIMS, LAST, NI, HIST, TRAJ>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc, wm,
+                                               opath, tstep, K);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (ok[i]) {
@@ -713,7 +767,8 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
 // the problem.  The problem constants (W rows, M11, Pi) are loaded once per
 // block.  AS: MFMA column slots per sample (4, or 2 in 2D); RT: 16-step time
 // blocks per wave; MAXT: the launch bound.
-template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP, bool HIST = false>
+template <int DIMS, int AS, int RT, int MAXT, bool BF16, bool LOOP, bool HIST = false,
+          bool TRAJ = false>
 __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int stride, int total) {
   static_assert(AS == 4 || AS == 8 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
   constexpr int SPB = 16 / AS;           // samples per block
@@ -845,7 +900,9 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     // ---- scene records, samples ---------------------------------------------
     // (every reader of the previous tile's records passed the barrier that
     // precedes its epilogue)
-    if (prob != cur_prob) build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
+    if (prob != cur_prob)
+      build_records<DIMS, TRAJ>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec, K);
+    const float* opath = a.obs + prob * a.obs_stride;
     cur_prob = prob;
     if (a.mode == kFromInput) {
       const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(s0) * D;
@@ -918,8 +975,8 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       forward(p, v, ac);
       PRIEST_PROJ_MARK(1);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-      item_push<DIMS, false, NI, HIST>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
-                                 da, r2, lane, cull, wm);
+      item_push<DIMS, false, NI, HIST, TRAJ>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax,
+                                             a.box, S, dv, da, r2, lane, cull, wm, opath, t_item, K);
       PRIEST_PROJ_MARK(2);
       if constexpr (HIST) {
         // squared push-outs of this iteration per (t, sample), summed per
@@ -1062,8 +1119,8 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
       float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS];
       forward(p, v, ac);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-      item_push<DIMS, true, NI>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax, a.box, S, dv,
-                                da, r2, lane, cull, wm);
+      item_push<DIMS, true, NI, false, TRAJ>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax,
+                                             a.box, S, dv, da, r2, lane, cull, wm, opath, t_item, K);
       float* fin = sm + l.fin;
       // segment of the path-following term: start p0 -> goal pf of this problem
       float sg[DIMS], ug[DIMS], iuu = 0.0f;
@@ -1146,11 +1203,11 @@ __global__ __launch_bounds__(MAXT) void project_kernel(ProjArgs a, int total) {
   project_block<DIMS, AS, RT, MAXT, BF16, LOOP>(a, lb, G, total);
 }
 
-// The default shape with the per-iteration residual history (one problem,
-// one block per tile).
-template <int DIMS, int MAXT, bool BF16>
-__global__ __launch_bounds__(MAXT) void project_hist_kernel(ProjArgs a, int total) {
-  project_block<DIMS, 4, 1, MAXT, BF16, false, true>(a, blockIdx.x, 1, total);
+// The default shape with the per-iteration residual history (HIST, one
+// problem) and/or obstacles given by their paths (TRAJ); one block per tile.
+template <int DIMS, int MAXT, bool BF16, bool HIST, bool TRAJ>
+__global__ __launch_bounds__(MAXT) void project_special_kernel(ProjArgs a, int total) {
+  project_block<DIMS, 4, 1, MAXT, BF16, false, HIST, TRAJ>(a, blockIdx.x, 1, total);
 }
 
 // Descriptor table (heterogeneous requests sharing n_steps): task t owns
@@ -1177,7 +1234,8 @@ __global__ void offsets_kernel(ProjArgs a, const float* xi, float* out) {
   __shared__ float4 rec[3 * PRIEST_MAX_OBS];
   const int nv = a.nv, K = a.K, M = a.M;
   const int D = DIMS * nv;
-  build_records<DIMS>(a.obs, M, threadIdx.x, blockDim.x, rec);
+  if (a.traj) build_records<DIMS, true>(a.obs, M, threadIdx.x, blockDim.x, rec, K);
+  else build_records<DIMS>(a.obs, M, threadIdx.x, blockDim.x, rec);
   __syncthreads();
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= a.N * K) return;
@@ -1196,7 +1254,15 @@ __global__ void offsets_kernel(ProjArgs a, const float* xi, float* out) {
   const float tt = a.dt * static_cast<float>(t);
   float* o = out + static_cast<int64_t>(s) * (M + 2) * K * DIMS;
   for (int j = 0; j < M; ++j) {
-    const Rec r = rec_from_lds(rec, M, j);
+    Rec r = rec_from_lds(rec, M, j);
+    if (a.traj) {  // the obstacle's position at step t, from its path
+      const float* pt = a.obs + static_cast<int64_t>(j) * (K * DIMS + 2) + t * DIMS;
+      r.cx = pt[0];
+      r.cy = pt[1];
+      r.cz = (DIMS == 3) ? pt[2] : 0.0f;
+      r.vx = r.vy = r.vz = 0.0f;
+      r.moving = false;
+    }
     float S[DIMS], r2 = 0.0f;
     for (int x = 0; x < DIMS; ++x) S[x] = 0.0f;
     if (pair_push<DIMS, false>(r, tt, p, S, r2)) zero_push<DIMS, false>(r, S, r2);
@@ -1282,11 +1348,17 @@ hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, h
 
 template <int DIMS, bool BF16>
 hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s) {
-  if (a.resid_hist) {  // default shape only (checked by the caller)
-    if (threads <= 512)
-      hipLaunchKernelGGL((project_hist_kernel<DIMS, 512, BF16>), dim3(total), dim3(threads), lds, s, a, total);
-    else
-      hipLaunchKernelGGL((project_hist_kernel<DIMS, 1024, BF16>), dim3(total), dim3(threads), lds, s, a, total);
+  if (a.resid_hist || a.traj) {  // default shape only (checked by the caller)
+    const dim3 g(total), b(threads);
+    if (threads <= 512) {
+      if (a.resid_hist && a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 512, BF16, true, true>), g, b, lds, s, a, total);
+      else if (a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 512, BF16, false, true>), g, b, lds, s, a, total);
+      else hipLaunchKernelGGL((project_special_kernel<DIMS, 512, BF16, true, false>), g, b, lds, s, a, total);
+    } else {
+      if (a.resid_hist && a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 1024, BF16, true, true>), g, b, lds, s, a, total);
+      else if (a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 1024, BF16, false, true>), g, b, lds, s, a, total);
+      else hipLaunchKernelGGL((project_special_kernel<DIMS, 1024, BF16, true, false>), g, b, lds, s, a, total);
+    }
     return hipGetLastError();
   }
   if (a.row_tiles == 2) {
@@ -1335,8 +1407,9 @@ hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
   if (!tiling_valid(a.dims, a.axis_slots, a.row_tiles) || a.S != samples_per_block(a.axis_slots) ||
       a.blocks_per_problem != (a.N + a.S - 1) / a.S)
     return hipErrorInvalidValue;
-  if (a.resid_hist && (a.axis_slots != 4 || a.row_tiles != 1 || a.persistent || n_problems != 1))
+  if ((a.resid_hist || a.traj) && (a.axis_slots != 4 || a.row_tiles != 1 || a.persistent))
     return hipErrorInvalidValue;
+  if (a.resid_hist && n_problems != 1) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(a);
   const int threads = project_threads(a.K, a.row_tiles);
   const int total = n_problems * a.blocks_per_problem;

@@ -55,7 +55,8 @@ class ProblemDesc(ctypes.Structure):
                 ("v_max", ctypes.c_double), ("a_max", ctypes.c_double),
                 ("bc_mask", ctypes.c_uint32), ("precision", ctypes.c_int32),
                 ("n_refine_fp32", ctypes.c_int32), ("use_bounds", ctypes.c_int32),
-                ("s_min", ctypes.c_double * 3), ("s_max", ctypes.c_double * 3)]
+                ("s_min", ctypes.c_double * 3), ("s_max", ctypes.c_double * 3),
+                ("obs_model", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class CostParams(ctypes.Structure):
@@ -75,6 +76,7 @@ class CemParams(ctypes.Structure):
 
 
 COST_SMOOTH, COST_WEIGHTED = 0, 1
+OBS_VELOCITY, OBS_PATH = 0, 1
 UPDATE_MPPI, UPDATE_CMA = 0, 1
 
 
@@ -480,15 +482,16 @@ class Problem:
 
     def __init__(self, dims, n_coeff, n_steps, horizon, n_obs, rho=1.0, v_max=math.inf,
                  a_max=math.inf, bc_mask=BC_DEFAULT, precision=FP32, n_refine_fp32=10,
-                 s_min=None, s_max=None, stream=None):
-        """s_min / s_max (per axis, both or neither): workspace bounds."""
+                 s_min=None, s_max=None, obs_model=0, stream=None):
+        """s_min / s_max (per axis, both or neither): workspace bounds.
+        obs_model OBS_PATH: obstacle rows are paths [K * dims] + (a, b)."""
         if (s_min is None) != (s_max is None):
             raise ValueError("give both s_min and s_max, or neither")
         lo = (ctypes.c_double * 3)(*(list(s_min or ()) + [0.0] * 3)[:3])
         hi = (ctypes.c_double * 3)(*(list(s_max or ()) + [0.0] * 3)[:3])
         self.desc = ProblemDesc(dims, n_coeff, n_steps, n_obs, horizon, rho, v_max, a_max,
                                 bc_mask, precision, n_refine_fp32, 0 if s_min is None else 1,
-                                lo, hi)
+                                lo, hi, obs_model, 0)
         self.dims, self.n_coeff, self.n_steps, self.n_obs = dims, n_coeff, n_steps, n_obs
         self.D = dims * n_coeff
         self.handle = priest_init_problem(self.desc, stream)

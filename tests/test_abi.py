@@ -50,6 +50,7 @@ def _desc(P, **kw):
     (dict(v_max=0.0), -1), (dict(v_max=math.nan), -1), (dict(a_max=-2.0), -1),
     (dict(bc_mask=64), -1), (dict(precision=7), -1), (dict(use_bounds=2), -1),
     (dict(n_coeff=3, bc_mask=63), -2),
+    (dict(obs_model=2), -1), (dict(reserved2=1), -1),
     (dict(use_bounds=1, s_min=(1.0, 0.0, 0.0), s_max=(0.0, 1.0, 1.0)), -1),
     (dict(use_bounds=1, s_min=(0.0, math.nan, 0.0), s_max=(1.0, 1.0, 1.0)), -1),
 ])
