@@ -191,6 +191,16 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs,
                        const float* xi_in, int32_t N, int32_t n_iter,
                        float* xi_out, float* resid, float* c1, void* stream);
 
+/* priest_project for n_problems problems of the same shape in one launch:
+ * bc [P][dims][6], obs [P][n_obs][row] (row 8, or K * dims + 2 for paths),
+ * xi_in / xi_out [P][N][D], resid / c1 [P][N] (nullable).  Problem q's
+ * samples see only problem q's scene.  Tile shape as priest_project (the
+ * first call with a new (N, P) tunes it).  xi_in and xi_out may alias.
+ * Errors as priest_project. */
+int32_t priest_project_batch(priest_problem* p, int32_t n_problems, const float* bc,
+                             const float* obs, const float* xi_in, int32_t N, int32_t n_iter,
+                             float* xi_out, float* resid, float* c1, void* stream);
+
 /* priest_project with the residual history of Alg. 1's projection: resid_hist
  * [n_iter][N] receives, for every iteration k and sample i, the norm
  * ||F xi_bar^k - e^{k+1}||_2 of the push-outs that iteration computes from

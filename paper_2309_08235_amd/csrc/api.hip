@@ -667,6 +667,58 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   return PRIEST_OK;
 }
 
+int32_t priest_project_batch(priest_problem* p, int32_t n_problems, const float* bc,
+                             const float* obs, const float* xi_in, int32_t N, int32_t n_iter,
+                             float* xi_out, float* resid, float* c1, void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  if (n_problems < 1) return fail(PRIEST_ERR_INVALID, "n_problems must be >= 1");
+  if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);
+  if (n_iter < 0) return fail(PRIEST_ERR_INVALID, "n_iter must be >= 0");
+  if (!bc || !xi_in || !xi_out) return fail(PRIEST_ERR_INVALID, "bc, xi_in and xi_out are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  if (N == 0) return PRIEST_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProjArgs a = base_args(p);
+  a.N = N;
+  a.n_iter = n_iter;
+  a.bf16_iters = bf16_iters(p, n_iter);
+  a.mode = kFromInput;
+  a.bc = bc;
+  a.bc_stride = static_cast<int64_t>(a.dims) * 6;
+  a.obs = obs;
+  a.obs_stride = static_cast<int64_t>(a.M) * (a.traj ? a.K * a.dims + 2 : 8);
+  const int64_t nd = static_cast<int64_t>(N) * p->D;
+  a.xi_in = xi_in;
+  a.xi_in_stride = nd;
+  a.xi_out = xi_out;
+  a.xi_out_stride = nd;
+  a.resid = resid;
+  a.c1 = c1;
+  a.n_stride = N;
+  apply_tiling(a, tile_candidates(a.dims)[0]);
+  int32_t st = check_lds(p, a);
+  if (st != PRIEST_OK) return st;
+  TileCfg cfg{};
+  if (n_iter > 0 && autotune_enabled() && !tiling_cached(p, a, n_problems) && !stream_capturing(s)) {
+    // time the candidates with outputs in scratch (xi_in may alias xi_out)
+    float* scratch = nullptr;
+    const size_t n = static_cast<size_t>(n_problems) * N * (p->D + 2);
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&scratch), sizeof(float) * n));
+    ProjArgs t = trial_args(a);
+    t.xi_out = scratch;
+    t.resid = scratch + static_cast<size_t>(n_problems) * nd;
+    t.c1 = t.resid + static_cast<size_t>(n_problems) * N;
+    st = resolve_tiling(p, a, n_problems, s, &t, &cfg);
+    (void)hipFree(scratch);
+  } else {
+    st = resolve_tiling(p, a, n_problems, s, nullptr, &cfg);
+  }
+  if (st != PRIEST_OK) return st;
+  apply_tiling(a, cfg);
+  HIP_TRY(launch_project_timed(a, n_problems, s));
+  return PRIEST_OK;
+}
+
 int32_t priest_project_hist(priest_problem* p, const float* bc, const float* obs,
                             const float* xi_in, int32_t N, int32_t n_iter, float* xi_out,
                             float* resid, float* c1, float* resid_hist, void* stream) {

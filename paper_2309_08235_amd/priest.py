@@ -41,7 +41,7 @@ EXPORTS = (
     "priest_tiling_candidates", "priest_set_tiling", "priest_last_tiling",
     "priest_profile_enable", "priest_profile_read", "priest_project_unfused_workspace_size",
     "priest_project_unfused", "priest_plan_dpriest", "priest_profile_count_pairs",
-    "priest_profile_read_pairs", "priest_project_hist",
+    "priest_profile_read_pairs", "priest_project_hist", "priest_project_batch",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -196,6 +196,7 @@ _SIGS = {
     "priest_profile_read": (_I, [ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
     "priest_profile_count_pairs": (_I, [_I]),
     "priest_project_hist": (_I, [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P, _P]),
+    "priest_project_batch": (_I, [_P, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P]),
     "priest_profile_read_pairs": (_I, [ctypes.POINTER(ctypes.c_uint64)]),
     "priest_last_error": (ctypes.c_char_p, []),
     "priest_version": (_I, []),
@@ -373,6 +374,13 @@ def priest_profile_read():
     return n.value, ms.value
 
 
+def priest_project_batch(handle, bc, obs, xi_in, n_iter, xi_out, resid, c1, stream=None):
+    """xi_in [P, N, D]; bc [P, dims, 6]; obs [P, n_obs, row]."""
+    P_, N = xi_in.shape[0], xi_in.shape[1]
+    _check(lib().priest_project_batch(handle, P_, _ptr(bc), _ptr(obs), _ptr(xi_in), N, n_iter,
+                                      _ptr(xi_out), _ptr(resid), _ptr(c1), _stream(stream)))
+
+
 def priest_project_hist(handle, bc, obs, xi_in, n_iter, xi_out, resid, c1, resid_hist, stream=None):
     N = xi_in.shape[0]
     _check(lib().priest_project_hist(handle, _ptr(bc), _ptr(obs), _ptr(xi_in), N, n_iter,
@@ -530,6 +538,15 @@ class Problem:
         r = torch.empty(N, device=dev, dtype=torch.float32)
         c1 = torch.empty(N, device=dev, dtype=torch.float32)
         priest_project(self.handle, bc, obs, xi, n_iter, xo, r, c1, stream)
+        return xo, r, c1
+
+    def project_batch(self, bc, obs, xi, n_iter, stream=None):
+        """priest_project_batch: xi [P, N, D] -> (xi_out, resid [P, N], c1 [P, N])."""
+        P_, N = xi.shape[0], xi.shape[1]
+        xo = torch.empty_like(xi)
+        r = torch.empty((P_, N), device=xi.device, dtype=torch.float32)
+        c1 = torch.empty((P_, N), device=xi.device, dtype=torch.float32)
+        priest_project_batch(self.handle, bc, obs, xi, n_iter, xo, r, c1, stream)
         return xo, r, c1
 
     def project_hist(self, bc, obs, xi, n_iter, stream=None):
