@@ -66,13 +66,13 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 }
 
 // Lower Cholesky of the D x D matrix A (LDS) by one wave, rows padded to DM
-// with the identity; lane i keeps row i in registers.  Column j is
-// broadcast through `col` (LDS, DM floats): lane c's value of the column is
-// exactly what the update of entry c reads.  Writes L back into A (lower
-// triangle).  Returns false if a pivot is not positive and finite (it is
-// replaced by 1).
+// with the identity; lane i keeps row i in registers.  Column j of L is
+// broadcast lane by lane with readlane (lane c holds L[c][j], which the
+// update of entry c of every row needs), so the factorisation touches LDS
+// only to load A and store L.  Writes L back into A (lower triangle).
+// Returns false if a pivot is not positive and finite (it is replaced by 1).
 template <int DM>
-__device__ bool cholesky_wave(float* A, int D, int lane, float* col) {
+__device__ bool cholesky_wave(float* A, int D, int lane, float* /*col*/) {
   float row[DM];
 #pragma unroll
   for (int c = 0; c < DM; ++c)
@@ -89,15 +89,8 @@ __device__ bool cholesky_wave(float* A, int D, int lane, float* col) {
     const float ljj = b ? 1.0f : piv * inv;
     const float lij = (lane > j) ? row[j] * inv : ((lane == j) ? ljj : row[j]);
     row[j] = lij;
-    if (lane < DM) col[lane] = lij;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int c = j + 1; c < DM; ++c) row[c] = fmaf(-lij, col[c], row[c]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = j + 1; c < DM; ++c) row[c] = fmaf(-lij, bcast(lij, c), row[c]);
   }
   if (lane < D) {
 #pragma unroll
