@@ -112,6 +112,19 @@ def cpu_baseline(wl, n_sample: int, gpu_results=None):
     t0 = time.perf_counter()
     pr = O.project(prob, bc, obs, xi, wl.n_proj_iters)
     dt = time.perf_counter() - t0
+    # the same oracle with its math libraries held to one thread, on a
+    # quarter of the sample
+    n1 = max(1, n_sample // 4)
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            O.project(prob, bc, obs, xi[:n1], wl.n_proj_iters)
+            dt1 = time.perf_counter() - t1
+        one_thread = {"value": n1 * wl.n_proj_iters / dt1, "cores": 1,
+                      "sample": f"{n1} samples x {wl.n_proj_iters} projection iterations, {dt1:.1f} s"}
+    except ImportError:
+        one_thread = None
     errors = {}
     for label, (xb, r) in (gpu_results or {}).items():
         xb = np.asarray(xb, np.float64)[:n_sample]
@@ -127,7 +140,21 @@ def cpu_baseline(wl, n_sample: int, gpu_results=None):
             "cores": int(threads), "kind": "oracle",
             "sample": f"{n_sample} samples x {wl.n_proj_iters} projection iterations of the "
                       f"{wl.name} scene (one CEM iteration's projection), FP64 NumPy, {dt:.1f} s",
+            "one_thread": one_thread, "host": host_cpu(),
             "gpu_error_vs_oracle": errors}
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
 
 def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note, pairs_per_launch):
