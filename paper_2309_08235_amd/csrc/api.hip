@@ -388,6 +388,10 @@ int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const f
     a.xi_out2 = last ? out->xi_bar : nullptr;
     HIP_TRY(launch_project_timed(a, P, s));
     ca.first = (l == 0) ? 1 : 0;
+    // the selection outputs describe the last iteration; without the ordered
+    // constraint-elite set the refit selects without sorting
+    ca.elite_idx = last ? pa.ca.elite_idx : nullptr;
+    ca.proj_idx = last ? pa.ca.proj_idx : nullptr;
     HIP_TRY(launch_cem(ca, P, s));
   }
   return PRIEST_OK;

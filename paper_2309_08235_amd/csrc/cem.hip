@@ -2,10 +2,14 @@
 // eqs. (9a)-(9c)) on gfx950: one 512-thread block per problem.
 //
 //   1. ConstraintEliteSet: the n_proj samples with the lowest residual r,
-//      ordered by (r, index) - a stable block radix sort of the order-
-//      preserving bit patterns of r (ties keep index order);
+//      ordered by (r, index) over the order-preserving bit patterns of r
+//      (ties keep index order);
 //   2. EliteSet: the n_elite lowest c_aug = c1 + r among them, ties kept in
-//      the order of step 1 (second stable radix sort, on positions);
+//      the order of step 1.
+//   When the ordered set of step 1 is an output, both steps are stable block
+//   radix sorts; otherwise (N <= 2048, n_elite <= 512) they are radix selects
+//   of the boundary keys and a ranking of the n_elite survivors by counting,
+//   which select and order exactly the same samples.
 //   3. weights c_m = exp(-(c_aug_m - delta)/gamma), delta = min c_aug;
 //   4. mu' = (1-sigma) mu + sigma sum w xi_bar / sum w,
 //      Sigma' = (1-sigma) Sigma + sigma sum w (xi_bar - mu')(xi_bar - mu')^T / sum w;
@@ -29,7 +33,7 @@ constexpr int kStageFloats = 4096;  // elite rows staged in LDS per chunk
 __host__ __device__ inline size_t align16(size_t n) { return (n + 15) & ~static_cast<size_t>(15); }
 
 struct CemLayout {
-  size_t proj, elite, w, red, mu, pc, A, stage, total;
+  size_t proj, elite, w, red, mu, pc, A, mu0, cov0, pc0, stage, total;
 };
 
 __host__ __device__ inline CemLayout cem_layout(int D, int n_proj, int n_elite) {
@@ -42,6 +46,9 @@ __host__ __device__ inline CemLayout cem_layout(int D, int n_proj, int n_elite) 
   l.mu = o;    o += align16(sizeof(float) * D);
   l.pc = o;    o += align16(sizeof(float) * D);
   l.A = o;     o += align16(sizeof(float) * D * D);
+  l.mu0 = o;   o += align16(sizeof(float) * D);
+  l.cov0 = o;  o += align16(sizeof(float) * D * D);
+  l.pc0 = o;   o += align16(sizeof(float) * D);
   l.stage = o; o += align16(sizeof(float) * kStageFloats);
   l.total = o;
   return l;
@@ -65,18 +72,20 @@ __device__ __forceinline__ float bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Lower Cholesky of the D x D matrix A (LDS) by one wave, rows padded to DM
-// with the identity; lane i keeps row i in registers.  Column j of L is
-// broadcast lane by lane with readlane (lane c holds L[c][j], which the
-// update of entry c of every row needs), so the factorisation touches LDS
-// only to load A and store L.  Writes L back into A (lower triangle).
-// Returns false if a pivot is not positive and finite (it is replaced by 1).
+// Lower Cholesky factor L of A + eps I, A the D x D matrix in LDS, by one
+// wave, rows padded to DM with the identity; lane i keeps row i in registers.
+// Column j of L is broadcast lane by lane with readlane (lane c holds
+// L[c][j], which the update of entry c of every row needs), so the
+// factorisation reads LDS only to load A.  Writes L (zeros above the
+// diagonal) row by row to `L`; A is left unchanged.  Returns false if a pivot
+// is not positive and finite (it is replaced by 1).
 template <int DM>
-__device__ bool cholesky_wave(float* A, int D, int lane, float* /*col*/) {
+__device__ __forceinline__ bool cholesky_wave(const float* A, float eps, int D, int lane, float* L) {
   float row[DM];
 #pragma unroll
   for (int c = 0; c < DM; ++c)
-    row[c] = (lane < D && c < D) ? A[lane * D + c] : (lane == c ? 1.0f : 0.0f);
+    row[c] = (lane < D && c < D) ? A[lane * D + c] + (lane == c ? eps : 0.0f)
+                                 : (lane == c ? 1.0f : 0.0f);
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < DM; ++j) {
@@ -95,7 +104,7 @@ __device__ bool cholesky_wave(float* A, int D, int lane, float* /*col*/) {
   if (lane < D) {
 #pragma unroll
     for (int c = 0; c < DM; ++c)
-      if (c <= lane && c < D) A[lane * D + c] = row[c];
+      if (c < D) L[lane * D + c] = c <= lane ? row[c] : 0.0f;
   }
   return !bad;
 }
@@ -109,7 +118,7 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
 // Stable selection of the k smallest keys among n (n <= T * IPT): writes the
 // values of ranks 0..k-1 to out[] in ascending (key, input position) order.
 template <int IPT>
-__device__ void select_sorted(const uint32_t* keys_in, const int* vals_in, int n, int k,
+__device__ __forceinline__ void select_sorted(const uint32_t* keys_in, const int* vals_in, int n, int k,
                               int* out, void* temp) {
   using Sort = hipcub::BlockRadixSort<uint32_t, kCemThreads, IPT, int>;
   uint32_t key[IPT];
@@ -128,6 +137,220 @@ __device__ void select_sorted(const uint32_t* keys_in, const int* vals_in, int n
   }
 }
 
+// ---- selection without a full sort ------------------------------------------
+// Used when the ordered constraint-elite set is not asked for: the two
+// selections of steps 1 and 2 as exact radix selects (the k-th smallest key,
+// 8 bits per pass from the top), then the n_elite survivors ranked by
+// counting.  Selects exactly the samples, in exactly the order, of the two
+// stable sorts: step 1 keeps the lowest (r key, index), step 2 the lowest
+// (c_aug key, r key, index).
+
+constexpr int kFastElite = kCemThreads;  // largest n_elite of the fast selection
+static_assert(kCemThreads == 512, "index-order scans assume 8 waves");
+
+// Exclusive sum over the lanes of a wave of values below 2^12, bit-sliced:
+// one ballot per bit, no LDS.
+__device__ __forceinline__ uint32_t wave_excl_sum12(uint32_t v, int lane) {
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  uint32_t s = 0;
+#pragma unroll
+  for (int b = 0; b < 12; ++b)
+    s += static_cast<uint32_t>(__builtin_popcountll(__ballot((v >> b) & 1u) & lt)) << b;
+  return s;
+}
+
+// The k-th smallest (0-based) of the keys with valid[j] set, over the block
+// (k below their count, at most 4095 of them), 8 bits per pass from the top.
+// On return the keys whose bits under vmask are below v are the `less`
+// smallest, and `eq` keys match v under vmask, the k-th among them; vmask is
+// all ones unless the k-th key is the largest of its group after an earlier
+// pass (then the group is taken whole and the remaining passes are skipped).
+// hist: 4 x 256 zeroed LDS counters, bc: 12 LDS words.
+template <int IPT>
+__device__ __forceinline__ void radix_select(const uint32_t (&key)[IPT], const bool (&valid)[IPT],
+                                             uint32_t k, uint32_t* hist, uint32_t* bc, uint32_t& v,
+                                             uint32_t& vmask, uint32_t& less, uint32_t& eq) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  uint32_t prefix = 0, mask = 0, kk = k;
+  less = 0;
+  eq = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int shift = 24 - 8 * p;
+    uint32_t* h = hist + 256 * p;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      if (valid[j] && (key[j] & mask) == prefix) atomicAdd(h + ((key[j] >> shift) & 255u), 1u);
+    __syncthreads();
+    if (tid < 64) {
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = h[4 * lane + q];
+        sum += c[q];
+      }
+      uint32_t cum = wave_excl_sum12(sum, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (kk >= cum && kk < cum + c[q]) {
+          bc[3 * p] = 4 * lane + q;
+          bc[3 * p + 1] = cum;
+          bc[3 * p + 2] = c[q];
+        }
+        cum += c[q];
+      }
+    }
+    __syncthreads();
+    const uint32_t bin = bc[3 * p], before = bc[3 * p + 1];
+    eq = bc[3 * p + 2];
+    prefix |= bin << shift;
+    mask |= 255u << shift;
+    kk -= before;
+    less += before;
+    if (kk + 1 == eq) break;
+  }
+  v = prefix;
+  vmask = mask;
+}
+
+// Exclusive count of the set flags in index order (item j of thread t is
+// sample j * 512 + t).  wc: 8 * IPT LDS words.
+template <int IPT>
+__device__ __forceinline__ void index_scan(const bool (&f)[IPT], uint32_t (&pre)[IPT], uint32_t* wc) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const unsigned long long b = __ballot(f[j]);
+    pre[j] = static_cast<uint32_t>(__builtin_popcountll(b & lt));
+    if (lane == 0) wc[8 * j + wv] = static_cast<uint32_t>(__builtin_popcountll(b));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    uint32_t off = 0;
+    for (int x = 0; x < 8 * j + wv; ++x) off += wc[x];
+    pre[j] += off;
+  }
+}
+
+// LDS of the fast selection (words): 2 x 4 x 256 histogram counters, 24
+// broadcast words, 8 * IPT scan counts, one slot counter, and four lists of
+// kFastElite entries (c_aug keys, r keys, indices, ranks).  The counters, the
+// slot counter and the ranks must be zero on entry.
+template <int IPT>
+constexpr int fast_select_words() { return 2048 + 24 + 8 * IPT + 1 + 4 * kFastElite; }
+
+// Steps 1 and 2 for N <= 512 * IPT samples: elite[0..n_elite) receives the
+// sample indices in rank order.  vr / vc: this thread's r and c1 (sample
+// j * 512 + tid); s_r: r of every sample (LDS); gk2: N LDS words of scratch.
+template <int IPT>
+__device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float (&vc)[IPT], int N,
+                                            int n_proj, int n_elite, const float* s_r, uint32_t* ws,
+                                            uint32_t* gk2, int* elite) {
+  const int tid = threadIdx.x;
+  uint32_t* hist = ws;
+  uint32_t* bc = ws + 2048;
+  uint32_t* wc = bc + 24;
+  uint32_t* cnt = wc + 8 * IPT;
+  uint32_t* lk2 = cnt + 1;
+  uint32_t* lk1 = lk2 + kFastElite;
+  int* li = reinterpret_cast<int*>(lk1 + kFastElite);
+  uint32_t* lrank = reinterpret_cast<uint32_t*>(li + kFastElite);
+  bool valid[IPT];
+  uint32_t k1[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    valid[j] = tid + j * kCemThreads < N;
+    k1[j] = valid[j] ? ordered_bits(vr[j]) : ~0u;
+  }
+  // step 1: the n_proj lowest (r key, index)
+  uint32_t v1, m1, less1, eq1;
+  radix_select<IPT>(k1, valid, static_cast<uint32_t>(n_proj - 1), hist, bc, v1, m1, less1, eq1);
+  const uint32_t t1 = static_cast<uint32_t>(n_proj) - less1;  // members among the keys equal to v1
+  bool mem[IPT];
+  if (eq1 == t1) {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) mem[j] = valid[j] && (k1[j] & m1) <= v1;
+  } else {
+    // (only after all four passes: m1 is all ones)
+    bool tie[IPT];
+    uint32_t pre[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) tie[j] = valid[j] && k1[j] == v1;
+    index_scan<IPT>(tie, pre, wc);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) mem[j] = valid[j] && (k1[j] < v1 || (tie[j] && pre[j] < t1));
+  }
+  // step 2: the n_elite lowest (c_aug key, r key, index) among them
+  uint32_t k2[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) k2[j] = mem[j] ? ordered_bits(vc[j] + vr[j]) : ~0u;
+  uint32_t v2, m2, less2, eq2;
+  radix_select<IPT>(k2, mem, static_cast<uint32_t>(n_elite - 1), hist + 1024, bc + 12,
+                    v2, m2, less2, eq2);
+  const uint32_t t2 = static_cast<uint32_t>(n_elite) - less2;
+  bool sel[IPT];
+  if (eq2 == t2) {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) sel[j] = mem[j] && (k2[j] & m2) <= v2;
+  } else {
+    // more c_aug ties at the boundary than places left: rank the tied
+    // samples by (r key, index)
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      if (valid[j]) gk2[tid + j * kCemThreads] = k2[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      sel[j] = mem[j] && k2[j] < v2;
+      if (mem[j] && k2[j] == v2) {
+        const int i = tid + j * kCemThreads;
+        uint32_t rank = 0;
+        for (int x = 0; x < N; ++x) {
+          if (gk2[x] != v2) continue;
+          const uint32_t kx = ordered_bits(s_r[x]);
+          rank += (kx < k1[j]) || (kx == k1[j] && x < i);
+        }
+        sel[j] = rank < t2;
+      }
+    }
+  }
+  // the n_elite survivors, in slots of arbitrary order ...
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if (sel[j]) {
+      const uint32_t slot = atomicAdd(cnt, 1u);
+      if (slot < static_cast<uint32_t>(n_elite)) {
+        lk2[slot] = k2[j];
+        lk1[slot] = k1[j];
+        li[slot] = tid + j * kCemThreads;
+      }
+    }
+  }
+  __syncthreads();
+  // ... ranked by counting: Q threads per survivor, each over a share of the
+  // others
+  const int Q = kCemThreads / n_elite;
+  const int am = tid % n_elite, q = tid / n_elite;
+  if (q < Q) {
+    const uint32_t ak2 = lk2[am], ak1 = lk1[am];
+    const int ai = li[am];
+    uint32_t rk = 0;
+#pragma unroll 4
+    for (int b = q * n_elite / Q; b < (q + 1) * n_elite / Q; ++b) {
+      const uint32_t bk2 = lk2[b], bk1 = lk1[b];
+      rk += (bk2 < ak2) || (bk2 == ak2 && (bk1 < ak1 || (bk1 == ak1 && li[b] < ai)));
+    }
+    atomicAdd(lrank + am, rk);
+  }
+  __syncthreads();
+  for (int m = tid; m < n_elite; m += kCemThreads) {
+    const uint32_t rk = lrank[m];
+    if (rk < static_cast<uint32_t>(n_elite)) elite[rk] = li[m];
+  }
+}
+
 // One block's work: selection, refit and factorisation for problem `prob`
 // of `a`.  Shared by the uniform-batch kernel and the descriptor-table kernel.
 template <int IPT, int DM>
@@ -136,6 +359,11 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   __shared__ typename Sort::TempStorage sort_tmp;
   __shared__ uint32_t skey[kCemThreads * IPT];
   __shared__ int sval[kCemThreads * IPT];
+  // r and c1 of every sample, read from HBM once (up to 2048 samples; larger
+  // problems gather them from HBM)
+  constexpr bool kPre = IPT <= 4;
+  __shared__ float s_r[kPre ? kCemThreads * IPT : 1], s_c1[kPre ? kCemThreads * IPT : 1];
+  __shared__ uint32_t s_fast[kPre ? fast_select_words<IPT>() : 1];
   extern __shared__ float4 sm4[];
   char* sm = reinterpret_cast<char*>(sm4);
   const int D = a.D, N = a.N, tid = threadIdx.x, T = blockDim.x;
@@ -147,40 +375,96 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   float* muN = reinterpret_cast<float*>(sm + l.mu);
   float* pcN = reinterpret_cast<float*>(sm + l.pc);
   float* A = reinterpret_cast<float*>(sm + l.A);
+  float* mu0 = reinterpret_cast<float*>(sm + l.mu0);
+  float* cov0 = reinterpret_cast<float*>(sm + l.cov0);
+  float* pc0 = reinterpret_cast<float*>(sm + l.pc0);
   float* mu = a.mu + prob * a.mu_stride;
   float* cov = a.cov + prob * a.cov_stride;
   float* L = a.L + prob * a.L_stride;
   PRIEST_CEM_MARK(0);
 
+  bool best_ok = true;  // the best c_aug is not NaN
   if (!a.chol_only) {
+    const float* xb = a.xb + prob * a.xb_stride;
+    // everything the refit reads besides the elite rows, loaded in one batch
+    // so that the block waits on HBM once: r, c1, mu, Sigma (and the
+    // evolution path)
     const float* r = a.resid + prob * a.n_stride;
     const float* c1 = a.c1 + prob * a.n_stride;
-    const float* xb = a.xb + prob * a.xb_stride;
+    constexpr int kCovPer = (DM * DM + kCemThreads - 1) / kCemThreads;
+    float vr[IPT], vc[IPT], vcov[kCovPer];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const int i = tid + k * kCemThreads;
+      vr[k] = i < N ? r[i] : 0.0f;
+      vc[k] = (kPre && i < N) ? c1[i] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kCovPer; ++k) {
+      const int i = tid + k * kCemThreads;
+      vcov[k] = i < D * D ? cov[i] : 0.0f;
+    }
+    const float vmu = tid < D ? mu[tid] : 0.0f;
+    const float vpc = (a.rule == 1 && !a.first && tid < D) ? a.pc[prob * a.pc_stride + tid] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kCovPer; ++k) {
+      const int i = tid + k * kCemThreads;
+      if (i < D * D) cov0[i] = vcov[k];
+    }
+    if (tid < D) {
+      mu0[tid] = vmu;
+      pc0[tid] = vpc;
+    }
     // 1. lowest residuals
-    for (int i = tid; i < N; i += T) {
-      skey[i] = ordered_bits(r[i]);
-      sval[i] = i;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const int i = tid + k * kCemThreads;
+      if (i < N) {
+        if constexpr (kPre) {
+          s_r[i] = vr[k];
+          s_c1[i] = vc[k];
+        }
+        skey[i] = ordered_bits(vr[k]);
+        sval[i] = i;
+      }
+    }
+    if constexpr (kPre) {
+      r = s_r;
+      c1 = s_c1;
+    }
+    // the ordered constraint-elite set is produced only when asked for;
+    // otherwise both selections run as radix selects
+    const bool fast = kPre && !a.proj_idx && a.n_elite <= kFastElite;
+    if (fast) {
+      // (zero counters, ranks and a valid elite list before anyone counts)
+      for (int i = tid; i < fast_select_words<IPT>(); i += T) s_fast[i] = 0u;
+      for (int m = tid; m < a.n_elite; m += T) elite[m] = 0;
     }
     __syncthreads();
-    select_sorted<IPT>(skey, sval, N, a.n_proj, proj, &sort_tmp);
-    __syncthreads();
-    PRIEST_CEM_MARK(1);
-    for (int i = tid; i < a.n_proj; i += T)
-      if (a.proj_idx) a.proj_idx[prob * a.n_proj + i] = proj[i];
-    // 2. lowest c_aug within them; ties keep the order of step 1
-    for (int i = tid; i < a.n_proj; i += T) {
-      const int s = proj[i];
-      skey[i] = ordered_bits(c1[s] + r[s]);
-      sval[i] = i;
+    if (fast) {
+      if constexpr (kPre) select_fast<IPT>(vr, vc, N, a.n_proj, a.n_elite, s_r, s_fast, skey, elite);
+      __syncthreads();
+      PRIEST_CEM_MARK(1);
+    } else {
+      select_sorted<IPT>(skey, sval, N, a.n_proj, proj, &sort_tmp);
+      __syncthreads();
+      PRIEST_CEM_MARK(1);
+      for (int i = tid; i < a.n_proj; i += T)
+        if (a.proj_idx) a.proj_idx[prob * a.n_proj + i] = proj[i];
+      // 2. lowest c_aug within them; ties keep the order of step 1
+      for (int i = tid; i < a.n_proj; i += T) {
+        const int s = proj[i];
+        skey[i] = ordered_bits(c1[s] + r[s]);
+        sval[i] = i;
+      }
+      __syncthreads();
+      select_sorted<IPT>(skey, sval, a.n_proj, a.n_elite, elite, &sort_tmp);
+      __syncthreads();
+      for (int m = tid; m < a.n_elite; m += T) elite[m] = proj[elite[m]];
+      __syncthreads();
     }
-    __syncthreads();
-    select_sorted<IPT>(skey, sval, a.n_proj, a.n_elite, elite, &sort_tmp);
-    __syncthreads();
-    for (int m = tid; m < a.n_elite; m += T) {
-      elite[m] = proj[elite[m]];
-      if (a.elite_idx) a.elite_idx[prob * a.n_elite + m] = elite[m];
-    }
-    __syncthreads();
+    if (a.elite_idx)
+      for (int m = tid; m < a.n_elite; m += T) a.elite_idx[prob * a.n_elite + m] = elite[m];
     PRIEST_CEM_MARK(2);
     // 3. weights; fixed-order sum by the first wave
     const int e0 = elite[0];
@@ -220,10 +504,22 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     float* stage = reinterpret_cast<float*>(sm + l.stage);
     const int CH = kStageFloats / D;
     const bool one_chunk = a.n_elite <= CH;
+    // (eight loads per thread in flight before the first store)
     auto stage_rows = [&](int m0, int nm) {
-      for (int i = tid; i < nm * D; i += T) {
-        const int m = i / D;
-        stage[i] = xb[static_cast<int64_t>(elite[m0 + m]) * D + (i - m * D)];
+      constexpr int kG = 8;
+      for (int b = 0; b < nm * D; b += kG * kCemThreads) {
+        float v[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) {
+          const int i = b + u * kCemThreads + tid;
+          const int m = i / D;
+          v[u] = i < nm * D ? xb[static_cast<int64_t>(elite[m0 + m]) * D + (i - m * D)] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kG; ++u) {
+          const int i = b + u * kCemThreads + tid;
+          if (i < nm * D) stage[i] = v[u];
+        }
       }
     };
     // mean: coefficient d gets 4 partial sums (elites m = part mod 4), added
@@ -235,6 +531,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       stage_rows(m0, nm);
       __syncthreads();
       if (part < 4) {
+#pragma unroll 5
         for (int m = part; m < nm; m += 4) macc = fmaf(w[m0 + m], stage[m * D + md], macc);
       }
       if (!one_chunk) __syncthreads();
@@ -244,10 +541,9 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     if (tid < D) {
       const float sm4 = (A[tid] + A[D + tid]) + (A[2 * D + tid] + A[3 * D + tid]);
       const float mw = sm4 * inv_sw;
-      muN[tid] = (1.0f - a.sigma) * mu[tid] + a.sigma * mw;
+      muN[tid] = (1.0f - a.sigma) * mu0[tid] + a.sigma * mw;
       if (a.rule == 1) {
-        const float p0 = a.first ? 0.0f : a.pc[prob * a.pc_stride + tid];
-        pcN[tid] = fmaf(sqrtf(cc * (2.0f - cc) * mu_eff), mw - mu[tid], (1.0f - cc) * p0);
+        pcN[tid] = fmaf(sqrtf(cc * (2.0f - cc) * mu_eff), mw - mu0[tid], (1.0f - cc) * pc0[tid]);
       }
     }
     __syncthreads();
@@ -256,7 +552,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     // 1: about the current mean), on MFMA 16x16x4: wave v computes
     // lower-triangle tile v of the ceil(D/16)^2 tiles, elites four at a time
     // (two accumulation chains, added at the end)
-    const float* cen = (a.rule == 1) ? mu : muN;
+    const float* cen = (a.rule == 1) ? mu0 : muN;
     const int wv = tid >> 6, lane = tid & 63;
     const int nt = (D + 15) / 16;
     int ti = 0, tj = 0;
@@ -278,15 +574,31 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       }
       if (owner) {
         const int ii = ti * 16 + (lane & 15), jj = tj * 16 + (lane & 15);
-        const float mi = ii < D ? cen[ii] : 0.0f, mj = jj < D ? cen[jj] : 0.0f;
-        for (int s4 = 0; s4 < nm; s4 += 8) {
-          const int ma = s4 + (lane >> 4), mb = ma + 4;
-          const float av0 = (ma < nm && ii < D) ? w[m0 + ma] * (stage[ma * D + ii] - mi) : 0.0f;
-          const float bv0 = (ma < nm && jj < D) ? stage[ma * D + jj] - mj : 0.0f;
-          const float av1 = (mb < nm && ii < D) ? w[m0 + mb] * (stage[mb * D + ii] - mi) : 0.0f;
-          const float bv1 = (mb < nm && jj < D) ? stage[mb * D + jj] - mj : 0.0f;
-          acc0 = mfma(av0, bv0, acc0);
-          acc1 = mfma(av1, bv1, acc1);
+        const bool iok = ii < D, jok = jj < D;
+        const int ic = iok ? ii : 0, jc = jok ? jj : 0;
+        const float mi = cen[ic], mj = cen[jc];
+        // four groups of eight elites per step: every load of a step is
+        // issued before its products (positions past the chunk load a
+        // clamped, in-range row and contribute zero operands)
+        constexpr int kU = 4;
+        for (int s0 = 0; s0 < nm; s0 += 8 * kU) {
+          float av[kU][2], bv[kU][2];
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int m = s0 + 8 * u + 4 * h + (lane >> 4);
+              const bool ok = m < nm;
+              const int mc = ok ? m : 0;
+              const float wm = w[m0 + mc], xi_ = stage[mc * D + ic], xj_ = stage[mc * D + jc];
+              av[u][h] = (ok && iok) ? wm * (xi_ - mi) : 0.0f;
+              bv[u][h] = (ok && jok) ? xj_ - mj : 0.0f;
+            }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            acc0 = mfma(av[u][0], bv[u][0], acc0);
+            acc1 = mfma(av[u][1], bv[u][1], acc1);
+          }
         }
       }
       if (!one_chunk) __syncthreads();
@@ -300,24 +612,30 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
           float v;
           if (a.rule == 1)
             v = fmaf(cmu, acc[r] * inv_sw,
-                     fmaf(c1r, pcN[i] * pcN[j], (1.0f - c1r - cmu) * cov[i * D + j]));
+                     fmaf(c1r, pcN[i] * pcN[j], (1.0f - c1r - cmu) * cov0[i * D + j]));
           else
-            v = (1.0f - a.sigma) * cov[i * D + j] + a.sigma * (acc[r] * inv_sw);
+            v = (1.0f - a.sigma) * cov0[i * D + j] + a.sigma * (acc[r] * inv_sw);
           A[i * D + j] = v;
           A[j * D + i] = v;
         }
       }
     }
     __syncthreads();
-    for (int e = tid; e < D * D; e += T) cov[e] = A[e];
-    for (int d = tid; d < D; d += T) {
-      mu[d] = muN[d];
-      if (a.rule == 1) a.pc[prob * a.pc_stride + d] = pcN[d];
-      a.best_xi[prob * a.best_stride + d] = xb[static_cast<int64_t>(e0) * D + d];
-    }
-    if (tid == 0) a.best_cost[prob] = delta;
-    __syncthreads();
     PRIEST_CEM_MARK(5);
+    // the outputs other than L, written by the other waves while the first
+    // one factors
+    if (tid >= 64) {
+      const int t2 = tid - 64, T2 = T - 64;
+      for (int e = t2; e < D * D; e += T2) cov[e] = A[e];
+      for (int d = t2; d < D; d += T2) {
+        mu[d] = muN[d];
+        if (a.rule == 1) a.pc[prob * a.pc_stride + d] = pcN[d];
+        // (elite 0's row is still staged when all elites fit one chunk)
+        a.best_xi[prob * a.best_stride + d] = one_chunk ? stage[d] : xb[static_cast<int64_t>(e0) * D + d];
+      }
+      if (t2 == 0) a.best_cost[prob] = delta;
+    }
+    best_ok = delta == delta;
   } else {
     for (int e = tid; e < D * D; e += T) A[e] = cov[e];
     __syncthreads();
@@ -328,20 +646,10 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     for (int d = tid; d < D; d += 64) tr += A[d * D + d];
     tr = wave_sum(tr);
     const float eps = a.cov_jitter * tr / static_cast<float>(D);
-    for (int d = tid; d < D; d += 64) A[d * D + d] += eps;
-    const bool ok = cholesky_wave<DM>(A, D, tid, red);
-    if (tid == 0 && a.status) {
-      bool fin = ok;
-      if (!a.chol_only) fin = fin && (a.best_cost[prob] == a.best_cost[prob]);
-      if (!fin) a.status[prob] = PRIEST_ERR_NONFINITE;
-    }
+    const bool ok = cholesky_wave<DM>(A, eps, D, tid, L);
+    if (tid == 0 && a.status && !(ok && best_ok)) a.status[prob] = PRIEST_ERR_NONFINITE;
   }
-  __syncthreads();
   PRIEST_CEM_MARK(6);
-  for (int e = tid; e < D * D; e += T) {
-    const int i = e / D, j = e - i * D;
-    L[e] = (j <= i) ? A[e] : 0.0f;
-  }
   PRIEST_CEM_MARK(7);
 }
 

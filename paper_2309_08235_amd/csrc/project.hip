@@ -1043,7 +1043,7 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
           G[rt] = G0 + G1 + G2;
         }
         // issue the LDS reads before the MFMAs that consume them
-        __builtin_amdgcn_sched_group_barrier(0x100, 6 * RT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 12 * RT, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 12 * RT, 0);
   #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
