@@ -356,6 +356,19 @@ int32_t priest_debug_offsets(priest_problem* p, const float* bc, const float* ob
 int32_t priest_debug_normals(uint64_t seed, uint32_t stream_id, int32_t iter, int32_t N,
                              int32_t D, float* z, void* stream);
 
+/* Debug/parity hook for the two selections of Alg. 1 (ConstraintEliteSet,
+ * then EliteSet), as the refit kernel makes them: from r [N] and c1 [N]
+ * (device), writes elite_idx [n_elite] (device), the n_elite lowest
+ * c_aug = c1 + r (FP32 sum) among the n_proj lowest r, ascending c_aug with
+ * ties in the order of the first selection (ascending r, then index).  With
+ * proj_idx non-NULL it also writes that first selection [n_proj] (device),
+ * ascending r, and takes the sorting path; with NULL it takes the path the
+ * plan takes in its other iterations (radix selects where N <= 2048 and
+ * n_elite <= 512).  Requires 1 <= n_elite <= n_proj <= N <= 8192.
+ * Allocates and frees scratch; synchronises `stream`. */
+int32_t priest_debug_select(int32_t N, int32_t n_proj, int32_t n_elite, const float* r,
+                            const float* c1, int32_t* elite_idx, int32_t* proj_idx, void* stream);
+
 /* Copies the problem's FP32 constants to host memory for inspection:
  * which = 0: KKT block M11 [n_coeff][n_coeff]; 1: Pi = M11 Q [n_coeff][n_coeff];
  * 2: M12 [n_coeff][6] (column i multiplies boundary value i of an axis);

@@ -1048,6 +1048,46 @@ int32_t priest_debug_normals(uint64_t seed, uint32_t stream_id, int32_t iter, in
   return PRIEST_OK;
 }
 
+int32_t priest_debug_select(int32_t N, int32_t n_proj, int32_t n_elite, const float* r,
+                            const float* c1, int32_t* elite_idx, int32_t* proj_idx, void* stream) {
+  if (!r || !c1 || !elite_idx || n_elite < 1 || n_proj < n_elite || N < n_proj ||
+      N > kCemThreads * 16)
+    return fail(PRIEST_ERR_INVALID, "need r, c1, elite_idx and 1 <= n_elite <= n_proj <= N <= %d",
+                kCemThreads * 16);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // a one-coefficient problem around the selection: zero rows, mu = 0, Sigma = 1
+  float* buf = nullptr;
+  const size_t nf = static_cast<size_t>(N) + 8;
+  HIP_TRY(hipMalloc(&buf, nf * sizeof(float)));
+  std::vector<float> h(nf, 0.0f);
+  h[N + 1] = 1.0f;  // cov
+  hipError_t e = hipMemcpyAsync(buf, h.data(), nf * sizeof(float), hipMemcpyHostToDevice, s);
+  CemArgs ca{};
+  ca.D = 1;
+  ca.N = N;
+  ca.n_proj = n_proj;
+  ca.n_elite = n_elite;
+  ca.sigma = 0.5f;
+  ca.gamma = 1.0f;
+  ca.cov_jitter = 0.0f;
+  ca.xb = buf;
+  ca.resid = r;
+  ca.c1 = c1;
+  ca.mu = buf + N;
+  ca.cov = buf + N + 1;
+  ca.L = buf + N + 2;
+  ca.best_xi = buf + N + 3;
+  ca.best_cost = buf + N + 4;
+  ca.elite_idx = elite_idx;
+  ca.proj_idx = proj_idx;
+  if (e == hipSuccess) e = launch_cem(ca, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t ef = hipFree(buf);
+  HIP_TRY(e);
+  HIP_TRY(ef);
+  return PRIEST_OK;
+}
+
 int32_t priest_debug_constants(const priest_problem* p, int32_t which, float* host_out,
                                int32_t count) {
   if (!p || !host_out) return fail(PRIEST_ERR_INVALID, "problem and host_out are required");

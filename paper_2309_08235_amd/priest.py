@@ -42,6 +42,7 @@ EXPORTS = (
     "priest_profile_enable", "priest_profile_read", "priest_project_unfused_workspace_size",
     "priest_project_unfused", "priest_plan_dpriest", "priest_profile_count_pairs",
     "priest_profile_read_pairs", "priest_project_hist", "priest_project_batch",
+    "priest_debug_select",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -175,6 +176,7 @@ _SIGS = {
                                  ctypes.c_size_t, _P]),
     "priest_debug_offsets": (_I, [_P, _P, _P, _P, _I, _P, _P]),
     "priest_debug_normals": (_I, [ctypes.c_uint64, ctypes.c_uint32, _I, _I, _I, _P, _P]),
+    "priest_debug_select": (_I, [_I, _I, _I, _P, _P, _P, _P, _P]),
     "priest_debug_constants": (_I, [_P, _I, _P, _I]),
     "priest_server_now": (ctypes.c_double, []),
     "priest_server_create": (_I, [ctypes.POINTER(ServerConfig), _P, ctypes.POINTER(_P)]),
@@ -330,6 +332,14 @@ def priest_debug_offsets(handle, bc, obs, xi, offsets, stream=None):
 def priest_debug_normals(seed, stream_id, it, z, stream=None):
     _check(lib().priest_debug_normals(seed, stream_id, it, z.shape[0], z.shape[1], _ptr(z),
                                       _stream(stream)))
+
+
+def priest_debug_select(n_proj, n_elite, r, c1, elite_idx, proj_idx=None, stream=None):
+    """The refit kernel's two selections on r, c1 [N] (device, FP32): fills
+    elite_idx [n_elite] and, if given, proj_idx [n_proj] (device, int32)."""
+    _check(lib().priest_debug_select(r.shape[0], n_proj, n_elite, _ptr(r), _ptr(c1),
+                                     _ptr(elite_idx, torch.int32), _ptr(proj_idx, torch.int32),
+                                     _stream(stream)))
 
 
 def priest_debug_constants(handle, which: int, count: int):
