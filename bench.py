@@ -466,9 +466,12 @@ def main():
     bc_h, obs_h = W.scene(wl, 0)
     bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
     obs = torch.tensor(obs_h, dtype=torch.float32, device=dev)
-    mu0 = torch.tensor(W.initial_mean(wl), dtype=torch.float32, device=dev)
-    cov0 = torch.tensor(W.initial_cov(wl), dtype=torch.float32, device=dev)
-    mu, cov = mu0.clone(), cov0.clone()
+    # (mu, Sigma) in one buffer, so that resetting them before a plan is one copy
+    D = prob.D
+    state0 = torch.cat([torch.tensor(W.initial_mean(wl), dtype=torch.float32).reshape(-1),
+                        torch.tensor(W.initial_cov(wl), dtype=torch.float32).reshape(-1)]).to(dev)
+    state = state0.clone()
+    mu, cov = state[:D], state[D:].view(D, D)
     cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
                 n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
                 cov_jitter=wl.cov_jitter)
@@ -479,8 +482,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(i):
-        mu.copy_(mu0)
-        cov.copy_(cov0)
+        state.copy_(state0)
         prob.plan(bc, obs, cem, mu, cov, seed=1234 + i, stream_id=0, out=out, workspace=ws)
 
     for i in range(args.warmup):       # the first plan also runs the autotuner

@@ -39,11 +39,6 @@ int32_t fail(int32_t code, const char* fmt, ...) {
       return fail(PRIEST_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-__global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 double binom(int n, int k) {
   double r = 1.0;
   for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
@@ -370,12 +365,7 @@ int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const f
   ProjArgs a = pa.a;
   CemArgs ca = pa.ca;
   const int D = ca.D, N = ca.N;
-  if (out->status) {
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((P + 255) / 256), dim3(256), 0, s, out->status, P,
-                       PRIEST_OK);
-    HIP_TRY(hipGetLastError());
-  }
-  ca.chol_only = 1;
+  ca.chol_only = 1;  // (also sets every status word to PRIEST_OK)
   HIP_TRY(launch_cem(ca, P, s));
   ca.chol_only = 0;
   for (int l = 0; l < c->n_cem; ++l) {

@@ -384,6 +384,8 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   PRIEST_CEM_MARK(0);
 
   bool best_ok = true;  // the best c_aug is not NaN
+  // (the factorisation that starts a plan also starts its status word)
+  if (a.chol_only && a.status && tid == 0) a.status[prob] = PRIEST_OK;
   if (!a.chol_only) {
     const float* xb = a.xb + prob * a.xb_stride;
     // everything the refit reads besides the elite rows, loaded in one batch
