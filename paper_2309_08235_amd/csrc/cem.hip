@@ -24,6 +24,9 @@
 #ifndef PRIEST_CEM_MARK
 #define PRIEST_CEM_MARK(i)
 #endif
+#ifndef PRIEST_CEM_SUB
+#define PRIEST_CEM_SUB(i)
+#endif
 
 namespace priest {
 namespace {
@@ -81,11 +84,18 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 // is not positive and finite (it is replaced by 1).
 template <int DM>
 __device__ __forceinline__ bool cholesky_wave(const float* A, float eps, int D, int lane, float* L) {
+  // (every lane loads a clamped, in-range entry and scales it by zero where
+  // it pads: with a select the compiler puts each load under its own branch,
+  // one LDS round trip after another)
   float row[DM];
+  const int lr = lane < D ? lane : D - 1;
+  const float inrow = lane < D ? 1.0f : 0.0f;
 #pragma unroll
-  for (int c = 0; c < DM; ++c)
-    row[c] = (lane < D && c < D) ? A[lane * D + c] + (lane == c ? eps : 0.0f)
-                                 : (lane == c ? 1.0f : 0.0f);
+  for (int c = 0; c < DM; ++c) {
+    const float v = A[lr * D + (c < D ? c : D - 1)];
+    const float m = (c < D) ? inrow : 0.0f;
+    row[c] = v * m + (lane == c ? (m != 0.0f ? eps : 1.0f) : 0.0f);
+  }
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < DM; ++j) {
@@ -580,9 +590,12 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
         const int ic = iok ? ii : 0, jc = jok ? jj : 0;
         const float mi = cen[ic], mj = cen[jc];
         // four groups of eight elites per step: every load of a step is
-        // issued before its products (positions past the chunk load a
-        // clamped, in-range row and contribute zero operands)
+        // issued before its products.  Positions past the chunk load a
+        // clamped, in-range (finite) row and are scaled by zero: a select
+        // here lets the compiler move each load under its own branch, one
+        // LDS round trip after another.
         constexpr int kU = 4;
+        PRIEST_CEM_SUB(0);
         for (int s0 = 0; s0 < nm; s0 += 8 * kU) {
           float av[kU][2], bv[kU][2];
 #pragma unroll
@@ -593,8 +606,8 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
               const bool ok = m < nm;
               const int mc = ok ? m : 0;
               const float wm = w[m0 + mc], xi_ = stage[mc * D + ic], xj_ = stage[mc * D + jc];
-              av[u][h] = (ok && iok) ? wm * (xi_ - mi) : 0.0f;
-              bv[u][h] = (ok && jok) ? xj_ - mj : 0.0f;
+              av[u][h] = (wm * (xi_ - mi)) * ((ok && iok) ? 1.0f : 0.0f);
+              bv[u][h] = (xj_ - mj) * ((ok && jok) ? 1.0f : 0.0f);
             }
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
@@ -605,6 +618,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       }
       if (!one_chunk) __syncthreads();
     }
+    PRIEST_CEM_SUB(1);
     if (owner) {
       const f4 acc = acc0 + acc1;
 #pragma unroll
@@ -622,6 +636,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
         }
       }
     }
+    PRIEST_CEM_SUB(2);
     __syncthreads();
     PRIEST_CEM_MARK(5);
     // the outputs other than L, written by the other waves while the first
