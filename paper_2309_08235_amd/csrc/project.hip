@@ -531,8 +531,17 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
                                                 const int* tstep = nullptr, int K = 0) {
   // records of the first group, issued before anything waits on LDS
   const float4 zr = make_float4(0, 0, 0, 0);
-  const float4 G0 = lane < M ? rec[lane] : zr, G1 = lane < M ? rec[M + lane] : zr,
-               G2 = lane < M ? rec[2 * M + lane] : zr;
+  // (lanes past the scene load the last record: only lanes of obstacles are
+  // ever read, and unconditional loads keep the compiler from putting each one
+  // under a branch of its own)
+  auto clampj = [M](int j) { return j < M ? j : M - 1; };
+  float4 G0 = zr, G1 = zr, G2 = zr;
+  if (M > 0) {
+    const int l0 = clampj(lane);
+    G0 = rec[l0];
+    G1 = rec[M + l0];
+    G2 = rec[2 * M + l0];
+  }
   // reuse the candidate sets if every item is still within the slack
   bool reuse = false;
   if (cc.valid) {
@@ -599,15 +608,15 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       cc.mv[g] = 0ull;
       if (64 * g < M) {
         const int j = 64 * g + lane;
-        const float4 R0 = g == 0 ? G0 : (j < M ? rec[j] : zr);
-        const float4 R1 = g == 0 ? G1 : (j < M ? rec[M + j] : zr);
+        const float4 R0 = g == 0 ? G0 : rec[clampj(j)];
+        const float4 R1 = g == 0 ? G1 : rec[M + clampj(j)];
         cull_group(g, R0, R1, cc.cm[g], cc.mv[g]);
       }
     }
     for (int g = kRegGroups; 64 * g < M; ++g) {
       const int j = 64 * g + lane;
       unsigned long long mask, moving;
-      cull_group(g, j < M ? rec[j] : zr, j < M ? rec[M + j] : zr, mask, moving);
+      cull_group(g, rec[clampj(j)], rec[M + clampj(j)], mask, moving);
       if (lane == 0) {
         wm[4 * g + 0] = static_cast<uint32_t>(mask);
         wm[4 * g + 1] = static_cast<uint32_t>(mask >> 32);
@@ -691,8 +700,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       group(0, cmask, cc.mv[0], G0, G1, G2);
     } else {
       const int j = 64 * g + lane;
-      group(64 * g, cmask, cc.mv[g], j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
-            j < M ? rec[2 * M + j] : zr);
+      group(64 * g, cmask, cc.mv[g], rec[clampj(j)], rec[M + clampj(j)], rec[2 * M + clampj(j)]);
     }
   }
   for (int g = kRegGroups; 64 * g < M; ++g) {
@@ -707,8 +715,8 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
     if (!cmask) continue;
     const int j = 64 * g + lane;
-    group(64 * g, cmask, u64(m4.z, m4.w), j < M ? rec[j] : zr, j < M ? rec[M + j] : zr,
-          j < M ? rec[2 * M + j] : zr);
+    group(64 * g, cmask, u64(m4.z, m4.w), rec[clampj(j)], rec[M + clampj(j)],
+          rec[2 * M + clampj(j)]);
   }
   cc.pairs += ncand * cc.nok;
   PRIEST_PROJ_MARK(8);
