@@ -275,6 +275,7 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     k1[j] = valid[j] ? ordered_bits(vr[j]) : ~0u;
   }
   // step 1: the n_proj lowest (r key, index)
+  PRIEST_CEM_SUB(3);
   uint32_t v1, m1, less1, eq1;
   radix_select<IPT>(k1, valid, static_cast<uint32_t>(n_proj - 1), hist, bc, v1, m1, less1, eq1);
   const uint32_t t1 = static_cast<uint32_t>(n_proj) - less1;  // members among the keys equal to v1
@@ -293,6 +294,7 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     for (int j = 0; j < IPT; ++j) mem[j] = valid[j] && (k1[j] < v1 || (tie[j] && pre[j] < t1));
   }
   // step 2: the n_elite lowest (c_aug key, r key, index) among them
+  PRIEST_CEM_SUB(4);
   uint32_t k2[IPT];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) k2[j] = mem[j] ? ordered_bits(vc[j] + vr[j]) : ~0u;
@@ -318,14 +320,15 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
         const int i = tid + j * kCemThreads;
         uint32_t rank = 0;
         for (int x = 0; x < N; ++x) {
-          if (gk2[x] != v2) continue;
           const uint32_t kx = ordered_bits(s_r[x]);
-          rank += (kx < k1[j]) || (kx == k1[j] && x < i);
+          rank += static_cast<uint32_t>(gk2[x] == v2) &
+                  (static_cast<uint32_t>(kx < k1[j]) | (static_cast<uint32_t>(kx == k1[j]) & static_cast<uint32_t>(x < i)));
         }
         sel[j] = rank < t2;
       }
     }
   }
+  PRIEST_CEM_SUB(5);
   // the n_elite survivors, in slots of arbitrary order ...
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
@@ -339,18 +342,22 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     }
   }
   __syncthreads();
+  PRIEST_CEM_SUB(6);
   // ... ranked by counting: Q threads per survivor, each over a share of the
   // others
+  // (all three fields read and compared without short-circuits: a lazy read
+  // of the tie fields becomes a branch and an LDS round trip per comparison)
   const int Q = kCemThreads / n_elite;
   const int am = tid % n_elite, q = tid / n_elite;
   if (q < Q) {
-    const uint32_t ak2 = lk2[am], ak1 = lk1[am];
+    const unsigned long long ak = (static_cast<unsigned long long>(lk2[am]) << 32) | lk1[am];
     const int ai = li[am];
     uint32_t rk = 0;
 #pragma unroll 4
     for (int b = q * n_elite / Q; b < (q + 1) * n_elite / Q; ++b) {
-      const uint32_t bk2 = lk2[b], bk1 = lk1[b];
-      rk += (bk2 < ak2) || (bk2 == ak2 && (bk1 < ak1 || (bk1 == ak1 && li[b] < ai)));
+      const unsigned long long bk = (static_cast<unsigned long long>(lk2[b]) << 32) | lk1[b];
+      const int bi = li[b];
+      rk += static_cast<uint32_t>(bk < ak) | (static_cast<uint32_t>(bk == ak) & static_cast<uint32_t>(bi < ai));
     }
     atomicAdd(lrank + am, rk);
   }
@@ -359,6 +366,7 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     const uint32_t rk = lrank[m];
     if (rk < static_cast<uint32_t>(n_elite)) elite[rk] = li[m];
   }
+  PRIEST_CEM_SUB(7);
 }
 
 // One block's work: selection, refit and factorisation for problem `prob`
