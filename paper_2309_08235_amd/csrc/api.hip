@@ -245,8 +245,9 @@ Profiler& profiler() {
   return *p;
 }
 
-// launch_project, bracketed by events when profiling is on and the stream is
-// not being captured.
+// launch_project, timed by events when profiling is on and the stream is not
+// being captured: the launch itself stamps the kernel's start and end into
+// them, so profiling adds no commands to the stream between kernels.
 hipError_t launch_project_timed(const ProjArgs& a, int P, hipStream_t s) {
   Profiler& pr = profiler();
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -265,13 +266,8 @@ hipError_t launch_project_timed(const ProjArgs& a, int P, hipStream_t s) {
       }
     }
   }
+  const hipError_t e = launch_project(b, P, s, ev.first, ev.second);
   if (ev.first) {
-    const hipError_t e = hipEventRecord(ev.first, s);
-    if (e != hipSuccess) return e;
-  }
-  hipError_t e = launch_project(b, P, s);
-  if (ev.first) {
-    if (e == hipSuccess) e = hipEventRecord(ev.second, s);
     std::lock_guard<std::mutex> lk(pr.mu);
     pr.pending.push_back(ev);
   }

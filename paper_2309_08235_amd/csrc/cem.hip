@@ -384,7 +384,8 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   __shared__ uint32_t s_fast[kPre ? fast_select_words<IPT>() : 1];
   extern __shared__ float4 sm4[];
   char* sm = reinterpret_cast<char*>(sm4);
-  const int D = a.D, N = a.N, tid = threadIdx.x, T = blockDim.x;
+  const int D = a.D, N = a.N, tid = threadIdx.x;
+  constexpr int T = kCemThreads;  // (every launch of the refit uses this block size)
   const CemLayout l = cem_layout(D, a.n_proj, a.n_elite);
   int* proj = reinterpret_cast<int*>(sm + l.proj);
   int* elite = reinterpret_cast<int*>(sm + l.elite);

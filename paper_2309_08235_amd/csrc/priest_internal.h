@@ -121,7 +121,10 @@ bool tiling_valid(int dims, int axis_slots, int row_tiles);
 int samples_per_block(int axis_slots);
 int project_threads(int K, int row_tiles);
 void set_default_tiling(ProjArgs& a);  // 4 axis slots, 1 time block per wave, not persistent
-hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s);
+// start / stop: optional events that receive the kernel's own start and end
+// times (hipExtLaunchKernel), for profiling without marker commands.
+hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s,
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 size_t cem_lds_bytes(int N, int D, int n_elite);
 hipError_t launch_cem(const CemArgs& a, int n_problems, hipStream_t s);
 hipError_t launch_pick_best(int G, int D, const float* xi, const float* cost, float* best_xi,

@@ -40,6 +40,8 @@
 // results and the autotuner may pick any of them.
 #include "priest_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <mutex>
 #include <type_traits>
 
@@ -1340,50 +1342,64 @@ int resident_blocks(const void* fn, int threads, size_t lds) {
   return v;
 }
 
+// Launch events: when set, the runtime stamps the kernel's own start and end
+// into them (no marker commands of their own on the stream).
+struct KEvents {
+  hipEvent_t start, stop;
+};
+
+template <typename F, typename... A>
+void launch_k(F kernel, dim3 g, dim3 b, size_t lds, hipStream_t s, KEvents ev, A... args) {
+  hipExtLaunchKernelGGL(kernel, g, b, static_cast<std::uint32_t>(lds), s, ev.start, ev.stop, 0u,
+                        args...);
+}
+
 template <int DIMS, int AS, int RT, int MAXT, bool BF16>
-hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s) {
+hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s,
+                        KEvents ev) {
   if (a.persistent) {
     const void* fn = reinterpret_cast<const void*>(&project_kernel<DIMS, AS, RT, MAXT, BF16, true>);
     const int grid = std::min(total, resident_blocks(fn, threads, lds));
-    hipLaunchKernelGGL((project_kernel<DIMS, AS, RT, MAXT, BF16, true>), dim3(grid), dim3(threads),
-                       lds, s, a, total);
+    launch_k(project_kernel<DIMS, AS, RT, MAXT, BF16, true>, dim3(grid), dim3(threads), lds, s, ev,
+             a, total);
   } else {
-    hipLaunchKernelGGL((project_kernel<DIMS, AS, RT, MAXT, BF16, false>), dim3(total),
-                       dim3(threads), lds, s, a, total);
+    launch_k(project_kernel<DIMS, AS, RT, MAXT, BF16, false>, dim3(total), dim3(threads), lds, s,
+             ev, a, total);
   }
   return hipGetLastError();
 }
 
 template <int DIMS, bool BF16>
-hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s) {
+hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s,
+                       KEvents ev) {
   if (a.resid_hist || a.traj) {  // default shape only (checked by the caller)
     const dim3 g(total), b(threads);
     if (threads <= 512) {
-      if (a.resid_hist && a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 512, BF16, true, true>), g, b, lds, s, a, total);
-      else if (a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 512, BF16, false, true>), g, b, lds, s, a, total);
-      else hipLaunchKernelGGL((project_special_kernel<DIMS, 512, BF16, true, false>), g, b, lds, s, a, total);
+      if (a.resid_hist && a.traj) launch_k(project_special_kernel<DIMS, 512, BF16, true, true>, g, b, lds, s, ev, a, total);
+      else if (a.traj) launch_k(project_special_kernel<DIMS, 512, BF16, false, true>, g, b, lds, s, ev, a, total);
+      else launch_k(project_special_kernel<DIMS, 512, BF16, true, false>, g, b, lds, s, ev, a, total);
     } else {
-      if (a.resid_hist && a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 1024, BF16, true, true>), g, b, lds, s, a, total);
-      else if (a.traj) hipLaunchKernelGGL((project_special_kernel<DIMS, 1024, BF16, false, true>), g, b, lds, s, a, total);
-      else hipLaunchKernelGGL((project_special_kernel<DIMS, 1024, BF16, true, false>), g, b, lds, s, a, total);
+      if (a.resid_hist && a.traj) launch_k(project_special_kernel<DIMS, 1024, BF16, true, true>, g, b, lds, s, ev, a, total);
+      else if (a.traj) launch_k(project_special_kernel<DIMS, 1024, BF16, false, true>, g, b, lds, s, ev, a, total);
+      else launch_k(project_special_kernel<DIMS, 1024, BF16, true, false>, g, b, lds, s, ev, a, total);
     }
     return hipGetLastError();
   }
   if (a.row_tiles == 2) {
     if constexpr (DIMS == 2)
-      if (a.axis_slots == 2) return launch_shape<DIMS, 2, 2, 512, BF16>(a, total, threads, lds, s);
-    return launch_shape<DIMS, 4, 2, 512, BF16>(a, total, threads, lds, s);
+      if (a.axis_slots == 2) return launch_shape<DIMS, 2, 2, 512, BF16>(a, total, threads, lds, s, ev);
+    return launch_shape<DIMS, 4, 2, 512, BF16>(a, total, threads, lds, s, ev);
   }
   if (threads <= 512) {
     if constexpr (DIMS == 2)
-      if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 512, BF16>(a, total, threads, lds, s);
-    if (a.axis_slots == 8) return launch_shape<DIMS, 8, 1, 512, BF16>(a, total, threads, lds, s);
-    return launch_shape<DIMS, 4, 1, 512, BF16>(a, total, threads, lds, s);
+      if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 512, BF16>(a, total, threads, lds, s, ev);
+    if (a.axis_slots == 8) return launch_shape<DIMS, 8, 1, 512, BF16>(a, total, threads, lds, s, ev);
+    return launch_shape<DIMS, 4, 1, 512, BF16>(a, total, threads, lds, s, ev);
   }
   if constexpr (DIMS == 2)
-    if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 1024, BF16>(a, total, threads, lds, s);
-  if (a.axis_slots == 8) return launch_shape<DIMS, 8, 1, 1024, BF16>(a, total, threads, lds, s);
-  return launch_shape<DIMS, 4, 1, 1024, BF16>(a, total, threads, lds, s);
+    if (a.axis_slots == 2) return launch_shape<DIMS, 2, 1, 1024, BF16>(a, total, threads, lds, s, ev);
+  if (a.axis_slots == 8) return launch_shape<DIMS, 8, 1, 1024, BF16>(a, total, threads, lds, s, ev);
+  return launch_shape<DIMS, 4, 1, 1024, BF16>(a, total, threads, lds, s, ev);
 }
 
 }  // namespace
@@ -1411,7 +1427,8 @@ void set_default_tiling(ProjArgs& a) {
   a.S = samples_per_block(a.axis_slots);
 }
 
-hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
+hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s, hipEvent_t start,
+                          hipEvent_t stop) {
   if (!tiling_valid(a.dims, a.axis_slots, a.row_tiles) || a.S != samples_per_block(a.axis_slots) ||
       a.blocks_per_problem != (a.N + a.S - 1) / a.S)
     return hipErrorInvalidValue;
@@ -1423,10 +1440,11 @@ hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s) {
   const int total = n_problems * a.blocks_per_problem;
   if (total <= 0) return hipSuccess;
   const bool bf = a.bf16_iters > 0;
-  if (a.dims == 2) return bf ? launch_dims<2, true>(a, total, threads, lds, s)
-                             : launch_dims<2, false>(a, total, threads, lds, s);
-  return bf ? launch_dims<3, true>(a, total, threads, lds, s)
-            : launch_dims<3, false>(a, total, threads, lds, s);
+  const KEvents ev{start, stop};
+  if (a.dims == 2) return bf ? launch_dims<2, true>(a, total, threads, lds, s, ev)
+                             : launch_dims<2, false>(a, total, threads, lds, s, ev);
+  return bf ? launch_dims<3, true>(a, total, threads, lds, s, ev)
+            : launch_dims<3, false>(a, total, threads, lds, s, ev);
 }
 
 hipError_t launch_project_tasks(const ProjTaskLaunch& t, hipStream_t s) {
