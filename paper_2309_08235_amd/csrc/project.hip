@@ -868,17 +868,21 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      // two independent chains per row type (k-chunks 0, 1 and 2[, 3]), summed
-      f4 T0 = mfma(Af[rt][0][2], xb[2], z), T1 = mfma(Af[rt][1][2], xb[2], z),
-         T2 = mfma(Af[rt][2][2], xb[2], z);
-      if (chunk3) {
-        T0 = mfma(Af[rt][0][3], xb[3], T0);
-        T1 = mfma(Af[rt][1][3], xb[3], T1);
-        T2 = mfma(Af[rt][2][3], xb[3], T2);
+      // one accumulation chain per row type over k-chunks 0, 1, 2[, 3]; the
+      // three chains interleave, so each product waits on nothing
+      f4 Y0 = mfma(Af[rt][0][0], xb[0], z), Y1 = mfma(Af[rt][1][0], xb[0], z),
+         Y2 = mfma(Af[rt][2][0], xb[0], z);
+#pragma unroll
+      for (int c = 1; c < 3; ++c) {
+        Y0 = mfma(Af[rt][0][c], xb[c], Y0);
+        Y1 = mfma(Af[rt][1][c], xb[c], Y1);
+        Y2 = mfma(Af[rt][2][c], xb[c], Y2);
       }
-      const f4 Y0 = mfma(Af[rt][0][1], xb[1], mfma(Af[rt][0][0], xb[0], z)) + T0;
-      const f4 Y1 = mfma(Af[rt][1][1], xb[1], mfma(Af[rt][1][0], xb[0], z)) + T1;
-      const f4 Y2 = mfma(Af[rt][2][1], xb[1], mfma(Af[rt][2][0], xb[0], z)) + T2;
+      if (chunk3) {
+        Y0 = mfma(Af[rt][0][3], xb[3], Y0);
+        Y1 = mfma(Af[rt][1][3], xb[3], Y1);
+        Y2 = mfma(Af[rt][2][3], xb[3], Y2);
+      }
       float* x0 = xt + rt * kXtBlock + xt_at(lane);
       *reinterpret_cast<f4*>(x0) = Y0;
       *reinterpret_cast<f4*>(x0 + kXtRow) = Y1;
