@@ -1039,22 +1039,23 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
         // MFMA per row type covers a whole 16-step block
   #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          const f4 g = mfma_bf16(Abf[rt][0], pack_bf16(B[rt][0][0], B[rt][0][1], B[rt][0][2], B[rt][0][3]), zb) +
-                       mfma_bf16(Abf[rt][1], pack_bf16(B[rt][1][0], B[rt][1][1], B[rt][1][2], B[rt][1][3]), zb) +
-                       mfma_bf16(Abf[rt][2], pack_bf16(B[rt][2][0], B[rt][2][1], B[rt][2][2], B[rt][2][3]), zb);
+          f4 g = zb;
+  #pragma unroll
+          for (int d = 0; d < 3; ++d)
+            g = mfma_bf16(Abf[rt][d], pack_bf16(B[rt][d][0], B[rt][d][1], B[rt][d][2], B[rt][d][3]), g);
           *reinterpret_cast<f4*>(gp + (w * RT + rt) * 256 + lane * 4) = g;
         }
       } else {
         f4 G[RT];
   #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          f4 G0 = mfma(Ab[rt][0][1], B[rt][0][1], mfma(Ab[rt][0][0], B[rt][0][0], zb));
-          f4 G1 = mfma(Ab[rt][0][3], B[rt][0][3], mfma(Ab[rt][0][2], B[rt][0][2], zb));
-          f4 G2 = mfma(Ab[rt][1][1], B[rt][1][1], mfma(Ab[rt][1][0], B[rt][1][0], zb));
-          G0 = mfma(Ab[rt][1][3], B[rt][1][3], mfma(Ab[rt][1][2], B[rt][1][2], G0));
-          G1 = mfma(Ab[rt][2][1], B[rt][2][1], mfma(Ab[rt][2][0], B[rt][2][0], G1));
-          G2 = mfma(Ab[rt][2][3], B[rt][2][3], mfma(Ab[rt][2][2], B[rt][2][2], G2));
-          G[rt] = G0 + G1 + G2;
+          // one accumulation chain over the three row types and four k-chunks
+          f4 acc = zb;
+  #pragma unroll
+          for (int d = 0; d < 3; ++d)
+  #pragma unroll
+            for (int r = 0; r < 4; ++r) acc = mfma(Ab[rt][d][r], B[rt][d][r], acc);
+          G[rt] = acc;
         }
         // issue the LDS reads before the MFMAs that consume them
         __builtin_amdgcn_sched_group_barrier(0x100, 12 * RT, 0);
@@ -1117,13 +1118,14 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
         const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
         const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
                                 u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
-        xb = xb + (mfma_bf16(Mhi, uh, z) + (mfma_bf16(Mhi, ul, z) + mfma_bf16(Mlo, uh, z)));
+        // (the two small cross terms first, then the leading one, all into
+        // one accumulator)
+        xb = xb + mfma_bf16(Mhi, uh, mfma_bf16(Mlo, uh, mfma_bf16(Mhi, ul, z)));
       } else {
+        // accumulated straight into xi_bar: one chain, no VALU sums
         const f4 u = (xi - xb) + lam + rho * g;
-        const f4 h0 = mfma(Am[1], u[1], mfma(Am[0], u[0], z));
-        f4 h1 = mfma(Am[2], u[2], z);
-        if (chunk3) h1 = mfma(Am[3], u[3], h1);
-        xb = xb + (h0 + h1);
+        xb = mfma(Am[2], u[2], mfma(Am[1], u[1], mfma(Am[0], u[0], xb)));
+        if (chunk3) xb = mfma(Am[3], u[3], xb);
       }
       PRIEST_PROJ_MARK(5);
     }
