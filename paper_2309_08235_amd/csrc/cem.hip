@@ -668,11 +668,14 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   }
   // 5. factor Sigma' + eps I (first wave)
   if (tid < 64) {
+    PRIEST_CEM_SUB(8);
     float tr = 0.0f;
     for (int d = tid; d < D; d += 64) tr += A[d * D + d];
     tr = wave_sum(tr);
+    PRIEST_CEM_SUB(9);
     const float eps = a.cov_jitter * tr / static_cast<float>(D);
     const bool ok = cholesky_wave<DM>(A, eps, D, tid, L);
+    PRIEST_CEM_SUB(10);
     if (tid == 0 && a.status && !(ok && best_ok)) a.status[prob] = PRIEST_ERR_NONFINITE;
   }
   PRIEST_CEM_MARK(6);
