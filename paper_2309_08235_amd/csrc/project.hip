@@ -10,8 +10,8 @@
 // per-sample batching of Sec. III-A):
 //
 //   forward   p, v, a rows of each of the wave's time blocks = W xi_bar
-//             (3 chains of 4 MFMA 16x16x4 per block, W = [P; Pdot; Pddot]
-//             rows as A)
+//             (one MFMA 16x16x4 accumulation chain per row type over the
+//             k-chunks, W = [P; Pdot; Pddot] rows as A)
 //   transpose quad-local transpose through LDS: each lane then holds every
 //             axis of 4/AS (sample, t) items per time block
 //   push-out  closed-form alpha/beta/d of each obstacle as a push-out
