@@ -279,15 +279,19 @@ __device__ __forceinline__ bool pair_push(const Rec& o, float tt, const float p[
 // The same push-out split in two so that the independent parts of several
 // obstacles can interleave: pair_term computes the offset and the factor
 // (MOVING: centre advanced to time t), pair_add accumulates them in the
-// order the caller adds obstacles.  The canonical push-out of a zero offset
-// is added through a select: other lanes add +0, which leaves the sums
-// unchanged (they are never -0).
+// order the caller adds obstacles.  A zero offset gets its canonical push-out
+// through kNudge.
 template <int DIMS>
 struct PairTerm {
   float d[DIMS];
   float f, len2;
-  bool zero;
 };
+
+// Added to the canonical component of every offset (x in 2D, z in 3D): it
+// leaves any offset above 1e-11 unchanged and turns an offset of exactly zero
+// into a tiny one along the canonical axis, whose push-out is the semi-axis
+// up to rounding, so the pair loop needs no test for that case.
+constexpr float kNudge = 1.0e-18f;
 
 template <int DIMS, bool LAST, bool MOVING>
 __device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, const float p[DIMS]) {
@@ -301,6 +305,7 @@ __device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, cons
     r.d[1] = p[1] - o.cy;
     if constexpr (DIMS == 3) r.d[2] = p[2] - o.cz;
   }
+  r.d[DIMS == 2 ? 0 : 2] += kNudge;
   const float h = fmaf(r.d[1], r.d[1], r.d[0] * r.d[0]);
   float q, f;
   if constexpr (DIMS == 2) {
@@ -315,7 +320,6 @@ __device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, cons
     if (LAST) f = (q < 1.0f) ? f : 0.0f;
   }
   r.f = fmaxf(f, 0.0f);
-  r.zero = q == 0.0f;
   return r;
 }
 
@@ -327,14 +331,6 @@ __device__ __forceinline__ void pair_add(const Rec& o, const PairTerm<DIMS>& t, 
 #pragma unroll
   for (int x = 0; x < DIMS; ++x) s[x] = fmaf(t.d[x], t.f, s[x]);
   if (LAST) r2 = fmaf(t.len2 * t.f, t.f, r2);
-  if constexpr (DIMS == 2) {
-    s[0] += t.zero ? o.a : 0.0f;
-    if (LAST) r2 += t.zero ? o.a2 : 0.0f;
-  } else {
-    const float b = o.a2;  // rsq(1/b^2), precomputed in the record
-    s[2] += t.zero ? b : 0.0f;
-    if (LAST) r2 = t.zero ? fmaf(b, b, r2) : r2;
-  }
 }
 
 // Record of lane b broadcast to the wave (velocity only if MOVING).
