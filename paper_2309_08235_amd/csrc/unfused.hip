@@ -14,6 +14,7 @@
 // sample as [row type][axis][t], so consecutive threads (consecutive t) and
 // the update's lanes touch consecutive addresses.
 #include <algorithm>
+#include <type_traits>
 
 #include "priest_internal.h"
 
@@ -26,26 +27,52 @@ struct ORec {
   float cx, cy, cz, vx, vy, vz, a, a2, ia2, ib2;
 };
 
-// One thread per (sample, t); the basis rows are staged in LDS (row stride
-// 3 n_coeff floats: an odd stride for odd n_coeff, so lanes of consecutive t
-// hit distinct banks).
-__global__ void uf_forward(const float* __restrict__ W, const float* __restrict__ xb, int N, int K,
-                           int nv, int dims, float* __restrict__ pva) {
-  extern __shared__ float sW[];
-  for (int j = threadIdx.x; j < K * 3 * nv; j += blockDim.x) sW[j] = W[j];
+// One thread per time step t (blockIdx.y picks a chunk of kFwdT steps); a
+// block runs through `spb` consecutive samples.  The thread keeps its three
+// basis rows in registers (entries c >= n_coeff zeroed), and a sample's
+// coefficients are block-uniform (staged in LDS and read as broadcasts,
+// clamped to the row so that no read sits under a condition), so each
+// sample costs 3 dims coalesced row stores.
+constexpr int kFwdT = 128;
+constexpr int kFwdMaxSpb = 16;
+
+__global__ __launch_bounds__(kFwdT) void uf_forward(const float* __restrict__ W,
+                                                    const float* __restrict__ xb, int N, int K,
+                                                    int nv, int dims, int spb,
+                                                    float* __restrict__ pva) {
+  const int t = blockIdx.y * kFwdT + threadIdx.x;
+  const bool live = t < K;
+  const int tc = live ? t : K - 1;
+  float w[3][kMaxNV];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int c = 0; c < kMaxNV; ++c)
+      w[d][c] = W[(tc * 3 + d) * nv + (c < nv ? c : nv - 1)] * (c < nv ? 1.0f : 0.0f);
+  const int s0 = blockIdx.x * spb;
+  const int s1 = min(N, s0 + spb);
+  __shared__ float sx[kFwdMaxSpb * 3 * kMaxNV];
+  const int row = dims * nv;
+  for (int j = threadIdx.x; j < (s1 - s0) * row; j += kFwdT)
+    sx[j] = xb[static_cast<int64_t>(s0) * row + j];
   __syncthreads();
-  // grid-stride over (sample, t) items so the staging is amortised
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * K; i += gridDim.x * blockDim.x) {
-    const int s = i / K, t = i - s * K;
-    const float* w = sW + t * 3 * nv;
-    const float* x = xb + static_cast<int64_t>(s) * dims * nv;
+  for (int s = s0; s < s1; ++s) {
+    const float* x = sx + (s - s0) * row;
     float* o = pva + static_cast<int64_t>(s) * 3 * dims * K + t;
-    for (int d = 0; d < 3; ++d)
-      for (int ax = 0; ax < dims; ++ax) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (ax >= dims) break;
+      float xv[kMaxNV];
+#pragma unroll
+      for (int c = 0; c < kMaxNV; ++c) xv[c] = x[ax * nv + (c < nv ? c : nv - 1)];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
         float acc = 0.0f;
-        for (int c = 0; c < nv; ++c) acc = fmaf(w[d * nv + c], x[ax * nv + c], acc);
-        o[(d * dims + ax) * K] = acc;
+#pragma unroll
+        for (int c = 0; c < kMaxNV; ++c) acc = fmaf(w[d][c], xv[c], acc);
+        if (live) o[(d * dims + ax) * K] = acc;
       }
+    }
   }
 }
 
@@ -128,81 +155,120 @@ __global__ void uf_push(const float* __restrict__ pva, const float* __restrict__
   if (LAST) r2out[i] = r2;
 }
 
-// One wave per (sample, axis): lanes split the K time steps of
-// g = W^T delta, a wave reduction sums them, then lane r < n_coeff applies
-// lambda += rho g and row r of the QP step through the fixed KKT block.
-// Loops run to the compile-time bound kMaxNV with n_coeff guards so the
-// per-lane vectors stay in registers.
-__global__ void uf_update(const float* __restrict__ W, const float* __restrict__ M11,
-                          const float* __restrict__ Pi, const float* __restrict__ M12,
-                          const float* __restrict__ bc, const float* __restrict__ delta,
-                          const float* __restrict__ xi, float* __restrict__ xb,
-                          float* __restrict__ lam, int N, int K, int nv, int dims, float rho,
-                          int first) {
-  extern __shared__ float sW[];
-  for (int j = threadIdx.x; j < K * 3 * nv; j += blockDim.x) sW[j] = W[j];
+// A group of `tpr` consecutive lanes (a power of two up to 64) per
+// (sample, axis) row: g = W^T delta over the row's 3K entries, lambda +=
+// rho g, and the QP step through the fixed KKT block.  The group streams
+// its three K-long delta rows in VW-wide loads, lane `sub` taking vectors
+// sub, sub + tpr, ... (consecutive lanes read consecutive addresses), and an
+// xor butterfly inside the group sums g; every lane of the group then
+// forms the step and lane 0 stores it.  W, M11 and Pi are staged in LDS with
+// rows zero-padded to 16 entries, so the per-row loops run to 16 without
+// conditions and entries c >= n_coeff stay zero.  tpr grows for small
+// batches so that enough lanes stream.
+constexpr int kUpdT = 128;
+
+template <int VW>
+__global__ __launch_bounds__(kUpdT) void uf_update(const float* __restrict__ W,
+                                                   const float* __restrict__ M11,
+                                                   const float* __restrict__ Pi,
+                                                   const float* __restrict__ M12,
+                                                   const float* __restrict__ bc,
+                                                   const float* __restrict__ delta,
+                                                   const float* __restrict__ xi,
+                                                   float* __restrict__ xb, float* __restrict__ lam,
+                                                   int N, int K, int nv, int dims, float rho,
+                                                   int first, int tpr) {
+  static_assert(kMaxNV == 16, "LDS rows are padded to 16 entries");
+  extern __shared__ float4 sm4[];
+  float* sW = reinterpret_cast<float*>(sm4);  // [3K][16]
+  float* sM = sW + 3 * K * 16;                 // M11 [16][16]
+  float* sP = sM + 256;                        // Pi  [16][16]
+  for (int j = threadIdx.x; j < 3 * K * 16; j += kUpdT) {
+    const int row = j >> 4, c = j & 15;
+    sW[j] = c < nv ? W[row * nv + c] : 0.0f;
+  }
+  for (int j = threadIdx.x; j < 256; j += kUpdT) {
+    const int row = j >> 4, c = j & 15;
+    const bool in = row < nv && c < nv;
+    sM[j] = in ? M11[row * nv + c] : 0.0f;
+    sP[j] = in ? Pi[row * nv + c] : 0.0f;
+  }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wstride = (gridDim.x * blockDim.x) >> 6;
-  // whole waves stride over (sample, axis) rows, so the staging is amortised
-  for (int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv < N * dims; wv += wstride) {
-  const int s = wv / dims, ax = wv - s * dims;
-  float g[kMaxNV];
+  const int tid = blockIdx.x * kUpdT + threadIdx.x;
+  const int rowi = tid / tpr, sub = tid - rowi * tpr;
+  if (rowi >= N * dims) return;  // whole groups leave together (tpr divides 64)
+  const int s = rowi / dims, ax = rowi - s * dims;
+  float g[16];
 #pragma unroll
-  for (int c = 0; c < kMaxNV; ++c) g[c] = 0.0f;
+  for (int c = 0; c < 16; ++c) g[c] = 0.0f;
   const float* dl = delta + static_cast<int64_t>(s) * 3 * dims * K;
-  for (int t = lane; t < K; t += 64)
-    for (int d = 0; d < 3; ++d) {
-      const float v = dl[(d * dims + ax) * K + t];
-      const float* w = sW + (t * 3 + d) * nv;
+  using VT = typename std::conditional<VW == 4, float4, typename std::conditional<VW == 2, float2, float>::type>::type;
 #pragma unroll
-      for (int c = 0; c < kMaxNV; ++c)
-        if (c < nv) g[c] = fmaf(w[c], v, g[c]);
-    }
+  for (int d = 0; d < 3; ++d) {
+    const VT* row = reinterpret_cast<const VT*>(dl + (d * dims + ax) * K);
+#pragma unroll 4
+    for (int q = sub; q < K / VW; q += tpr) {
+      const VT v = row[q];
+      const float* vv = reinterpret_cast<const float*>(&v);
 #pragma unroll
-  for (int c = 0; c < kMaxNV; ++c)
-    if (c < nv)
+      for (int e = 0; e < VW; ++e) {
+        const float4* w4 = reinterpret_cast<const float4*>(sW + ((q * VW + e) * 3 + d) * 16);
 #pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) g[c] += __shfl_xor(g[c], m, 64);
-  const int64_t base = static_cast<int64_t>(s) * dims * nv + ax * nv;
-  float u[kMaxNV], x0[kMaxNV];
-  float lr = 0.0f, xr = 0.0f;
-#pragma unroll
-  for (int c = 0; c < kMaxNV; ++c) {
-    u[c] = 0.0f;
-    x0[c] = 0.0f;
-    if (c < nv) {
-      x0[c] = xi[base + c];
-      const float xo = xb[base + c];
-      const float l = lam[base + c] + rho * g[c];
-      u[c] = first ? l + rho * g[c] : (x0[c] - xo) + l + rho * g[c];
-      if (c == lane) {
-        lr = l;
-        xr = xo;
+        for (int c4 = 0; c4 < 4; ++c4) {
+          const float4 w = w4[c4];
+          g[4 * c4 + 0] = fmaf(w.x, vv[e], g[4 * c4 + 0]);
+          g[4 * c4 + 1] = fmaf(w.y, vv[e], g[4 * c4 + 1]);
+          g[4 * c4 + 2] = fmaf(w.z, vv[e], g[4 * c4 + 2]);
+          g[4 * c4 + 3] = fmaf(w.w, vv[e], g[4 * c4 + 3]);
+        }
       }
     }
   }
-  if (lane < nv) {
-    const int r = lane;
+  for (int m = 1; m < tpr; m <<= 1)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) g[c] += __shfl_xor(g[c], m, 64);
+  auto cl = [nv](int c) { return c < nv ? c : nv - 1; };
+  const int64_t base = static_cast<int64_t>(s) * dims * nv + ax * nv;
+  float u[16], x0[16], xo[16], l[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const bool in = c < nv;
+    x0[c] = in ? xi[base + cl(c)] : 0.0f;
+    xo[c] = xb[base + cl(c)];
+    l[c] = lam[base + cl(c)] + rho * g[c];
+    u[c] = in ? (first ? l[c] + rho * g[c] : (x0[c] - xo[c]) + l[c] + rho * g[c]) : 0.0f;
+  }
+  float c0[16];
+  if (first) {
+    float bcv[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) bcv[e] = bc[ax * 6 + e];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float a = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) a = fmaf(M12[cl(r) * 6 + e], bcv[e], a);
+      c0[r] = a;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
     float acc = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kMaxNV; ++c)
-      if (c < nv) acc = fmaf(M11[r * nv + c], u[c], acc);
+    for (int c = 0; c < 16; ++c) acc = fmaf(sM[r * 16 + c], u[c], acc);
     float nx;
     if (first) {
       float h = 0.0f;
 #pragma unroll
-      for (int c = 0; c < kMaxNV; ++c)
-        if (c < nv) h = fmaf(Pi[r * nv + c], x0[c], h);
-      float c0 = 0.0f;
-      for (int e = 0; e < 6; ++e) c0 = fmaf(M12[r * 6 + e], bc[ax * 6 + e], c0);
-      nx = (h + c0) + acc;
+      for (int c = 0; c < 16; ++c) h = fmaf(sP[r * 16 + c], x0[c], h);
+      nx = (h + c0[r]) + acc;
     } else {
-      nx = xr + acc;
+      nx = xo[r] + acc;
     }
-    lam[base + r] = lr;
-    xb[base + r] = nx;
-  }
+    if (r < nv && sub == 0) {
+      lam[base + r] = l[r];
+      xb[base + r] = nx;
+    }
   }
 }
 
@@ -260,11 +326,20 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
   float* lam = reinterpret_cast<float*>(ws + l.lam);
   const int64_t nD = static_cast<int64_t>(N) * dims * nv;
   const int items = N * K;
-  const dim3 b256(256), b1024(1024);
-  // forward and update stage W in LDS: at most 8 blocks per CU, grid-stride beyond
-  const dim3 g_items((items + 255) / 256), g_axes((N * dims + 15) / 16);
-  const dim3 g_fwd(std::min<unsigned>(g_items.x, 2048u)), g_upd(std::min<unsigned>(g_axes.x, 512u));
-  const size_t ldsW = sizeof(float) * K * 3 * nv;
+  const dim3 b256(256);
+  const dim3 g_items((items + 255) / 256);
+  // forward: blocks of kFwdT time steps over spb samples, about 2048+ blocks
+  const int spb = std::max(1, std::min(kFwdMaxSpb, N / 2048));
+  const dim3 g_fwd((N + spb - 1) / spb, (K + kFwdT - 1) / kFwdT), b_fwd(kFwdT);
+  // update: tpr lanes per (sample, axis) row, raised only until about 64k
+  // lanes stream (at most 16 per row: at N = 64000, 2D, one lane per row
+  // takes 69 us and four take 109 us; at N = 1000 sixteen take 14 us
+  // against 52 us for one); W, M11 and Pi padded in LDS
+  int tpr = 1;
+  while (tpr < 16 && static_cast<int64_t>(N) * dims * tpr < (64 << 10)) tpr *= 2;
+  const dim3 g_upd(static_cast<unsigned>((static_cast<int64_t>(N) * dims * tpr + kUpdT - 1) / kUpdT));
+  const dim3 b_upd(kUpdT);
+  const size_t lds_upd = sizeof(float) * (3 * K * 16 + 2 * 256);
   const dim3 g_nD(static_cast<unsigned>((nD + 255) / 256)), g_N((N + 255) / 256);
   const size_t lds = sizeof(ORec) * (M > 0 ? M : 1);
   hipLaunchKernelGGL(uf_init, g_nD, b256, 0, s, xi_in, xb, lam, nD);
@@ -278,12 +353,19 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
     }
   };
   for (int k = 0; k < a.n_iter; ++k) {
-    hipLaunchKernelGGL(uf_forward, g_fwd, b256, ldsW, s, a.W, xb, N, K, nv, dims, pva);
+    hipLaunchKernelGGL(uf_forward, g_fwd, b_fwd, 0, s, a.W, xb, N, K, nv, dims, spb, pva);
     push(false);
-    hipLaunchKernelGGL(uf_update, g_upd, b1024, ldsW, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta, xi_in,
-                       xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0);
+    if (K % 4 == 0)
+      hipLaunchKernelGGL(uf_update<4>, g_upd, b_upd, lds_upd, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta,
+                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
+    else if (K % 2 == 0)
+      hipLaunchKernelGGL(uf_update<2>, g_upd, b_upd, lds_upd, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta,
+                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
+    else
+      hipLaunchKernelGGL(uf_update<1>, g_upd, b_upd, lds_upd, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta,
+                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
   }
-  hipLaunchKernelGGL(uf_forward, g_fwd, b256, ldsW, s, a.W, xb, N, K, nv, dims, pva);
+  hipLaunchKernelGGL(uf_forward, g_fwd, b_fwd, 0, s, a.W, xb, N, K, nv, dims, spb, pva);
   push(true);
   hipLaunchKernelGGL(uf_finish, g_N, b256, 0, s, r2, pva, N, K, dims, resid, c1);
   hipLaunchKernelGGL(uf_copy, g_nD, b256, 0, s, xb, xi_out, nD);
