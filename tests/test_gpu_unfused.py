@@ -83,3 +83,44 @@ def test_unfused_rejects_bf16_and_small_workspace(P):
                                  xi, 5, xo, None, None, ws)
     assert e.value.code == P.PRIEST_ERR_NOMEM
     prob.close()
+
+
+def test_unfused_odd_steps_against_oracle(P):
+    """K = 51: rows of odd length, streamed in single-float loads."""
+    wl = W.with_changes(W.C1, n_steps=51)
+    say("unfused projection c1 with K=51, N=64, 30 iterations vs oracle")
+    prob = P.Problem.from_workload(wl)
+    op = oracle_problem(wl)
+    bc, obs = W.scene(wl, 4)
+    xi = W.samples(wl, 6, n=64).astype(np.float32)
+    xo, r, _ = prob.project_unfused(t32(bc), t32(obs), t32(xi), 30)
+    torch.cuda.synchronize()
+    pr = O.project(op, bc, obs, xi.astype(np.float64), 30)
+    check_projection(op, bc, obs, xi, xo.cpu().numpy().astype(np.float64), pr.xi_bar, 30,
+                     label="unfused K=51")
+    np.testing.assert_allclose(r.cpu().numpy(), pr.resid, atol=2e-3 * max(1.0, pr.resid.max()))
+    prob.close()
+
+
+def test_unfused_large_batch_against_fused_and_oracle(P):
+    """N = 40000 in 2D: 80000 update rows, enough for one lane per row (small
+    batches split each row over a group of lanes)."""
+    wl = W.C2
+    N, n_iter = 40000, 20
+    say(f"unfused vs fused and an oracle sample, C2 shape, N={N}, {n_iter} iterations")
+    prob = P.Problem.from_workload(wl)
+    op = oracle_problem(wl)
+    bc, obs = W.scene(wl, 3)
+    xi_np = W.samples(wl, 5, n=N).astype(np.float32)
+    xi = t32(xi_np)
+    xf, _, _ = prob.project(t32(bc), t32(obs), xi, n_iter)
+    xu, _, _ = prob.project_unfused(t32(bc), t32(obs), xi, n_iter)
+    torch.cuda.synchronize()
+    xu_np = xu.cpu().numpy()
+    e = rel_err(xu_np, xf.cpu().numpy())
+    assert np.median(e) < 1e-5 and np.quantile(e, 0.99) < 1e-3, (np.median(e), e.max())
+    idx = np.sort(np.random.default_rng(0).choice(N, 48, replace=False))
+    pr = O.project(op, bc, obs, xi_np[idx].astype(np.float64), n_iter)
+    check_projection(op, bc, obs, xi_np[idx], xu_np[idx].astype(np.float64), pr.xi_bar, n_iter,
+                     label="unfused N=40000 sample")
+    prob.close()
