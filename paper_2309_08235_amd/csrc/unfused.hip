@@ -30,9 +30,9 @@ struct ORec {
 // One thread per time step t (blockIdx.y picks a chunk of kFwdT steps); a
 // block runs through `spb` consecutive samples.  The thread keeps its three
 // basis rows in registers (entries c >= n_coeff zeroed), and a sample's
-// coefficients are block-uniform (staged in LDS and read as broadcasts,
-// clamped to the row so that no read sits under a condition), so each
-// sample costs 3 dims coalesced row stores.
+// coefficients are block-uniform (staged in LDS as zero-padded rows of 16
+// and read as four 16-byte broadcasts per axis), so each sample costs
+// 3 dims coalesced row stores.
 constexpr int kFwdT = 128;
 constexpr int kFwdMaxSpb = 16;
 
@@ -51,20 +51,29 @@ __global__ __launch_bounds__(kFwdT) void uf_forward(const float* __restrict__ W,
       w[d][c] = W[(tc * 3 + d) * nv + (c < nv ? c : nv - 1)] * (c < nv ? 1.0f : 0.0f);
   const int s0 = blockIdx.x * spb;
   const int s1 = min(N, s0 + spb);
-  __shared__ float sx[kFwdMaxSpb * 3 * kMaxNV];
-  const int row = dims * nv;
-  for (int j = threadIdx.x; j < (s1 - s0) * row; j += kFwdT)
-    sx[j] = xb[static_cast<int64_t>(s0) * row + j];
+  static_assert(kMaxNV == 16, "coefficient rows are staged as four float4");
+  __shared__ float4 sx[kFwdMaxSpb * 3 * 4];  // [sample][axis][16], zero-padded
+  for (int j = threadIdx.x; j < (s1 - s0) * dims * 16; j += kFwdT) {
+    const int k = j / (dims * 16), rem = j - k * dims * 16, ax = rem >> 4, c = rem & 15;
+    reinterpret_cast<float*>(sx)[j] =
+        c < nv ? xb[static_cast<int64_t>(s0 + k) * dims * nv + ax * nv + c] : 0.0f;
+  }
   __syncthreads();
   for (int s = s0; s < s1; ++s) {
-    const float* x = sx + (s - s0) * row;
+    const float4* x = sx + (s - s0) * dims * 4;
     float* o = pva + static_cast<int64_t>(s) * 3 * dims * K + t;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       if (ax >= dims) break;
       float xv[kMaxNV];
 #pragma unroll
-      for (int c = 0; c < kMaxNV; ++c) xv[c] = x[ax * nv + (c < nv ? c : nv - 1)];
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const float4 v = x[ax * 4 + c4];
+        xv[4 * c4] = v.x;
+        xv[4 * c4 + 1] = v.y;
+        xv[4 * c4 + 2] = v.z;
+        xv[4 * c4 + 3] = v.w;
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         float acc = 0.0f;
