@@ -342,7 +342,7 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
   const dim3 g_fwd((N + spb - 1) / spb, (K + kFwdT - 1) / kFwdT), b_fwd(kFwdT);
   // update: tpr lanes per (sample, axis) row, raised only until about 64k
   // lanes stream (at most 16 per row: at N = 64000, 2D, one lane per row
-  // takes 69 us and four take 109 us; at N = 1000 sixteen take 14 us
+  // takes 98 us, two 102 us and four 109 us; at N = 1000 sixteen take 14 us
   // against 52 us for one); W, M11 and Pi padded in LDS
   int tpr = 1;
   while (tpr < 16 && static_cast<int64_t>(N) * dims * tpr < (64 << 10)) tpr *= 2;
