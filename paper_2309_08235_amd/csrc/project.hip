@@ -154,7 +154,7 @@ __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int MB
 // the box.  A skipped obstacle is farther than a * 1.001 + 1e-4 from every
 // item, where the push-out is exactly 0, so culling does not change results.
 // ---------------------------------------------------------------------------
-constexpr float kTiny = 1.0e-30f;
+constexpr float kTiny = 1.0e-36f;
 
 // Obstacle candidates processed together in the push-out loop.
 #ifndef PRIEST_CAND_UNROLL
@@ -287,11 +287,13 @@ struct PairTerm {
   float f, len2;
 };
 
-// Added to the canonical component of every offset (x in 2D, z in 3D): it
-// leaves any offset above 1e-11 unchanged and turns an offset of exactly zero
-// into a tiny one along the canonical axis, whose push-out is the semi-axis
-// up to rounding, so the pair loop needs no test for that case.
-constexpr float kNudge = 1.0e-18f;
+// Added to the canonical component of every offset (x in 2D, z in 3D): it is
+// below half an ulp of any offset above about 2e-8, so those are unchanged,
+// and it turns an offset of exactly zero into one of 1e-15 along the
+// canonical axis, whose push-out is the semi-axis up to rounding, so the
+// pair loop needs no test for that case.  Its square over b^2 (1e-30 / b^2)
+// must stay above the clamp kTiny, which holds for semi-axes up to 1000.
+constexpr float kNudge = 1.0e-15f;
 
 template <int DIMS, bool LAST, bool MOVING>
 __device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, const float p[DIMS]) {
