@@ -129,7 +129,9 @@ typedef struct priest_cost {
 /* Sampling-loop settings (Alg. 1, eqs. (9a)-(9c)).  A zero-initialised cost
  * is the smoothness cost. */
 typedef struct priest_cem_params {
-  int32_t n_samples;    /* N_b: samples per CEM iteration, 1..PRIEST_MAX_SAMPLES */
+  int32_t n_samples;    /* N_b: samples per CEM iteration, 1..8192 (the selection kernel
+                           holds a problem's samples in one block; PRIEST_MAX_SAMPLES
+                           bounds the projection calls only) */
   int32_t n_cem;        /* CEM iterations */
   int32_t n_proj_iters; /* projection iterations per CEM iteration */
   int32_t n_proj;       /* N_proj: size of the lowest-residual set, 1..n_samples */
@@ -347,7 +349,13 @@ int32_t priest_plan_dpriest(priest_problem* p, int32_t n_groups, const float* bc
 /* Debug/parity hook for the closed-form alpha/beta/d step (Appendix eqs.
  * (15a)-(15c), (13)): for samples xi [N][D] writes the per-row push-outs
  * e(xi) - F xi, laid out [N][n_obs + 2][K][dims] (obstacle blocks, then the
- * velocity block, then the acceleration block).  Meant for small N. */
+ * velocity block, then the acceleration block).  The push-outs rather than
+ * alpha, beta, d themselves are returned because the kernels never form the
+ * angles: each target of eq. (13) is the obstacle (or origin) plus the
+ * scaled direction (cos a sin b, sin a sin b, cos b) d, so alpha, beta and d
+ * are the polar coordinates of (push-out + F xi - o) in the obstacle's
+ * scaled frame, and comparing push-outs checks all three at once.  Meant for
+ * small N (<= 4096). */
 int32_t priest_debug_offsets(priest_problem* p, const float* bc, const float* obs,
                              const float* xi, int32_t N, float* offsets, void* stream);
 

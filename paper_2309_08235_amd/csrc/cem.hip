@@ -6,10 +6,11 @@
 //      (ties keep index order);
 //   2. EliteSet: the n_elite lowest c_aug = c1 + r among them, ties kept in
 //      the order of step 1.
-//   When the ordered set of step 1 is an output, both steps are stable block
-//   radix sorts; otherwise (N <= 2048, n_elite <= 512) they are radix selects
-//   of the boundary keys and a ranking of the n_elite survivors by counting,
-//   which select and order exactly the same samples.
+//   When the ordered set of step 1 is an output, both steps sort packed
+//   64-bit keys (order-preserving key bits above the position) with a
+//   bitonic network in LDS; otherwise (N <= 2048, n_elite <= 512) they are
+//   radix selects of the boundary keys and a ranking of the n_elite
+//   survivors by counting, which select and order exactly the same samples.
 //   3. weights c_m = exp(-(c_aug_m - delta)/gamma), delta = min c_aug;
 //   4. mu' = (1-sigma) mu + sigma sum w xi_bar / sum w,
 //      Sigma' = (1-sigma) Sigma + sigma sum w (xi_bar - mu')(xi_bar - mu')^T / sum w;
@@ -17,16 +18,6 @@
 //      draw: one wave, lane i holds row i in registers.
 // Every sum runs in a fixed order, so results are bitwise reproducible.
 #include "priest_internal.h"
-
-#include <hipcub/block/block_radix_sort.hpp>
-
-// Phase markers (no-ops unless a profiling build defines them).
-#ifndef PRIEST_CEM_MARK
-#define PRIEST_CEM_MARK(i)
-#endif
-#ifndef PRIEST_CEM_SUB
-#define PRIEST_CEM_SUB(i)
-#endif
 
 namespace priest {
 namespace {
@@ -125,25 +116,30 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Stable selection of the k smallest keys among n (n <= T * IPT): writes the
-// values of ranks 0..k-1 to out[] in ascending (key, input position) order.
-template <int IPT>
-__device__ __forceinline__ void select_sorted(const uint32_t* keys_in, const int* vals_in, int n, int k,
-                              int* out, void* temp) {
-  using Sort = hipcub::BlockRadixSort<uint32_t, kCemThreads, IPT, int>;
-  uint32_t key[IPT];
-  int val[IPT];
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const int e = threadIdx.x * IPT + i;
-    key[i] = (e < n) ? keys_in[e] : 0xffffffffu;
-    val[i] = (e < n) ? vals_in[e] : -1;
-  }
-  Sort(*reinterpret_cast<typename Sort::TempStorage*>(temp)).Sort(key, val);
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const int rnk = threadIdx.x * IPT + i;
-    if (rnk < k) out[rnk] = val[i];
+// Ascending sort of n packed keys (key bits << 32 | position) in LDS by a
+// bitonic network over the next power of two (padding keys sort last).  The
+// positions make every key distinct, so the order is that of a stable sort
+// of the key bits.  Every thread of the block calls it; a[] holds at least
+// the next power of two >= n entries.
+__device__ __forceinline__ void bitonic_sort_keys(unsigned long long* a, int n) {
+  const int tid = threadIdx.x;
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int i = n + tid; i < m; i += kCemThreads) a[i] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < (m >> 1); i += kCemThreads) {
+        const int lo = 2 * i - (i & (j - 1)), hi = lo + j;
+        const unsigned long long x = a[lo], y = a[hi];
+        const bool up = (lo & k) == 0;
+        if ((x > y) == up) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -275,7 +271,6 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     k1[j] = valid[j] ? ordered_bits(vr[j]) : ~0u;
   }
   // step 1: the n_proj lowest (r key, index)
-  PRIEST_CEM_SUB(3);
   uint32_t v1, m1, less1, eq1;
   radix_select<IPT>(k1, valid, static_cast<uint32_t>(n_proj - 1), hist, bc, v1, m1, less1, eq1);
   const uint32_t t1 = static_cast<uint32_t>(n_proj) - less1;  // members among the keys equal to v1
@@ -294,7 +289,6 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     for (int j = 0; j < IPT; ++j) mem[j] = valid[j] && (k1[j] < v1 || (tie[j] && pre[j] < t1));
   }
   // step 2: the n_elite lowest (c_aug key, r key, index) among them
-  PRIEST_CEM_SUB(4);
   uint32_t k2[IPT];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) k2[j] = mem[j] ? ordered_bits(vc[j] + vr[j]) : ~0u;
@@ -328,7 +322,6 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
       }
     }
   }
-  PRIEST_CEM_SUB(5);
   // the n_elite survivors, in slots of arbitrary order ...
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
@@ -342,7 +335,6 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     }
   }
   __syncthreads();
-  PRIEST_CEM_SUB(6);
   // ... ranked by counting: Q threads per survivor, each over a share of the
   // others
   // (all three fields read and compared without short-circuits: a lazy read
@@ -366,17 +358,16 @@ __device__ __forceinline__ void select_fast(const float (&vr)[IPT], const float 
     const uint32_t rk = lrank[m];
     if (rk < static_cast<uint32_t>(n_elite)) elite[rk] = li[m];
   }
-  PRIEST_CEM_SUB(7);
 }
 
 // One block's work: selection, refit and factorisation for problem `prob`
 // of `a`.  Shared by the uniform-batch kernel and the descriptor-table kernel.
 template <int IPT, int DM>
 __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
-  using Sort = hipcub::BlockRadixSort<uint32_t, kCemThreads, IPT, int>;
-  __shared__ typename Sort::TempStorage sort_tmp;
-  __shared__ uint32_t skey[kCemThreads * IPT];
-  __shared__ int sval[kCemThreads * IPT];
+  // packed sort keys of the ordered selection; their low words double as the
+  // fast selection's scratch
+  __shared__ unsigned long long skv[kCemThreads * IPT];
+  uint32_t* skey = reinterpret_cast<uint32_t*>(skv);
   // r and c1 of every sample, read from HBM once (up to 2048 samples; larger
   // problems gather them from HBM)
   constexpr bool kPre = IPT <= 4;
@@ -400,7 +391,6 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   float* mu = a.mu + prob * a.mu_stride;
   float* cov = a.cov + prob * a.cov_stride;
   float* L = a.L + prob * a.L_stride;
-  PRIEST_CEM_MARK(0);
 
   bool best_ok = true;  // the best c_aug is not NaN
   // (the factorisation that starts a plan also starts its status word)
@@ -445,8 +435,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
           s_r[i] = vr[k];
           s_c1[i] = vc[k];
         }
-        skey[i] = ordered_bits(vr[k]);
-        sval[i] = i;
+        skv[i] = (static_cast<unsigned long long>(ordered_bits(vr[k])) << 32) | static_cast<uint32_t>(i);
       }
     }
     if constexpr (kPre) {
@@ -465,28 +454,27 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
     if (fast) {
       if constexpr (kPre) select_fast<IPT>(vr, vc, N, a.n_proj, a.n_elite, s_r, s_fast, skey, elite);
       __syncthreads();
-      PRIEST_CEM_MARK(1);
     } else {
-      select_sorted<IPT>(skey, sval, N, a.n_proj, proj, &sort_tmp);
+      bitonic_sort_keys(skv, N);
+      for (int i = tid; i < a.n_proj; i += T) {
+        const int s = static_cast<int>(static_cast<uint32_t>(skv[i]));
+        proj[i] = s;
+        if (a.proj_idx) a.proj_idx[prob * a.n_proj + i] = s;
+      }
       __syncthreads();
-      PRIEST_CEM_MARK(1);
-      for (int i = tid; i < a.n_proj; i += T)
-        if (a.proj_idx) a.proj_idx[prob * a.n_proj + i] = proj[i];
       // 2. lowest c_aug within them; ties keep the order of step 1
       for (int i = tid; i < a.n_proj; i += T) {
         const int s = proj[i];
-        skey[i] = ordered_bits(c1[s] + r[s]);
-        sval[i] = i;
+        skv[i] = (static_cast<unsigned long long>(ordered_bits(c1[s] + r[s])) << 32) |
+                 static_cast<uint32_t>(i);
       }
       __syncthreads();
-      select_sorted<IPT>(skey, sval, a.n_proj, a.n_elite, elite, &sort_tmp);
-      __syncthreads();
-      for (int m = tid; m < a.n_elite; m += T) elite[m] = proj[elite[m]];
+      bitonic_sort_keys(skv, a.n_proj);
+      for (int m = tid; m < a.n_elite; m += T) elite[m] = proj[static_cast<uint32_t>(skv[m])];
       __syncthreads();
     }
     if (a.elite_idx)
       for (int m = tid; m < a.n_elite; m += T) a.elite_idx[prob * a.n_elite + m] = elite[m];
-    PRIEST_CEM_MARK(2);
     // 3. weights; fixed-order sum by the first wave
     const int e0 = elite[0];
     const float delta = c1[e0] + r[e0];
@@ -520,7 +508,6 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       c1r = 2.0f / ((n + 1.3f) * (n + 1.3f) + mu_eff);
       cmu = fminf(1.0f - c1r, 2.0f * (mu_eff - 2.0f + 1.0f / mu_eff) / ((n + 2.0f) * (n + 2.0f) + mu_eff));
     }
-    PRIEST_CEM_MARK(3);
     // 4. mean and covariance from elite rows staged in LDS, CH rows at a time
     float* stage = reinterpret_cast<float*>(sm + l.stage);
     const int CH = kStageFloats / D;
@@ -568,7 +555,6 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       }
     }
     __syncthreads();
-    PRIEST_CEM_MARK(4);
     // covariance about the new mean, sum_m w_m (x_m - mu')(x_m - mu')^T (rule
     // 1: about the current mean), on MFMA 16x16x4: wave v computes
     // lower-triangle tile v of the ceil(D/16)^2 tiles, elites four at a time
@@ -604,7 +590,6 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
         // here lets the compiler move each load under its own branch, one
         // LDS round trip after another.
         constexpr int kU = 4;
-        PRIEST_CEM_SUB(0);
         for (int s0 = 0; s0 < nm; s0 += 8 * kU) {
           float av[kU][2], bv[kU][2];
 #pragma unroll
@@ -627,7 +612,6 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
       }
       if (!one_chunk) __syncthreads();
     }
-    PRIEST_CEM_SUB(1);
     if (owner) {
       const f4 acc = acc0 + acc1;
 #pragma unroll
@@ -645,9 +629,7 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
         }
       }
     }
-    PRIEST_CEM_SUB(2);
     __syncthreads();
-    PRIEST_CEM_MARK(5);
     // the outputs other than L, written by the other waves while the first
     // one factors
     if (tid >= 64) {
@@ -668,18 +650,13 @@ __device__ __forceinline__ void cem_block(const CemArgs& a, int prob) {
   }
   // 5. factor Sigma' + eps I (first wave)
   if (tid < 64) {
-    PRIEST_CEM_SUB(8);
     float tr = 0.0f;
     for (int d = tid; d < D; d += 64) tr += A[d * D + d];
     tr = wave_sum(tr);
-    PRIEST_CEM_SUB(9);
     const float eps = a.cov_jitter * tr / static_cast<float>(D);
     const bool ok = cholesky_wave<DM>(A, eps, D, tid, L);
-    PRIEST_CEM_SUB(10);
     if (tid == 0 && a.status && !(ok && best_ok)) a.status[prob] = PRIEST_ERR_NONFINITE;
   }
-  PRIEST_CEM_MARK(6);
-  PRIEST_CEM_MARK(7);
 }
 
 template <int IPT, int DM>

@@ -45,15 +45,6 @@
 #include <mutex>
 #include <type_traits>
 
-// Phase markers inside a projection iteration (no-ops unless a profiling
-// build defines them).
-#ifndef PRIEST_PROJ_MARK
-#define PRIEST_PROJ_MARK(i)
-#endif
-#ifndef PRIEST_PROJ_COUNT
-#define PRIEST_PROJ_COUNT(n)
-#endif
-
 namespace priest {
 namespace {
 
@@ -573,7 +564,6 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       row_min4(mn, lo[x]);
       row_max4(mx, hi[x]);
     }
-    PRIEST_PROJ_MARK(6);
     float cmin = INFINITY;
     auto cull_group = [&](int g, float4 R0, float4 R1, unsigned long long& mask,
                           unsigned long long& moving) {
@@ -633,7 +623,6 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     cc.valid = true;
     if (M > 64 * kRegGroups) wave_lds_sync();
   }
-  PRIEST_PROJ_MARK(7);
   uint32_t ncand = 0;
   // the candidates of one group, kCandUnroll at a time (their offsets and
   // factors are independent), added in the canonical order, the tail one at a
@@ -661,7 +650,6 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     }
     auto run = [&](unsigned long long mask, auto moving_tag) {
       constexpr bool MV = decltype(moving_tag)::value;
-      PRIEST_PROJ_COUNT(__builtin_popcountll(mask));
       while (mask) {
         if (__builtin_popcountll(mask) >= kCandUnroll) {
           Rec o[kCandUnroll];
@@ -719,7 +707,6 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
           rec[2 * M + clampj(j)]);
   }
   cc.pairs += ncand * cc.nok;
-  PRIEST_PROJ_MARK(8);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (!ok[i]) {
@@ -994,14 +981,11 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
     }
     // ---- projection iterations ---------------------------------------------------
     for (int k = 0; k < a.n_iter; ++k) {
-      PRIEST_PROJ_MARK(0);
       float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS];
       forward(p, v, ac);
-      PRIEST_PROJ_MARK(1);
       float S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
       item_push<DIMS, false, NI, HIST, TRAJ>(rec, M, tt, tmid, thalf, item_ok, p, v, ac, a.vmax, a.amax,
                                              a.box, S, dv, da, r2, lane, cull, wm, opath, t_item, K);
-      PRIEST_PROJ_MARK(2);
       if constexpr (HIST) {
         // squared push-outs of this iteration per (t, sample), summed per
         // sample after the barrier below (double-buffered by iteration)
@@ -1083,7 +1067,6 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
         for (int rt = 0; rt < RT; ++rt)
           *reinterpret_cast<f4*>(gp + (w * RT + rt) * 256 + lane * 4) = G[rt];
       }
-      PRIEST_PROJ_MARK(3);
       __syncthreads();
       // g = sum of the NB block partials, in the pairwise order of a balanced
       // tree over MB slots (empty slots are zero, which leaves every partial
@@ -1108,7 +1091,6 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
           if (b == MB - 1) g = v;
         }
       }
-      PRIEST_PROJ_MARK(4);
       if constexpr (HIST) {
         // ||F xi_bar^k - e^{k+1}|| per sample, summed over t in order
         if (tid < ns) {
@@ -1146,7 +1128,6 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
         xb = mfma(Am[2], u[2], mfma(Am[1], u[1], mfma(Am[0], u[0], xb)));
         if (chunk3) xb = mfma(Am[3], u[3], xb);
       }
-      PRIEST_PROJ_MARK(5);
     }
 
     // ---- residual and smoothness cost of the returned iterate -----------------------

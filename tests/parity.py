@@ -30,11 +30,20 @@ def rel_err(got: np.ndarray, want: np.ndarray) -> np.ndarray:
     return np.abs(got - want).max(1) / np.maximum(1.0, np.abs(want).max(1))
 
 
-def check_projection(prob, bc, obs, xi32, got, want, n_iter, rng_seed=0, label=""):
+def check_projection(prob, bc, obs, xi32, got, want, n_iter, rng_seed=0, label="",
+                     counts=None):
     """Element-wise parity of projected samples with the sensitivity rule.
-    Returns the per-sample errors; raises AssertionError on a violation."""
+    Returns the per-sample errors; raises AssertionError on a violation.
+    The number of samples above XI_TOL (every one of them shown to be
+    sensitive) is printed and, when ``counts`` is a dict, added to
+    counts["sensitive"] beside counts["checked"]."""
     err = rel_err(got, want)
     bad = np.nonzero(err > XI_TOL)[0]
+    print(f"[parity] {label}: {len(err)} samples checked, {bad.size} above {XI_TOL} "
+          f"(median err {np.median(err):.2e}, max {err.max():.2e})", flush=True)
+    if counts is not None:
+        counts["checked"] = counts.get("checked", 0) + len(err)
+        counts["sensitive"] = counts.get("sensitive", 0) + int(bad.size)
     if bad.size:
         rng = np.random.default_rng(rng_seed)
         pert = xi32[bad].astype(np.float64)

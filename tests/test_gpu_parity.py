@@ -130,6 +130,33 @@ def test_projection_zero_offset(priest, dims):
     gp.close()
 
 
+@pytest.mark.parametrize("dims", [2, 3])
+def test_residual_zero_offset_every_step(priest, dims):
+    """n_iter = 0 on the zero trajectory with an obstacle centred at the
+    origin: every step's offset is exactly zero (all coefficients are zero,
+    so every product and sum is an exact zero; a constant trajectory at 1.5
+    would leave rounding residues of the partition of unity instead), so the
+    final pass takes the canonical push-out at all K steps and
+    r = sqrt(K) * (canonical semi-axis): a in 2D (+x), b in 3D (+z), as in the
+    oracle.  No velocity or acceleration violation (v = a = 0)."""
+    say(f"residual of a trajectory at an obstacle's centre, n_iter = 0, {dims}D")
+    K = 7
+    wl = W.with_changes(W.C1, dims=dims, n_obs=1, n_steps=K, start=(0.0, 0.0, 0.0),
+                        goal=(5.0, 5.0, 5.0), bc_mask=W.BC_DEFAULT)
+    gp, op = make(priest, wl)
+    obs = np.zeros((1, 8)); obs[0, 6] = 0.4; obs[0, 7] = 0.7
+    xi = np.zeros((3, dims * 11), np.float32)
+    bc = W.boundary_values(wl)
+    xo, r, _ = gp.project(t32(bc), t32(obs), t32(xi), 0)
+    torch.cuda.synchronize()
+    semi = 0.4 if dims == 2 else 0.7
+    want = O.residual(op, obs, xi.astype(np.float64))
+    np.testing.assert_allclose(want, semi * math.sqrt(K), rtol=1e-12)
+    np.testing.assert_allclose(np64(r), want, rtol=2e-6)
+    np.testing.assert_array_equal(np64(xo), xi.astype(np.float64))
+    gp.close()
+
+
 # ---------------------------------------------------------------------------
 # counter-based draws
 # ---------------------------------------------------------------------------
@@ -188,6 +215,41 @@ def test_project_c3_shape_sampled(priest):
     err, got, gr, gc, pr, want_c1 = _project_case(priest, W.C3, 2000, idx, n_iter=60)
     assert np.median(err) < 1e-4
     np.testing.assert_allclose(gr[idx], pr.resid, atol=2e-3 * max(1, pr.resid.max()))
+
+
+def test_project_c3_full_batch_100_iterations(priest):
+    """The 3D batched workload at its configured size: 64 problems (distinct
+    scenes) x 2000 samples, M = 128 spheres, K = 100, 100 projection
+    iterations, in one priest_project_batch launch with the autotuned tile
+    shape (the launch the benchmark's batched plans make); the oracle checks
+    16 samples from each of 4 problems spread over the batch, element by
+    element, with their residual and smoothness cost."""
+    wl = W.C3
+    P_, N = wl.n_problems, wl.n_samples
+    say(f"project_batch c3 {P_} problems x {N} samples, 100 iterations, oracle on 4 x 16 samples")
+    gp, op = make(priest, wl)
+    scenes = [W.scene(wl, q) for q in range(P_)]
+    bc = np.stack([s[0] for s in scenes])
+    obs = np.stack([s[1] for s in scenes])
+    xi = np.stack([W.samples(wl, 500 + q, n=N) for q in range(P_)]).astype(np.float32)
+    xo, r, c1 = gp.project_batch(t32(bc), t32(obs), t32(xi), wl.n_proj_iters)
+    torch.cuda.synchronize()
+    got, gr, gc = np64(xo), np64(r), np64(c1)
+    assert np.all(np.isfinite(got)) and np.all(np.isfinite(gr)) and np.all(np.isfinite(gc))
+    counts = {}
+    rng = np.random.default_rng(3)
+    for q in (0, 21, 42, 63):
+        idx = rng.choice(N, 16, replace=False)
+        pr = O.project(op, bc[q], obs[q], xi[q, idx].astype(np.float64), wl.n_proj_iters)
+        err = check_projection(op, bc[q], obs[q], xi[q, idx], got[q, idx], pr.xi_bar,
+                               wl.n_proj_iters, label=f"c3 batch problem {q}", counts=counts)
+        assert np.median(err) < 1e-4, (q, np.median(err))
+        np.testing.assert_allclose(gr[q, idx], pr.resid, atol=2e-3 * max(1, pr.resid.max()))
+        want_c1 = O.smoothness_cost(op, pr.xi_bar)
+        np.testing.assert_allclose(gc[q, idx], want_c1, rtol=2e-3, atol=1e-3)
+    say(f"c3 batch: {counts['sensitive']} of {counts['checked']} checked samples above the "
+        f"tolerance (each shown sensitive)")
+    gp.close()
 
 
 @pytest.mark.parametrize("n", [1, 3, 37])
@@ -298,6 +360,12 @@ def _check_cem_step(op, bc, obs, wl, cem, mu, cov, noise, out, mu_gpu, cov_gpu, 
     np.testing.assert_array_equal(elite, proj[O.select_lowest(caug_g[proj], cem.n_elite)])
     check_selection(pr.resid, proj, cem.n_proj, label=f"{label} proj")
     c_aug = O.trajectory_cost(op, bc, pr.xi_bar, cost) + pr.resid
+    # EliteSet against the oracle's c_aug: among the GPU's constraint-elite
+    # set, the elites must be the n_elite lowest oracle keys wherever those
+    # are separated by more than the tie band
+    pos = {int(s): i for i, s in enumerate(proj)}
+    assert all(int(e) in pos for e in elite), f"{label}: an elite outside the constraint-elite set"
+    check_selection(c_aug[proj], [pos[int(e)] for e in elite], cem.n_elite, label=f"{label} elite")
     # c1 of the GPU's own projected samples
     c1_o = O.trajectory_cost(op, bc, xb_g, cost)
     np.testing.assert_allclose(c1_g, c1_o, rtol=2e-3, atol=2e-3 * max(1.0, np.abs(c1_o).mean()))

@@ -85,3 +85,50 @@ def test_plan_with_cma_update_improves_and_carries_the_path():
                         st1.c_aug[st1.elite_idx], prm.sigma, prm.gamma)
     np.testing.assert_allclose(again[2], st1.pc, atol=1e-12)
     np.testing.assert_allclose(again[1], st1.Sigma, atol=1e-12)
+
+
+def test_rates_asymptotics():
+    """The default rates pinned by their limits rather than by retyping them:
+    c_c ~ 4/n, c_1 ~ 2/n^2 and c_mu ~ 2 (mu_eff - 2 + 1/mu_eff)/n^2 for large
+    n; c_1 + c_mu <= 1 always, tending to 1 as mu_eff grows (the rank-mu
+    update then replaces the old covariance).  A dropped square, a swapped
+    rate or a missing min() fails one of these."""
+    for mu_eff in (1.0, 3.0, 12.5):
+        n = 1e6
+        cc, c1, cmu = O.cma_rates(n, mu_eff)
+        assert cc * n == pytest.approx(4.0, rel=1e-4)
+        assert c1 * n * n == pytest.approx(2.0, rel=1e-4)
+        assert cmu * n * n == pytest.approx(2.0 * (mu_eff - 2.0 + 1.0 / mu_eff), rel=1e-4, abs=1e-9)
+    for n in (2, 6, 22, 33):
+        for mu_eff in (1.0, 2.0, 7.3, 50.0, 1e3):
+            cc, c1, cmu = O.cma_rates(n, mu_eff)
+            assert 0.0 < cc < 1.0 and 0.0 < c1 < 1.0 and 0.0 <= cmu
+            assert c1 + cmu <= 1.0 + 1e-15
+        _, c1, cmu = O.cma_rates(n, 1e9)
+        assert c1 + cmu == pytest.approx(1.0, abs=1e-6)
+
+
+def test_evolution_path_is_stationary_under_random_selection():
+    """With elites drawn from N(mu, Sigma) independently of their costs (no
+    selection pressure) the path's normalisation sqrt(c_c (2 - c_c) mu_eff)
+    keeps it distributed as N(0, Sigma): the stationary covariance of
+    p' = (1 - c_c) p + sqrt(c_c (2 - c_c) mu_eff) y_w is exactly Sigma."""
+    rng = np.random.default_rng(7)
+    D, M = 3, 6
+    B = np.array([[1.0, 0.0, 0.0], [0.4, 0.8, 0.0], [-0.3, 0.2, 0.5]])
+    S = B @ B.T
+    mu = np.array([1.0, -2.0, 0.5])
+    pc = np.zeros(D)
+    acc = np.zeros((D, D))
+    n_burn, n_keep = 200, 6000
+    for it in range(n_burn + n_keep):
+        el = mu + rng.normal(0.0, 1.0, (M, D)) @ B.T
+        _, _, pc = O.refit_cma(mu, S, pc, el, np.zeros(M), 0.0, 1.0)
+        if it >= n_burn:
+            acc += np.outer(pc, pc)
+    emp = acc / n_keep
+    # successive paths are correlated (1 - c_c ~ 0.5 here): a loose bound
+    np.testing.assert_allclose(emp, S, atol=0.12)
+    # a path normalised by sqrt(mu_eff) only (c_c dropped) would be off by ~1.4x
+    cc, _, _ = O.cma_rates(D, float(M))
+    assert abs(cc * (2 - cc) - 1.0) > 0.2

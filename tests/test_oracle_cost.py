@@ -14,15 +14,49 @@ def _prob(dims, K=41, T=4.0, nc=11):
 
 
 def _coeffs(poly_per_axis, T, nc):
-    """Bernstein coefficients of x_d(t) = sum_j c_j t^j (j <= 2) on [0, T]:
-    t = T tau, and tau^0, tau^1, tau^2 have coefficients 1, i/n, i(i-1)/(n(n-1))."""
+    """Bernstein coefficients of x_d(t) = sum_j c_j t^j on [0, T] (j <= nc-1):
+    t = T tau, and the monomial tau^j has the Bernstein coefficients
+    C(i, j) / C(n, j), i = 0..n (the textbook degree-elevation identity)."""
     n = nc - 1
-    i = np.arange(nc, dtype=np.float64)
-    basis = [np.ones(nc), i / n, i * (i - 1) / (n * (n - 1))]
     out = []
     for cs in poly_per_axis:
-        out.append(sum(c * T ** j * basis[j] for j, c in enumerate(cs)))
+        row = np.zeros(nc)
+        for j, c in enumerate(cs):
+            row += c * T ** j * np.array([math.comb(i, j) / math.comb(n, j) for i in range(nc)])
+        out.append(row)
     return np.concatenate(out)
+
+
+def test_smoothness_cost_closed_forms():
+    """c1 = sum_k ||a_k||^2 (Sec. V-A) on trajectories whose acceleration is
+    known exactly: a parabola x_d = c_d t^2 has a constant acceleration 2 c_d,
+    so c1 = K * sum_d 4 c_d^2; a cubic x = c t^3 has a = 6 c t, so
+    c1 = 36 c^2 sum_k t_k^2.  Catches ||a|| written for ||a||^2, a constant
+    factor, a dropped axis and a wrong time grid, none of which an invariance
+    or a comparison with itself would."""
+    T, K = 5.0, 37
+    for dims in (2, 3):
+        prob = O.Problem(dims=dims, n_coeff=11, n_steps=K, horizon=T, n_obs=0)
+        cs = [0.35, -1.2, 0.8][:dims]
+        # linear and constant parts add nothing
+        xi = _coeffs([(1.0 + d, 0.5 - d, c) for d, c in enumerate(cs)], T, 11)[None]
+        want = K * sum(4.0 * c * c for c in cs)
+        np.testing.assert_allclose(O.smoothness_cost(prob, xi), [want], rtol=1e-10)
+        np.testing.assert_allclose(O.trajectory_cost(prob, np.zeros((dims, 6)), xi), [want],
+                                   rtol=1e-10)
+        np.testing.assert_allclose(
+            O.trajectory_cost(prob, np.zeros((dims, 6)), xi, O.Cost(kind=1, w_acc=1.0)), [want],
+            rtol=1e-10)
+    prob = O.Problem(dims=2, n_coeff=11, n_steps=K, horizon=T, n_obs=0)
+    c = 0.07
+    xi = _coeffs([(0.0, 0.0, 0.0, c), (2.0, 1.0, 0.0, 0.0)], T, 11)[None]
+    t = O.time_grid(K, T)
+    np.testing.assert_allclose(O.smoothness_cost(prob, xi), [36.0 * c * c * np.sum(t * t)],
+                               rtol=1e-10)
+    # two samples at once: the cost is per sample
+    both = np.concatenate([xi, 2.0 * xi])
+    np.testing.assert_allclose(O.smoothness_cost(prob, both),
+                               36.0 * c * c * np.sum(t * t) * np.array([1.0, 4.0]), rtol=1e-10)
 
 
 def test_parabola_curvature_and_steering_closed_form():
