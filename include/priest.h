@@ -253,6 +253,27 @@ int32_t priest_plan(priest_problem* p, const float* bc, const float* obs,
                     const priest_plan_out* out, void* workspace, size_t workspace_bytes,
                     void* stream);
 
+/* priest_plan for callers that cannot allocate device memory - code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc:
+ * the same plan, on the same kernels, with its workspace taken from a static
+ * device array of the library (PRIEST_STATIC_WORKSPACE_BYTES per GPU, held
+ * until the process ends) instead of a caller buffer.  It calls no
+ * hipMalloc / hipFree and never synchronises: no autotuning (the tile shape
+ * is a forced or already tuned one for this shape, else the default, so the
+ * result equals priest_plan's bit for bit), no profiling events or pair
+ * counting.  Every call on one GPU shares that GPU's array and leaves the
+ * last call's contents in it: calls that overlap on one GPU (on different
+ * streams, or from several host threads) race and must be serialised by the
+ * caller.  Arguments and outputs as priest_plan.  Errors: INVALID, NOMEM
+ * (the plan needs more than PRIEST_STATIC_WORKSPACE_BYTES, which no plan of
+ * n_samples <= 8192 and D <= 48 does), DEVICE (the array's address could not
+ * be looked up on this device when the problem was built). */
+#define PRIEST_STATIC_WORKSPACE_BYTES (2u << 20)
+int32_t priest_plan_static(priest_problem* p, const float* bc, const float* obs,
+                           const priest_cem_params* c, float* mu, float* cov,
+                           uint64_t seed, uint32_t stream_id, const float* noise,
+                           const priest_plan_out* out, void* stream);
+
 /* Alg. 1 for n_problems independent problems of the same shape, every CEM
  * step batched over all problems in one launch (the 3D batched workload).
  * Arrays are stacked per problem: bc [P][dims][6], obs [P][n_obs][8],

@@ -18,6 +18,15 @@
 
 using namespace priest;
 
+// Workspace of priest_plan_static: one array per GPU, held until the
+// process ends.  Its size covers the largest single-problem plan
+// (n_samples 8192, D = 48 needs 1.57 MiB).  In host code `scratch` is only a
+// stand-in for the device symbol: kernels and copies take the per-device
+// address that hipGetSymbolAddress returns (static_scratch_ptr).
+constexpr size_t kStaticWorkspaceBytes = size_t(2) << 20;
+static_assert(kStaticWorkspaceBytes == PRIEST_STATIC_WORKSPACE_BYTES, "header and library disagree");
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -77,6 +86,42 @@ bool stream_capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
   return st != hipStreamCaptureStatusNone;
+}
+
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+  std::mutex mu;
+  void* ptr[kMaxDevices] = {};
+  hipError_t err[kMaxDevices] = {};
+  bool looked_up[kMaxDevices] = {};
+};
+StaticScratch& static_scratch() {
+  static StaticScratch* s = new StaticScratch();  // lives until exit
+  return *s;
+}
+
+// Looks up this device's copy of `scratch` once; `dev` must be current.
+void static_scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  StaticScratch& ss = static_scratch();
+  std::lock_guard<std::mutex> lk(ss.mu);
+  if (ss.looked_up[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  ss.looked_up[dev] = true;
+  ss.err[dev] = e;
+  ss.ptr[dev] = (e == hipSuccess) ? ptr : nullptr;
+}
+
+// This device's address of `scratch` (null if the lookup failed or never ran).
+void* static_scratch_ptr(int dev, hipError_t* err) {
+  *err = hipErrorInvalidDevice;
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  StaticScratch& ss = static_scratch();
+  std::lock_guard<std::mutex> lk(ss.mu);
+  if (!ss.looked_up[dev]) return nullptr;
+  *err = ss.err[dev];
+  return ss.ptr[dev];
 }
 
 }  // namespace
@@ -355,9 +400,11 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
   return pa;
 }
 
-// Enqueues n_cem CEM iterations for n_problems problems.
+// Enqueues n_cem CEM iterations for n_problems problems.  instrument: the
+// projection launches may carry the profiler's events and pair counter
+// (false: plain launches that create nothing).
 int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const float* noise,
-                     const priest_plan_out* out, hipStream_t s) {
+                     const priest_plan_out* out, hipStream_t s, bool instrument = true) {
   ProjArgs a = pa.a;
   CemArgs ca = pa.ca;
   const int D = ca.D, N = ca.N;
@@ -372,7 +419,8 @@ int32_t enqueue_plan(int32_t P, PlanArgs pa, const priest_cem_params* c, const f
     a.resid2 = last ? out->resid : nullptr;
     a.c12 = last ? out->c1 : nullptr;
     a.xi_out2 = last ? out->xi_bar : nullptr;
-    HIP_TRY(launch_project_timed(a, P, s));
+    if (instrument) HIP_TRY(launch_project_timed(a, P, s));
+    else HIP_TRY(launch_project(a, P, s));
     ca.first = (l == 0) ? 1 : 0;
     // the selection outputs describe the last iteration; without the ordered
     // constraint-elite set the refit selects without sorting
@@ -495,6 +543,7 @@ int32_t priest_init_problem(const priest_problem_desc* desc, void* stream, pries
     if ((d.bc_mask >> i) & 1) p->rowsel[E++] = i;
   p->E = E;
   HIP_TRY(hipGetDevice(&p->device));
+  static_scratch_setup(p->device);  // priest_plan_static's workspace on this device
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
   p->lds_limit = prop.sharedMemPerBlock;
@@ -858,6 +907,44 @@ int32_t priest_plan(priest_problem* p, const float* bc, const float* obs,
                     void* workspace, size_t workspace_bytes, void* stream) {
   return plan_common(p, 1, bc, obs, c, mu, cov, seed, stream_id, noise, out, workspace,
                      workspace_bytes, 0, stream);
+}
+
+int32_t priest_plan_static(priest_problem* p, const float* bc, const float* obs,
+                           const priest_cem_params* c, float* mu, float* cov, uint64_t seed,
+                           uint32_t stream_id, const float* noise, const priest_plan_out* out,
+                           void* stream) {
+  if (!p) return fail(PRIEST_ERR_INVALID, "problem is NULL");
+  int32_t st = validate_cem(c, p->desc.dims);
+  if (st != PRIEST_OK) return st;
+  if (!bc || !mu || !cov || !out || !out->best_xi || !out->best_cost)
+    return fail(PRIEST_ERR_INVALID, "bc, mu, cov, out->best_xi and out->best_cost are required");
+  if (p->desc.n_obs > 0 && !obs) return fail(PRIEST_ERR_INVALID, "obs is required when n_obs > 0");
+  size_t need = 0;
+  priest_plan_workspace_size(p, c, 1, &need);
+  if (need > kStaticWorkspaceBytes)
+    return fail(PRIEST_ERR_NOMEM, "plan needs %zu bytes of workspace, the static one has %zu", need,
+                kStaticWorkspaceBytes);
+  if (cem_lds_bytes(c->n_samples, p->D, c->n_elite) > p->lds_limit)
+    return fail(PRIEST_ERR_INVALID, "n_samples too large for the selection kernel");
+  hipError_t e = hipSuccess;
+  void* ws = static_scratch_ptr(p->device, &e);
+  if (!ws)
+    return fail(PRIEST_ERR_DEVICE, "static workspace of device %d unavailable: %s", p->device,
+                hipGetErrorString(e));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanArgs pa = plan_args(p, 1, bc, obs, c, mu, cov, seed, stream_id, noise, out,
+                          static_cast<char*>(ws));
+  // no autotuning (it synchronises and creates timing events): a forced or
+  // already tuned shape, else the default one
+  TileCfg cfg{};
+  st = check_lds(p, pa.a);
+  if (st != PRIEST_OK) return st;
+  st = resolve_tiling(p, pa.a, 1, s, nullptr, &cfg);
+  if (st != PRIEST_OK) return st;
+  apply_tiling(pa.a, cfg);
+  st = check_lds(p, pa.a);
+  if (st != PRIEST_OK) return st;
+  return enqueue_plan(1, pa, c, noise, out, s, false);
 }
 
 int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc,

@@ -42,7 +42,7 @@ EXPORTS = (
     "priest_profile_enable", "priest_profile_read", "priest_project_unfused_workspace_size",
     "priest_project_unfused", "priest_plan_dpriest", "priest_profile_count_pairs",
     "priest_profile_read_pairs", "priest_project_hist", "priest_project_batch",
-    "priest_debug_select",
+    "priest_debug_select", "priest_plan_static",
 )
 
 WARM_RESET, WARM_KEEP, WARM_KEEP_MEAN = 0, 1, 2
@@ -168,6 +168,8 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_size_t)]),
     "priest_plan": (_I, [_P, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
                          ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P, ctypes.c_size_t, _P]),
+    "priest_plan_static": (_I, [_P, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
+                                ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P]),
     "priest_plan_batch": (_I, [_P, _I, _P, _P, ctypes.POINTER(CemParams), _P, _P, ctypes.c_uint64,
                                ctypes.c_uint32, _P, ctypes.POINTER(PlanOut), _P, ctypes.c_size_t,
                                _I, _P]),
@@ -303,6 +305,14 @@ def priest_plan(handle, bc, obs, params: CemParams, mu, cov, seed, stream_id, no
     _check(lib().priest_plan(handle, _ptr(bc), _ptr(obs), ctypes.byref(params), _ptr(mu), _ptr(cov),
                              seed, stream_id, _ptr(noise), ctypes.byref(po),
                              _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def priest_plan_static(handle, bc, obs, params: CemParams, mu, cov, seed, stream_id, noise,
+                       out: dict, stream=None):
+    po = _plan_out(out)
+    _check(lib().priest_plan_static(handle, _ptr(bc), _ptr(obs), ctypes.byref(params), _ptr(mu),
+                                    _ptr(cov), seed, stream_id, _ptr(noise), ctypes.byref(po),
+                                    _stream(stream)))
 
 
 def priest_plan_batch(handle, n_problems, bc, obs, params: CemParams, mu, cov, seed, stream_base,

@@ -71,3 +71,13 @@ def test_calls_reject_null_handles(P):
     assert L.priest_free_problem(None) == 0
     assert L.priest_debug_normals(0, 0, 0, 4, 0, None, None) == -1
     assert L.priest_problem_dim(None) == 0
+
+
+def test_plan_static_rejects_on_host(P):
+    """The allocation-free plan validates on the host like priest_plan."""
+    L = P.lib()
+    prm = P.CemParams(64, 1, 10, 47, 12, 0, 0.5, 1.0, 1e-5, 0.0)
+    po = P.PlanOut()
+    assert L.priest_plan_static(None, None, None, ctypes.byref(prm), None, None, 0, 0, None,
+                                ctypes.byref(po), None) == -1
+    assert L.priest_last_error()
