@@ -2,23 +2,26 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-One step = one full plan (Alg. 1) of the paper-scale 2D workload: N = 1000
-samples, 20 CEM iterations of 100 projection iterations each, M = 50
-circular obstacles (30 static, 20 constant-velocity), K = 100 steps, FP32,
-every sub-step (draw, project, residual, cost, top-k twice, refit,
-Cholesky) on the GPU.  Inputs are resident in HBM before the timed region.
+One step = one batched plan (Alg. 1) of the 3D workload: 64 independent
+planning problems with distinct scenes, each N = 2000 samples, M = 128
+spherical obstacles, K = 100 steps, 20 CEM iterations of 100 projection
+iterations, FP32; every CEM step of all 64 problems runs as one projection
+launch and one selection / refit launch, the whole CEM loop captured once in
+a hipGraph and replayed, the projection's tile shape picked by the
+autotuner.  Every sub-step (draw, project, residual, cost, top-k twice,
+refit, Cholesky) runs on the GPU; inputs are resident in HBM before the
+timed region.
 
 Prints one JSON line: the metric is projected samples x iterations per
-second (N * n_proj_iters * n_cem per plan), plus plans/s and per-plan
+second (64 * N * n_proj_iters * n_cem per step), plus plans/s and per-step
 latency percentiles, the roofline position of the projection kernel (its
 launches timed by events that each launch stamps, over a second timed region
-of the same plans, since those events lengthen the gaps between kernels; the
-metric comes from the first, uninstrumented region) and the FP64 CPU oracle
-timed on a bounded sample of the same
-workload.  Extra sections compare the systems patterns with the plain
-one-problem-per-launch FP32 form: batched problems with graph-captured CEM
-loops and autotuned tile shapes (2D x64 and 3D x64), BF16 mixed precision,
-and the continuous-batching server.
+of the same plans without the graph, since those events need launches
+outside capture; the metric comes from the first, graph-replayed region) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.  Extra
+sections: the plain one-problem-per-launch FP32 form of the same 64 problems,
+the single 2D paper-scale plan, 2D batched x64, BF16 mixed precision, the
+unfused baseline, D-PRIEST and the continuous-batching server.
 """
 from __future__ import annotations
 
@@ -36,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector / MFMA peak
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_kernel_c2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_kernel_c3_traffic.txt")
 KERNEL_SOURCES = ("paper_2309_08235_amd/csrc/project.hip", "paper_2309_08235_amd/csrc/priest_internal.h")
 
 
@@ -95,11 +98,15 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(wl, n_sample: int, gpu_results=None):
-    """The FP64 oracle on `n_sample` samples of the same workload (one
-    projection of n_proj_iters iterations), in projected samples x iters/s.
-    `gpu_results` maps a label to GPU-projected samples of the same inputs
-    (first rows); their per-result error against this oracle run is returned."""
+def cpu_baseline(wl, n_sample: int, gpu_results=None, extra=None):
+    """The FP64 oracle on `n_sample` samples of problem 0 of workload `wl`
+    (one projection of n_proj_iters iterations), in projected samples x
+    iters/s, with the host's math libraries on all their threads and then
+    held to one thread (a quarter of the sample).  `gpu_results` maps a label
+    to GPU-projected samples of the same inputs (first rows); their error
+    against this oracle run is returned.  `extra` maps a label to
+    (workload, n, {label: gpu samples}) for further error checks of other
+    workloads (not timed)."""
     import oracle as O
     from paper_2309_08235_amd import workloads as W
     try:
@@ -107,9 +114,29 @@ def cpu_baseline(wl, n_sample: int, gpu_results=None):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = 1
+
+    def oracle_problem(w):
+        return O.Problem(w.dims, w.n_coeff, w.n_steps, w.horizon, w.n_obs, w.rho, w.v_max,
+                         w.a_max, w.bc_mask)
+
+    def errors_of(pr, results, n):
+        errors = {}
+        for label, (xb, r) in (results or {}).items():
+            xb = np.asarray(xb, np.float64)[:n]
+            r = np.asarray(r, np.float64)[:n]
+            e = np.abs(xb - pr.xi_bar).max(1) / np.maximum(1.0, np.abs(pr.xi_bar).max(1))
+            er = np.abs(r - pr.resid)
+            errors[label] = {"coeff_rel_median": float(np.median(e)),
+                             "coeff_rel_p99": float(np.quantile(e, 0.99)),
+                             "coeff_rel_max": float(e.max()),
+                             "samples_above_1e-3": int(np.sum(e > 1e-3)),
+                             "resid_abs_median": float(np.median(er)),
+                             "resid_abs_max": float(er.max()),
+                             "samples": int(n)}
+        return errors
+
     bc, obs = W.scene(wl, 0)
-    prob = O.Problem(wl.dims, wl.n_coeff, wl.n_steps, wl.horizon, wl.n_obs, wl.rho, wl.v_max,
-                     wl.a_max, wl.bc_mask)
+    prob = oracle_problem(wl)
     xi = W.samples(wl, 5, n=n_sample)
     t0 = time.perf_counter()
     pr = O.project(prob, bc, obs, xi, wl.n_proj_iters)
@@ -127,21 +154,17 @@ def cpu_baseline(wl, n_sample: int, gpu_results=None):
                       "sample": f"{n1} samples x {wl.n_proj_iters} projection iterations, {dt1:.1f} s"}
     except ImportError:
         one_thread = None
-    errors = {}
-    for label, (xb, r) in (gpu_results or {}).items():
-        xb = np.asarray(xb, np.float64)[:n_sample]
-        r = np.asarray(r, np.float64)[:n_sample]
-        e = np.abs(xb - pr.xi_bar).max(1) / np.maximum(1.0, np.abs(pr.xi_bar).max(1))
-        er = np.abs(r - pr.resid)
-        errors[label] = {"coeff_rel_median": float(np.median(e)),
-                         "coeff_rel_p99": float(np.quantile(e, 0.99)),
-                         "coeff_rel_max": float(e.max()),
-                         "resid_abs_median": float(np.median(er)),
-                         "resid_abs_max": float(er.max())}
+    errors = {wl.name: errors_of(pr, gpu_results, n_sample)}
+    for label, (w2, n2, res2) in (extra or {}).items():
+        b2, o2 = W.scene(w2, 0)
+        p2 = O.project(oracle_problem(w2), b2, o2, W.samples(w2, 5, n=n2), w2.n_proj_iters)
+        errors[label] = errors_of(p2, res2, n2)
     return {"value": n_sample * wl.n_proj_iters / dt, "unit": "projected samples*iters/s",
             "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_sample} samples x {wl.n_proj_iters} projection iterations of the "
-                      f"{wl.name} scene (one CEM iteration's projection), FP64 NumPy, {dt:.1f} s",
+            "sample": f"{n_sample} samples x {wl.n_proj_iters} projection iterations of problem 0 "
+                      f"of {wl.name} (part of one CEM iteration's projection; the projection is "
+                      f"independent per sample, so the rate extrapolates to the whole batch), "
+                      f"FP64 NumPy, {dt:.1f} s",
             "one_thread": one_thread, "host": host_cpu(),
             "gpu_error_vs_oracle": errors}
 
@@ -159,28 +182,37 @@ def host_cpu():
     return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
 
+def mfma_flops(dims: int, nv: int, K: int) -> float:
+    """FLOPs of the three dense products of one projection iteration for one
+    sample, unpadded: forward rows W xi_bar (3 dims nv K FMA), right-hand
+    side W^T delta (the same) and the KKT product (dims nv^2 FMA)."""
+    return 12 * dims * nv * K + 2 * dims * nv * nv
+
+
 def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note, pairs_per_launch):
     """Roofline of the fused projection kernel.  The work per launch is the
     dense part (per sample and iteration, plus the forward rows of the final
     residual pass) and the obstacle pairs the kernel evaluated, counted on
     the device (pairs dropped by culling contribute exact zeros and are not
-    work the kernel does).  The brute-force figure, every pair at every step,
-    is reported beside it."""
+    work the kernel does).  mfma_useful_* is the share of the three dense
+    products alone (their unpadded flops) against the FP32 matrix peak."""
     n, it = n_samples_per_launch, wl.n_proj_iters
-    dense = dense_flops(wl.dims, wl.n_coeff, wl.n_steps) * n * it + \
-        6 * wl.dims * wl.n_coeff * wl.n_steps * n
+    fwd = 6 * wl.dims * wl.n_coeff * wl.n_steps * n
+    dense = dense_flops(wl.dims, wl.n_coeff, wl.n_steps) * n * it + fwd
     flops = dense + pair_flops(wl.dims) * pairs_per_launch
-    brute = projection_flops(wl.dims, wl.n_coeff, wl.n_steps, wl.n_obs) * n * it
+    useful = mfma_flops(wl.dims, wl.n_coeff, wl.n_steps) * n * it + fwd
     all_pairs = n * wl.n_steps * wl.n_obs * (it + 1)
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    mfma = useful / (avg_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "kernel": f"project_kernel<{wl.dims}D, tiling {tuple(tiling)}>",
             "kernel_ms": round(avg_ms, 4), "launches": launches,
             "flops_per_launch": flops, "pairs_evaluated_per_launch": pairs_per_launch,
             "pairs_evaluated_frac": round(pairs_per_launch / all_pairs, 5) if all_pairs else None,
-            "brute_force_flops_per_launch": brute,
-            "brute_force_equiv_tflops": round(brute / (avg_ms * 1e-3) / 1e12, 3),
+            "mfma_useful_flops_per_launch": useful,
+            "mfma_useful_tflops": round(mfma, 3),
+            "mfma_useful_frac": round(mfma / PEAK_FP32_TFLOPS, 4),
             "timing": note}
 
 
@@ -414,15 +446,248 @@ def serving(P, W, n_requests: int, plain_limit_s: float):
                           f"{plain_limit_s} s if behind"}
 
 
+def headline_c3(P, W, args):
+    """The metric: K graph-replayed batched plans of the 3D workload (64
+    problems x 2000 samples), then the same plans without the graph with
+    every projection launch timed by its own events, then once more with the
+    device's pair counter on.  Every step resets (mu, Sigma) and uses the
+    same seed, so every step does identical work."""
+    import torch
+    dev = "cuda:0"
+    wl = W.C3
+    nP = wl.n_problems
+    prob = P.Problem.from_workload(wl)
+    if args.tiling:
+        prob.set_tiling(tuple(int(v) for v in args.tiling.split(",")))
+    scenes = [W.scene(wl, q) for q in range(nP)]
+    bc = torch.tensor(np.stack([sc[0] for sc in scenes]), dtype=torch.float32, device=dev)
+    obs = torch.tensor(np.stack([sc[1] for sc in scenes]), dtype=torch.float32, device=dev)
+    mu0 = torch.tensor(np.stack([W.initial_mean(wl)] * nP), dtype=torch.float32, device=dev)
+    cov0 = torch.tensor(np.stack([W.initial_cov(wl)] * nP), dtype=torch.float32, device=dev)
+    cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
+                n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
+                cov_jitter=wl.cov_jitter)
+    mu, cov = mu0.clone(), cov0.clone()
+    out = prob.plan_outputs(cem, nP, full=False)
+    ws = prob.workspace(cem, nP)
+    s = torch.cuda.Stream()
+
+    def step(graph=True):
+        mu.copy_(mu0)
+        cov.copy_(cov0)
+        prob.plan_batch(nP, bc, obs, cem, mu, cov, seed=77, stream_base=0, out=out, workspace=ws,
+                        use_graph=graph, stream=s)
+
+    with torch.cuda.stream(s):
+        for _ in range(max(1, args.warmup)):   # the first also tunes the tile shape and captures
+            step()
+        s.synchronize()
+        tiling = prob.last_tiling()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(s)
+            step()
+            ev[i][1].record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        # the same plans launched outside the graph, each projection launch
+        # timed by events that the launch itself stamps
+        P.priest_profile_read()
+        P.priest_profile_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(graph=False)
+        torch.cuda.synchronize()
+        wall_instr = time.perf_counter() - t1
+        P.priest_profile_enable(False)
+        n_launch, k_total_ms = P.priest_profile_read()
+        # evaluated obstacle pairs of one more identical plan
+        P.priest_profile_count_pairs(True)
+        step(graph=False)
+        pairs = P.priest_profile_read_pairs()
+        P.priest_profile_count_pairs(False)
+    status = out["status"].cpu().numpy()
+    best = out["best_cost"].cpu().numpy()
+    assert np.all(status == 0) and np.all(np.isfinite(best)), (status, best)
+    assert n_launch == args.steps * wl.n_cem, n_launch
+    work = nP * wl.n_samples * wl.n_proj_iters * wl.n_cem
+    roof = roofline_entry(wl, nP * wl.n_samples, k_total_ms / n_launch, n_launch, tiling[0],
+                          "HIP events stamped by every projection launch (hipExtLaunchKernel) over "
+                          "a second timed region of the same batched plans launched without the "
+                          "graph; its wall time is instrumented_ms_per_step", pairs / wl.n_cem)
+    roof["instrumented_ms_per_step"] = round(wall_instr / args.steps * 1e3, 3)
+    roof["traffic"] = measured_traffic()
+    roof["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE "
+                            "(profiles/project_kernel_c3_traffic.txt), null if the kernel sources "
+                            "changed since")
+    # plain form: one problem per launch, no graph, default tile shape, on
+    # plain_problems of the 64 problems (scaled to the batch)
+    prob.set_tiling((4, 1, 0))
+    out1 = prob.plan_outputs(cem, 1, full=False)
+    ws1 = prob.workspace(cem, 1)
+    m, c = mu0[0].clone(), cov0[0].clone()
+    prob.plan(bc[0], obs[0], cem, m, c, seed=77, stream_id=0, out=out1, workspace=ws1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(args.plain_problems):
+        m, c = mu0[q].clone(), cov0[q].clone()
+        prob.plan(bc[q], obs[q], cem, m, c, seed=77, stream_id=q, out=out1, workspace=ws1)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.plain_problems * nP
+    # standalone projection of fresh samples of problem 0 (for the oracle's
+    # error check in the CPU baseline leg)
+    xi = torch.tensor(W.samples(wl, 5), dtype=torch.float32, device=dev)
+    xo, r, _ = prob.project(bc[0], obs[0], xi, wl.n_proj_iters)
+    torch.cuda.synchronize()
+    prob.close()
+    return {
+        "wall": wall, "lat": lat, "work": work, "roofline": roof, "tiling": tiling,
+        "plain": {"s_per_batch_equivalent": round(t_plain, 4),
+                  "samples_iters_per_s": round(work / t_plain, 1),
+                  "plans_per_s": round(nP / t_plain, 2),
+                  "timed_problems": args.plain_problems,
+                  "speedup_of_batched_graph": round(t_plain / (wall / args.steps), 3)},
+        "gpu_samples": {"fp32": (xo.cpu().numpy(), r.cpu().numpy())},
+    }
+
+
+def single_plan_c2(P, W, args):
+    """The 2D paper-scale single plan (N = 1000, M = 50 incl. 20 moving, K =
+    100, 100 x 20 iterations), one problem per call: plan time, its
+    projection kernel's roofline, a standalone projection of fresh samples,
+    and the BF16 mixed-precision projection of the same samples."""
+    import torch
+    dev = "cuda:0"
+    wl = W.C2
+    prob = P.Problem.from_workload(wl)
+    bc_h, obs_h = W.scene(wl, 0)
+    bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
+    obs = torch.tensor(obs_h, dtype=torch.float32, device=dev)
+    D = prob.D
+    # (mu, Sigma) in one buffer, so that resetting them before a plan is one copy
+    state0 = torch.cat([torch.tensor(W.initial_mean(wl), dtype=torch.float32).reshape(-1),
+                        torch.tensor(W.initial_cov(wl), dtype=torch.float32).reshape(-1)]).to(dev)
+    state = state0.clone()
+    mu, cov = state[:D], state[D:].view(D, D)
+    cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
+                n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
+                cov_jitter=wl.cov_jitter)
+    out = prob.plan_outputs(cem, full=False)
+    ws = prob.workspace(cem)
+    stream = torch.cuda.current_stream()
+    steps = args.c2_steps
+
+    def step(i):
+        state.copy_(state0)
+        prob.plan(bc, obs, cem, mu, cov, seed=1234 + i, stream_id=0, out=out, workspace=ws)
+
+    for i in range(3):                 # the first plan also runs the autotuner
+        step(i)
+    torch.cuda.synchronize()
+    tiling = prob.last_tiling()
+
+    def timed(kernel_events):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        if kernel_events:
+            P.priest_profile_read()
+            P.priest_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ev[i][0].record(stream)
+            step(3 + i)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        prof = (0, 0.0)
+        if kernel_events:
+            P.priest_profile_enable(False)
+            prof = P.priest_profile_read()
+        return w, np.array([a.elapsed_time(b) for a, b in ev]), prof
+
+    wall, lat, _ = timed(False)
+    wall_instr, _, (n_launch, k_total_ms) = timed(True)
+    P.priest_profile_count_pairs(True)
+    for i in range(steps):
+        step(3 + i)
+    pairs_total = P.priest_profile_read_pairs()
+    P.priest_profile_count_pairs(False)
+    assert int(out["status"][0].item()) == 0 and np.isfinite(float(out["best_cost"][0].item()))
+    assert n_launch == steps * wl.n_cem, n_launch
+    per_plan = wl.n_samples * wl.n_proj_iters * wl.n_cem
+    roof = roofline_entry(wl, wl.n_samples, k_total_ms / n_launch, n_launch, tiling[0],
+                          "HIP events stamped by every projection launch over a second timed "
+                          "region of the same plans", pairs_total / n_launch)
+    roof["instrumented_ms_per_step"] = round(wall_instr / steps * 1e3, 4)
+    # standalone projection of fresh samples at the same shape
+    xi = torch.tensor(W.samples(wl, 5), dtype=torch.float32, device=dev)
+    xo = torch.empty_like(xi)
+    r = torch.empty(wl.n_samples, device=dev)
+    c1 = torch.empty(wl.n_samples, device=dev)
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+    torch.cuda.synchronize()
+    ka.record(stream)
+    for _ in range(args.kernel_reps):
+        P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
+    kb.record(stream)
+    torch.cuda.synchronize()
+    k_ms = round(ka.elapsed_time(kb) / args.kernel_reps, 4)
+    samples = {"fp32": (xo.cpu().numpy(), r.cpu().numpy())}
+    mixed = None
+    if not args.no_mixed:
+        # BF16 operands for the right-hand side and a BF16 hi/lo KKT product,
+        # last 10 iterations in FP32
+        prob_bf = P.Problem.from_workload(wl, precision=P.BF16_MIXED, n_refine_fp32=10)
+        xo_bf = torch.empty_like(xi)
+        r_bf = torch.empty(wl.n_samples, device=dev)
+        for _ in range(3):
+            P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
+        torch.cuda.synchronize()
+        ka.record(stream)
+        for _ in range(args.kernel_reps):
+            P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
+        kb.record(stream)
+        torch.cuda.synchronize()
+        samples["bf16_mixed"] = (xo_bf.cpu().numpy(), r_bf.cpu().numpy())
+        mixed = {"kernel_ms_fp32": k_ms,
+                 "kernel_ms_bf16_mixed": round(ka.elapsed_time(kb) / args.kernel_reps, 4),
+                 "n_refine_fp32": 10,
+                 "note": "BF16 operands for W^T(e - F xi) and a BF16 hi/lo split of M11 u, "
+                         "FP32 accumulation; errors vs the FP64 oracle in "
+                         "cpu_baseline.gpu_error_vs_oracle.c2_fp32_and_bf16"}
+        prob_bf.close()
+    prob.close()
+    return {
+        "section": {"workload": wl.name, "samples_iters_per_s": round(per_plan * steps / wall, 1),
+                    "ms_per_plan": round(wall * 1e3 / steps, 4),
+                    "plans_per_sec": round(steps / wall, 3),
+                    "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                   "p99": round(float(np.percentile(lat, 99)), 4)},
+                    "tiling": {"shape": list(tiling[0]), "from_autotuner": tiling[1]},
+                    "roofline": roof, "kernel_standalone_ms": k_ms, "plans": steps},
+        "mixed": mixed, "samples": samples, "wl": wl,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--c2-steps", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--cpu-sample", type=int, default=400)
+    ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched comparisons")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary sections")
+    ap.add_argument("--no-c2", action="store_true", help="skip the single 2D plan section")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision section")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--plain-problems", type=int, default=8)
@@ -431,10 +696,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--only-unfused", action="store_true",
                     help="run only the unfused-baseline section (profiling runs)")
-    ap.add_argument("--no-standalone", action="store_true",
-                    help="skip the standalone projection launches (profiling runs)")
     ap.add_argument("--tiling", type=str, default=None,
-                    help="axis_slots,row_tiles,persistent for the headline plan (default: autotuned)")
+                    help="axis_slots,row_tiles,persistent for the headline plans (default: autotuned)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -461,159 +724,41 @@ def main():
         print(json.dumps({"unfused_baseline": unfused_baseline(P, W, reps=2)}), flush=True)
         return
 
-    wl = W.C2
-    dev = "cuda:0"
-    torch.cuda.set_device(0)
-    prob = P.Problem.from_workload(wl)
-    bc_h, obs_h = W.scene(wl, 0)
-    bc = torch.tensor(bc_h, dtype=torch.float32, device=dev)
-    obs = torch.tensor(obs_h, dtype=torch.float32, device=dev)
-    # (mu, Sigma) in one buffer, so that resetting them before a plan is one copy
-    D = prob.D
-    state0 = torch.cat([torch.tensor(W.initial_mean(wl), dtype=torch.float32).reshape(-1),
-                        torch.tensor(W.initial_cov(wl), dtype=torch.float32).reshape(-1)]).to(dev)
-    state = state0.clone()
-    mu, cov = state[:D], state[D:].view(D, D)
-    cem = P.Cem(n_samples=wl.n_samples, n_cem=wl.n_cem, n_proj_iters=wl.n_proj_iters,
-                n_proj=wl.n_proj, n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma,
-                cov_jitter=wl.cov_jitter)
-    if args.tiling:
-        prob.set_tiling(tuple(int(v) for v in args.tiling.split(",")))
-    out = prob.plan_outputs(cem, full=False)
-    ws = prob.workspace(cem)
-    stream = torch.cuda.current_stream()
+    h = headline_c3(P, W, args)
+    wl = W.C3
+    print(f"[bench] headline done: {h['wall'] / args.steps * 1e3:.2f} ms per step", file=sys.stderr,
+          flush=True)
 
-    def step(i):
-        state.copy_(state0)
-        prob.plan(bc, obs, cem, mu, cov, seed=1234 + i, stream_id=0, out=out, workspace=ws)
+    c2 = None
+    if not args.no_c2:
+        c2 = single_plan_c2(P, W, args)
+        print("[bench] single 2D plan done", file=sys.stderr, flush=True)
 
-    for i in range(args.warmup):       # the first plan also runs the autotuner
-        step(i)
-    torch.cuda.synchronize()
-    tiling = prob.last_tiling()
-    def timed(kernel_events):
-        """The K timed plans (the same draws every time): wall time, per-plan
-        latencies from events around each plan and, with kernel_events, the
-        count and summed duration of the projection launches, each timed by
-        events that the launch itself stamps."""
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-        if kernel_events:
-            P.priest_profile_read()
-            P.priest_profile_enable(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            ev[i][0].record(stream)
-            step(args.warmup + i)
-            ev[i][1].record(stream)
-        torch.cuda.synchronize()
-        w = time.perf_counter() - t0
-        prof = (0, 0.0)
-        if kernel_events:
-            P.priest_profile_enable(False)
-            prof = P.priest_profile_read()
-        return w, np.array([a.elapsed_time(b) for a, b in ev]), prof
-
-    # the metric: the plans with nothing on the stream but one event pair per
-    # plan; the roofline: the same plans again with every projection launch
-    # timed, whose events add about 2.5 us per launch to the stream
-    wall, lat, _ = timed(False)
-    wall_instr, _, (n_launch, k_total_ms) = timed(True)
-    # evaluated obstacle pairs of the same plans, re-run outside the timed
-    # region with the same draws (the work is deterministic)
-    P.priest_profile_count_pairs(True)
-    for i in range(args.steps):
-        step(args.warmup + i)
-    pairs_total = P.priest_profile_read_pairs()
-    P.priest_profile_count_pairs(False)
-    status = int(out["status"][0].item())
-    best = float(out["best_cost"][0].item())
-    assert status == 0 and np.isfinite(best), (status, best)
-    assert n_launch == args.steps * wl.n_cem, n_launch
-
-    per_plan = wl.n_samples * wl.n_proj_iters * wl.n_cem
-    value = per_plan * args.steps / wall
-    roofline = roofline_entry(wl, wl.n_samples, k_total_ms / n_launch, n_launch, tiling[0],
-                              "HIP events stamped by every projection launch (hipExtLaunchKernel) "
-                              "over a second timed region of the same plans, whose wall time is "
-                              "instrumented_ms_per_step", pairs_total / n_launch)
-    roofline["instrumented_ms_per_step"] = round(wall_instr / args.steps * 1e3, 4)
-    roofline["traffic"] = measured_traffic()
-    roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE "
-                                "(profiles/project_kernel_c2_traffic.txt), null if the kernel "
-                                "changed since")
-
-    if args.no_standalone:
-        args.no_mixed = True
-    # standalone projection of fresh samples at the same shape (the samples
-    # inside a plan concentrate over the CEM iterations, so launches differ)
-    xi = torch.tensor(W.samples(wl, 5), dtype=torch.float32, device=dev)
-    xo = torch.empty_like(xi)
-    r = torch.empty(wl.n_samples, device=dev)
-    c1 = torch.empty(wl.n_samples, device=dev)
-    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k_ms = None
-    gpu_results = {}
-    if not args.no_standalone:
-        for _ in range(3):
-            P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
-        torch.cuda.synchronize()
-        ka.record(stream)
-        for _ in range(args.kernel_reps):
-            P.priest_project(prob.handle, bc, obs, xi, wl.n_proj_iters, xo, r, c1)
-        kb.record(stream)
-        torch.cuda.synchronize()
-        k_ms = round(ka.elapsed_time(kb) / args.kernel_reps, 4)
-        gpu_results["fp32"] = (xo.cpu().numpy(), r.cpu().numpy())
-
-    mixed = None
-    if not args.no_mixed:
-        # BF16 operands for the right-hand side and a BF16 hi/lo KKT product,
-        # last 10 iterations in FP32
-        prob_bf = P.Problem.from_workload(wl, precision=P.BF16_MIXED, n_refine_fp32=10)
-        xo_bf = torch.empty_like(xi)
-        r_bf = torch.empty(wl.n_samples, device=dev)
-        for _ in range(3):
-            P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
-        torch.cuda.synchronize()
-        ka.record(stream)
-        for _ in range(args.kernel_reps):
-            P.priest_project(prob_bf.handle, bc, obs, xi, wl.n_proj_iters, xo_bf, r_bf, c1)
-        kb.record(stream)
-        torch.cuda.synchronize()
-        k_ms_bf = ka.elapsed_time(kb) / args.kernel_reps
-        gpu_results["bf16_mixed"] = (xo_bf.cpu().numpy(), r_bf.cpu().numpy())
-        mixed = {"kernel_ms_fp32": k_ms, "kernel_ms_bf16_mixed": round(k_ms_bf, 4),
-                 "n_refine_fp32": 10,
-                 "note": "BF16 operands for W^T(e - F xi) and a BF16 hi/lo split of M11 u, "
-                         "FP32 accumulation; errors vs the FP64 oracle in "
-                         "cpu_baseline.gpu_error_vs_oracle"}
-        prob_bf.close()
-
-    extra_2d = extra_3d = None
+    extra_2d = unfused = dpr = None
     if not args.no_extra:
         extra_2d = batched(P, W, W.with_changes(W.C2, name="c2x64_2d_k100_n1000_m50", n_problems=64),
                            args.batch_steps, args.plain_problems)
-        extra_3d = batched(P, W, W.C3, args.batch_steps, args.plain_problems)
-
-    unfused = None
-    dpr = None
-    if not args.no_extra:
         unfused = unfused_baseline(P, W, reps=3)
         dpr = dpriest_section(P, W, reps=5)
+        print("[bench] secondary sections done", file=sys.stderr, flush=True)
 
     serve_line = None
     if not args.no_serve:
         serve_line = serving(P, W, args.serve_requests, args.serve_plain_limit)
+        print("[bench] serving done", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_sample, gpu_results)
+        extra = None
+        if c2 is not None:
+            extra = {"c2_fp32_and_bf16": (c2["wl"], 100, c2["samples"])}
+        cpu = cpu_baseline(wl, args.cpu_sample, h["gpu_samples"], extra)
+        cpu["value"] = round(cpu["value"], 2)
 
+    wall = h["wall"]
     line = {
         "metric": "projected samples*iters/s",
-        "value": round(value, 1),
+        "value": round(h["work"] * args.steps / wall, 1),
         "unit": "samples*iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -624,20 +769,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "dims": wl.dims, "n_samples": wl.n_samples,
-                   "n_obs": wl.n_obs, "n_steps": wl.n_steps, "n_coeff": wl.n_coeff,
-                   "n_proj_iters": wl.n_proj_iters, "n_cem": wl.n_cem, "n_proj": wl.n_proj,
-                   "n_elite": wl.n_elite, "parallelism": "single-gpu"},
-        "plans_per_sec": round(args.steps / wall, 3),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4)},
-        "tiling": {"shape": list(tiling[0]), "from_autotuner": tiling[1]},
-        "roofline": roofline,
-        "kernel_standalone_ms": k_ms,
+        "config": {"workload": wl.name, "dims": wl.dims, "n_problems": wl.n_problems,
+                   "n_samples": wl.n_samples, "n_obs": wl.n_obs, "n_steps": wl.n_steps,
+                   "n_coeff": wl.n_coeff, "n_proj_iters": wl.n_proj_iters, "n_cem": wl.n_cem,
+                   "n_proj": wl.n_proj, "n_elite": wl.n_elite, "hipgraph": True,
+                   "parallelism": "single-gpu"},
+        "plans_per_sec": round(wl.n_problems * args.steps / wall, 3),
+        "latency_ms": {"p50": round(float(np.percentile(h["lat"], 50)), 4),
+                       "p99": round(float(np.percentile(h["lat"], 99)), 4),
+                       "note": "per step; each step completes all 64 plans together"},
+        "tiling": {"shape": list(h["tiling"][0]), "from_autotuner": h["tiling"][1]},
+        "roofline": h["roofline"],
         "cpu_baseline": cpu,
-        "mixed_precision": mixed,
+        "plain_per_problem": h["plain"],
+        "c2_single_plan": c2["section"] if c2 else None,
+        "mixed_precision": c2["mixed"] if c2 else None,
         "batched_2d": extra_2d,
-        "batched_3d": extra_3d,
         "unfused_baseline": unfused,
         "dpriest": dpr,
         "serving": serve_line,
