@@ -295,8 +295,10 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
  * The same projection can be laid out on the GPU in several ways: 4 MFMA
  * columns per sample (4 samples per block) or, in 2D, 2 columns per sample
  * (8 samples per block, two items per lane); one or two 16-step time blocks
- * per wave; one block per tile or a persistent grid of resident blocks that
- * loop over tiles.  Every shape gives bit-identical results.  By default the
+ * per wave, or every time block of the horizon in one wave (blocks of 16
+ * waves, each with its own samples); one block per tile or a persistent grid
+ * of resident blocks that loop over tiles.  Every shape gives bit-identical
+ * results.  By default the
  * library times every candidate the first time a problem handle meets a new
  * (N, n_problems, sampling mode, precision) - one warm-up and two timed
  * launches of a shortened (<= 8 iteration) copy of the real launch, outputs
@@ -309,7 +311,10 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
 typedef struct priest_tiling {
   int32_t axis_slots; /* MFMA columns per sample: 4; 2 (2D only); or 8 (two samples per
                          block, half the lanes idle in the push-out: more blocks for small N) */
-  int32_t row_tiles;  /* 16-step time blocks per wave: 1 or 2 (8 axis slots: 1 only) */
+  int32_t row_tiles;  /* 16-step time blocks per wave: 1 or 2 (8 axis slots: 1 only); or 0:
+                         each wave carries its samples over the whole horizon (4 axis slots,
+                         or 2 in 2D; n_steps <= 128), no block barrier per iteration: for
+                         batches large enough to fill the chip */
   int32_t persistent; /* 1: grid of resident blocks looping over tiles */
   int32_t reserved;   /* must be 0 */
 } priest_tiling;

@@ -396,7 +396,7 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
   a.xi_src_stride = static_cast<int64_t>(N) * D;
   a.cost = CostArgs{c->cost.kind, c->cost.w_acc, c->cost.w_curv, c->cost.w_path,
                     c->cost.w_steer, c->cost.wheelbase, c->cost.eps};
-  apply_tiling(a, tile_candidates(a.dims)[0]);
+  apply_tiling(a, tile_candidates(a.dims, a.K)[0]);
   return pa;
 }
 
@@ -447,7 +447,7 @@ bool tiling_cached(priest_problem* p, const ProjArgs& a, int P) {
 int32_t resolve_tiling(priest_problem* p, const ProjArgs& a, int P, hipStream_t s,
                        const ProjArgs* trial, TileCfg* out) {
   std::lock_guard<std::mutex> lk(p->tune_mu);
-  const std::vector<TileCfg> cands = tile_candidates(a.dims);
+  const std::vector<TileCfg> cands = tile_candidates(a.dims, a.K);
   p->last_tuned = 0;
   if (p->forced) {
     *out = p->force_cfg;
@@ -682,7 +682,7 @@ int32_t priest_project(priest_problem* p, const float* bc, const float* obs, con
   a.xi_out = xi_out;
   a.resid = resid;
   a.c1 = c1;
-  apply_tiling(a, tile_candidates(a.dims)[0]);
+  apply_tiling(a, tile_candidates(a.dims, a.K)[0]);
   int32_t st = check_lds(p, a);
   if (st != PRIEST_OK) return st;
   TileCfg cfg{};
@@ -734,7 +734,7 @@ int32_t priest_project_batch(priest_problem* p, int32_t n_problems, const float*
   a.resid = resid;
   a.c1 = c1;
   a.n_stride = N;
-  apply_tiling(a, tile_candidates(a.dims)[0]);
+  apply_tiling(a, tile_candidates(a.dims, a.K)[0]);
   int32_t st = check_lds(p, a);
   if (st != PRIEST_OK) return st;
   TileCfg cfg{};
@@ -781,7 +781,7 @@ int32_t priest_project_hist(priest_problem* p, const float* bc, const float* obs
   a.resid = resid;
   a.c1 = c1;
   a.resid_hist = resid_hist;
-  apply_tiling(a, tile_candidates(a.dims)[0]);  // the default shape
+  apply_tiling(a, tile_candidates(a.dims, a.K)[0]);  // the default shape
   const int32_t st = check_lds(p, a);
   if (st != PRIEST_OK) return st;
   HIP_TRY(launch_project_timed(a, 1, s));
@@ -1025,7 +1025,7 @@ int32_t priest_tiling_candidates(const priest_problem* p, priest_tiling* out, in
                                  int32_t* n) {
   if (!p || !n || max_out < 0 || (max_out > 0 && !out))
     return fail(PRIEST_ERR_INVALID, "problem and n are required");
-  const std::vector<TileCfg> c = tile_candidates(p->desc.dims);
+  const std::vector<TileCfg> c = tile_candidates(p->desc.dims, p->desc.n_steps);
   *n = static_cast<int32_t>(c.size());
   for (int32_t i = 0; i < max_out && i < *n; ++i)
     out[i] = priest_tiling{c[i].axis_slots, c[i].row_tiles, c[i].persistent, 0};
@@ -1044,7 +1044,7 @@ int32_t priest_set_tiling(priest_problem* p, const priest_tiling* t) {
     p->forced = false;
     return PRIEST_OK;
   }
-  if (!tiling_valid(p->desc.dims, t->axis_slots, t->row_tiles) ||
+  if (!tiling_valid(p->desc.dims, t->axis_slots, t->row_tiles, p->desc.n_steps) ||
       (t->persistent != 0 && t->persistent != 1) || t->reserved != 0)
     return fail(PRIEST_ERR_INVALID, "tiling (%d, %d, %d) is not a candidate for dims %d",
                 t->axis_slots, t->row_tiles, t->persistent, p->desc.dims);

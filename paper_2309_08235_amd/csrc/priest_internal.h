@@ -38,11 +38,11 @@ struct CostArgs {
 
 struct ProjArgs {
   int32_t dims, nv, K, M, N;
-  int32_t S;                   // samples per block = 16 / axis_slots
+  int32_t S;                   // samples per block: 16 / axis_slots (x 16 waves for row_tiles 0)
   int32_t n_iter;              // projection iterations
   int32_t blocks_per_problem;  // ceil(N / S)
   int32_t axis_slots;          // MFMA columns per sample: 4, or 2 (2D only)
-  int32_t row_tiles;           // 16-step time blocks per wave: 1 or 2
+  int32_t row_tiles;           // 16-step time blocks per wave: 1 or 2; 0: the whole horizon
   int32_t persistent;          // 1: grid of resident blocks looping over tiles
   int32_t mode;                // SampleMode
   int32_t bf16_iters;          // leading iterations with BF16 MFMA operands (mixed precision)
@@ -117,8 +117,9 @@ struct CemTaskLaunch {
 hipError_t launch_project_tasks(const ProjTaskLaunch& t, hipStream_t s);
 hipError_t launch_cem_tasks(const CemTaskLaunch& t, hipStream_t s);
 size_t project_lds_bytes(const ProjArgs& a);
-bool tiling_valid(int dims, int axis_slots, int row_tiles);
-int samples_per_block(int axis_slots);
+// row_tiles 0: one wave owns a sample group over the whole horizon (K <= 128)
+bool tiling_valid(int dims, int axis_slots, int row_tiles, int K);
+int samples_per_block(const ProjArgs& a);  // from a's tile shape and problem size
 int project_threads(int K, int row_tiles);
 void set_default_tiling(ProjArgs& a);  // 4 axis slots, 1 time block per wave, not persistent
 // start / stop: optional events that receive the kernel's own start and end
@@ -140,7 +141,7 @@ hipError_t launch_debug_normals(uint64_t seed, uint32_t stream_id, int iter, int
 struct TileCfg {
   int axis_slots, row_tiles, persistent;
 };
-std::vector<TileCfg> tile_candidates(int dims);  // [0] is the default shape
+std::vector<TileCfg> tile_candidates(int dims, int K);  // [0] is the default shape
 void apply_tiling(ProjArgs& a, const TileCfg& t);
 // Times every candidate on `trial` (whose outputs must be safe to overwrite);
 // ms[i] < 0 marks a candidate that does not fit.  Synchronises s.

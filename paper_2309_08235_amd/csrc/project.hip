@@ -487,14 +487,15 @@ constexpr int kRegGroups = 2;
 // valid, and the candidate and moving bits of the first kRegGroups groups of
 // 64 obstacles (wave-uniform).  Masks of later groups live in LDS (4 words
 // per group).
-template <int NI, int DIMS>
+template <int NI, int DIMS, int REG = kRegGroups>
 struct CullCache {
   float pref[NI][DIMS];
   float lim2;
   bool valid;
   uint32_t nok;    // valid items of the wave (wave-uniform)
   uint32_t pairs;  // (item, obstacle) pairs evaluated by the wave so far
-  unsigned long long cm[kRegGroups], mv[kRegGroups];
+  bool rebuilt;    // the last call built new candidate sets
+  unsigned long long cm[REG > 0 ? REG : 1], mv[REG > 0 ? REG : 1];
 };
 
 // Growth of the candidate radius that lets a candidate set be reused: an
@@ -512,12 +513,12 @@ constexpr float kSlack = PRIEST_CULL_SLACK;
 // wave-level culling.  tmid / thalf: centre and half-width of the wave's time
 // window.  Candidates are added in one canonical order: per group of 64, the
 // static obstacles by index, then the moving ones by index.
-template <int DIMS, bool LAST, int NI, bool HIST = false, bool TRAJ = false>
+template <int DIMS, bool LAST, int NI, bool HIST = false, bool TRAJ = false, int REG = kRegGroups>
 __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const float tt[NI],
                                                 const float tmid[4], const float thalf[4],
                                                 const bool ok[NI],
                                                 const float p[NI][DIMS], float S[NI][DIMS],
-                                                float r2[NI], int lane, CullCache<NI, DIMS>& cc,
+                                                float r2[NI], int lane, CullCache<NI, DIMS, REG>& cc,
                                                 uint32_t* wm, const float* opath = nullptr,
                                                 const int* tstep = nullptr, int K = 0) {
   // records of the first group, issued before anything waits on LDS
@@ -549,6 +550,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     }
     reuse = __ballot(far) == 0ull;
   }
+  cc.rebuilt = !reuse;
   if (!reuse) {
     // one box per row of 16 lanes (the items of 4 time steps): an obstacle is
     // a candidate if it may come near any of the four
@@ -593,7 +595,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       moving = __ballot(cand && mv);
     };
 #pragma unroll
-    for (int g = 0; g < kRegGroups; ++g) {
+    for (int g = 0; g < REG; ++g) {
       cc.cm[g] = 0ull;
       cc.mv[g] = 0ull;
       if (64 * g < M) {
@@ -603,7 +605,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
         cull_group(g, R0, R1, cc.cm[g], cc.mv[g]);
       }
     }
-    for (int g = kRegGroups; 64 * g < M; ++g) {
+    for (int g = REG; 64 * g < M; ++g) {
       const int j = 64 * g + lane;
       unsigned long long mask, moving;
       cull_group(g, rec[clampj(j)], rec[M + clampj(j)], mask, moving);
@@ -621,7 +623,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
 #pragma unroll
       for (int x = 0; x < DIMS; ++x) cc.pref[i][x] = p[i][x];
     cc.valid = true;
-    if (M > 64 * kRegGroups) wave_lds_sync();
+    if (M > 64 * REG) wave_lds_sync();
   }
   uint32_t ncand = 0;
   // the candidates of one group, kCandUnroll at a time (their offsets and
@@ -680,7 +682,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     run(mvmask, std::true_type{});
   };
 #pragma unroll
-  for (int g = 0; g < kRegGroups; ++g) {
+  for (int g = 0; g < REG; ++g) {
     const unsigned long long cmask = cc.cm[g];
     ncand += static_cast<uint32_t>(__builtin_popcountll(cmask));
     if (!cmask) continue;
@@ -691,7 +693,7 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
       group(64 * g, cmask, cc.mv[g], rec[clampj(j)], rec[M + clampj(j)], rec[2 * M + clampj(j)]);
     }
   }
-  for (int g = kRegGroups; 64 * g < M; ++g) {
+  for (int g = REG; 64 * g < M; ++g) {
     const uint4 m4 = *reinterpret_cast<const uint4*>(wm + 4 * g);
     // (readfirstlane returns int: widen through uint32_t, not sign-extended)
     auto u64 = [](uint32_t lo, uint32_t hi) {
@@ -716,14 +718,14 @@ __device__ __forceinline__ void obstacle_pushes(const float4* rec, int M, const 
     }
 }
 
-template <int DIMS, bool LAST, int NI, bool HIST = false, bool TRAJ = false>
+template <int DIMS, bool LAST, int NI, bool HIST = false, bool TRAJ = false, int REG = kRegGroups>
 __device__ __forceinline__ void item_push(const float4* rec, int M, const float tt[NI],
                                           const float tmid[4], const float thalf[4],
                                           const bool ok[NI], const float p[NI][DIMS],
                                           const float v[NI][DIMS], const float ac[NI][DIMS],
                                           float vmax, float amax, const Box& box,
                                           float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS],
-                                          float r2[NI], int lane, CullCache<NI, DIMS>& cc,
+                                          float r2[NI], int lane, CullCache<NI, DIMS, REG>& cc,
                                           uint32_t* wm, const float* opath = nullptr,
                                           const int* tstep = nullptr, int K = 0) {
 #pragma unroll
@@ -732,8 +734,8 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
     for (int x = 0; x < DIMS; ++x) { S[i][x] = 0.0f; dv[i][x] = 0.0f; da[i][x] = 0.0f; }
     r2[i] = 0.0f;
   }
-  obstacle_pushes<DIMS, LAST, NI, HIST, TRAJ>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc, wm,
-                                               opath, tstep, K);
+  obstacle_pushes<DIMS, LAST, NI, HIST, TRAJ, REG>(rec, M, tt, tmid, thalf, ok, p, S, r2, lane, cc,
+                                                    wm, opath, tstep, K);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (ok[i]) {
@@ -1242,6 +1244,637 @@ __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* task
                                               tasks[lo].blocks_per_problem);
 }
 
+// ---------------------------------------------------------------------------
+// Whole-horizon tile shape (row_tiles = 0).  A wave owns 16/AS samples for
+// every time step: per projection iteration it walks the 16-step time blocks
+// of the horizon one after another, so the sum of the right-hand side over
+// time stays inside the wave and no iteration needs a block barrier, a
+// cross-wave partial sum or a KKT step repeated by every wave.  The waves of
+// a block share only read-only tables in LDS (obstacle records and the W
+// operands of every time block), so on a SIMD they drift out of step and
+// the matrix core of one wave overlaps the vector work of another.
+//
+// Forward rows are computed with the sample coefficients as the MFMA A
+// operand and the W rows as B (D = xi_bar W^T): lane l then holds time step
+// l % 16 of columns 4 (l / 16) + 0..3, i.e. every axis of its (sample, t)
+// items, with no transpose.  The right-hand side needs the time steps
+// spread over lane groups (they are the reduction index), so the push-outs
+// go back to the column layout through one LDS pass per time block: each
+// item lane writes its four column values to four planes, and each column
+// lane reads its four time steps from one plane with a 16-byte read.
+//
+// Each time block keeps its obstacle candidate cache (the item positions it
+// was built from, the candidate masks, a valid flag) in the wave's LDS
+// region between iterations, so the block loop needs no registers per
+// block and is not unrolled.
+//
+// The arithmetic per sample is that of the time-split shape: the same
+// product chains per 16-step block (operands swapped in the forward rows,
+// the same products in the same order), the per-block partial right-hand
+// sides summed in the same pairwise tree over 8 slots, the same push-out,
+// multiplier and KKT steps, and the residual and cost summed in t order.
+// ---------------------------------------------------------------------------
+constexpr int kWaveMaxBlocks = 8;  // 16-step time blocks (n_steps <= 128)
+constexpr int kPlane = 68;         // floats per transpose plane: 64 lanes + 4 (conflict-free reads)
+constexpr int kWtabV4 = 6;         // float4 per lane and time block in the W table
+
+struct WaveLayout {  // offsets into dynamic LDS, in floats
+  int rec, wtab, wave, wave_floats, cache, cstride, stage, total;
+};
+
+// rec: obstacle records; wtab: per time block and lane the 12 forward-row B
+// operands (rows P, Pdot, Pddot x 4 coefficient chunks) and the 12
+// right-hand-side A operands (row types x 4 time chunks); wave: per wave 12
+// transpose planes (3 quantities x 4 column residues), then per time block
+// its candidate cache: word 0 = 1 + number of candidates (0: none yet),
+// words 4..35 the box of each row of 16 lanes grown by the reuse slack
+// (low corner, high corner as float4), then 4 mask words per obstacle group
+// (static, moving; 64 bits each); stage: sampler staging of the block's
+// samples, aliasing the wave regions (used before any wave iterates).
+__host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int NB, int WPB, int SPW,
+                                                  int mode) {
+  WaveLayout l{};
+  const int D = dims * nv, D4 = round4(D), G = (M + 63) / 64, SPB = WPB * SPW;
+  int o = 0;
+  l.rec = o;  o += 12 * M;
+  l.wtab = o; o += NB * kWtabV4 * 64 * 4;
+  l.cache = 12 * kPlane;
+  l.cstride = 36 + 4 * G;
+  l.wave_floats = round4(l.cache + NB * l.cstride);
+  l.wave = o; o += WPB * l.wave_floats;
+  l.stage = l.wave;
+  int stage = SPB * D4;
+  if (mode != kFromInput) stage += D4 + round4(D * D) + SPB * D4;
+  if (l.stage + stage > o) o = l.stage + stage;
+  l.total = o;
+  return l;
+}
+
+// Minimum / maximum over each row of 16 lanes, left in every lane of the row.
+__device__ __forceinline__ float row16_min(float v) {
+  v = fminf(v, dpp<0xB1>(v));
+  v = fminf(v, dpp<0x4E>(v));
+  v = fminf(v, dpp<0x124>(v));
+  return fminf(v, dpp<0x128>(v));
+}
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x124>(v));
+  return fmaxf(v, dpp<0x128>(v));
+}
+
+// Builds the candidate cache of one 16-step block of the whole-horizon
+// shape.  Each row of 16 lanes (one or two samples over the block's steps)
+// gets the bounding box of its valid items; an obstacle is a candidate if its
+// sphere, grown by sqrt(DIMS) * slack and by |v| * (half window) for a moving
+// obstacle (centre taken at the window's middle), comes near any row's box.
+// The cache stays valid while every valid item lies in its row's box grown
+// by `slack` per axis: such an item is at most sqrt(DIMS) * slack from the
+// box, so a skipped obstacle stays farther than its cull radius (a * 1.001 +
+// 1e-4 beyond the surface) from every item, where the push-out is exactly
+// zero.  Writes the grown boxes, the masks and the state word; returns the
+// candidate count.
+template <int DIMS, int NI>
+__device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, const float p[NI][DIMS],
+                                                    const bool ok[NI], float tmid, float thalf,
+                                                    float slack, int lane, uint32_t* cw) {
+  float lo[DIMS], hi[DIMS];
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x) {
+    float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      mn = fminf(mn, ok[i] ? p[i][x] : INFINITY);
+      mx = fmaxf(mx, ok[i] ? p[i][x] : -INFINITY);
+    }
+    lo[x] = row16_min(mn);
+    hi[x] = row16_max(mx);
+  }
+  if ((lane & 15) == 0) {
+    float* bx = reinterpret_cast<float*>(cw) + 4 + 8 * (lane >> 4);
+    *reinterpret_cast<float4*>(bx) = make_float4(lo[0] - slack, lo[1] - slack,
+                                                 DIMS == 3 ? lo[DIMS - 1] - slack : 0.0f, 0.0f);
+    *reinterpret_cast<float4*>(bx + 4) = make_float4(hi[0] + slack, hi[1] + slack,
+                                                     DIMS == 3 ? hi[DIMS - 1] + slack : 0.0f, 0.0f);
+  }
+  float blo[DIMS][4], bhi[DIMS][4];
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      blo[x][q] = lane_f(lo[x], 16 * q);
+      bhi[x][q] = lane_f(hi[x], 16 * q);
+    }
+  const float grow = (DIMS == 3 ? 1.7320508f : 1.4142136f) * slack * 1.0001f;
+  uint32_t ncand = 0;
+  uint32_t* masks = cw + 36;
+  for (int g = 0; 64 * g < M; ++g) {
+    const int j = 64 * g + lane;
+    const int jc = j < M ? j : M - 1;
+    const float4 R0 = rec[jc], R1 = rec[M + jc];
+    const float oc[3] = {fmaf(R1.x, tmid, R0.x), fmaf(R1.y, tmid, R0.y), fmaf(R1.z, tmid, R0.z)};
+    const float rr = fmaf(R1.w, thalf, R0.w + grow);
+    bool cand = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) {
+        const float e = fmaxf(fmaxf(blo[x][q] - oc[x], oc[x] - bhi[x][q]), 0.0f);
+        d2 = fmaf(e, e, d2);
+      }
+      cand = cand || (d2 < rr * rr);
+    }
+    cand = cand && (j < M);
+    const unsigned long long mask = __ballot(cand), moving = __ballot(cand && R1.w != 0.0f);
+    if (lane == 0) {
+      *reinterpret_cast<uint4*>(masks + 4 * g) =
+          make_uint4(static_cast<uint32_t>(mask), static_cast<uint32_t>(mask >> 32),
+                     static_cast<uint32_t>(moving), static_cast<uint32_t>(moving >> 32));
+    }
+    ncand += static_cast<uint32_t>(__builtin_popcountll(mask));
+  }
+  if (lane == 0) cw[0] = 1u + ncand;
+  wave_lds_sync();
+  return ncand;
+}
+
+// Push-outs of this lane's items in one 16-step block of the whole-horizon
+// shape (the per-pair and per-bound arithmetic of item_push, in the same
+// canonical obstacle order), with the block's candidate cache in LDS.
+// Items that are not valid still get finite push-outs, which the caller
+// masks where they matter (steps past the horizon meet zero W rows in the
+// right-hand side; columns of absent samples are never written out).
+template <int DIMS, bool LAST, int NI>
+__device__ __forceinline__ void wave_block_push(const float4* rec, int M, float tt, float tmid, float thalf,
+                                                float slack, const bool ok[NI], const float p[NI][DIMS],
+                                                const float v[NI][DIMS], const float ac[NI][DIMS],
+                                                float vmax, float amax, const Box& box, float S[NI][DIMS],
+                                                float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
+                                                int lane, uint32_t* cw, uint32_t nok, uint32_t& pairs) {
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) S[i][x] = 0.0f;
+    r2[i] = 0.0f;
+  }
+  // reuse test: every valid item inside its row's grown box
+  const uint32_t state = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(cw[0]));
+  uint32_t ncand = state - 1u;
+  bool rebuild = state == 0u;
+  if (!rebuild) {
+    const float* bx = reinterpret_cast<const float*>(cw) + 4 + 8 * (lane >> 4);
+    const float4 glo = *reinterpret_cast<const float4*>(bx);
+    const float4 ghi = *reinterpret_cast<const float4*>(bx + 4);
+    const float gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
+    bool out = false;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) {
+        const int xx = (DIMS == 3 || x < 2) ? x : 2;
+        out = out || (ok[i] && !(p[i][x] >= gl[xx] && p[i][x] <= gh[xx]));
+      }
+    rebuild = __ballot(out) != 0ull;
+  }
+  if (rebuild) ncand = wave_block_cull<DIMS, NI>(rec, M, p, ok, tmid, thalf, slack, lane, cw);
+  if (ncand) {
+    pairs += ncand * nok;
+    const uint32_t* masks = cw + 36;
+    float tt_[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) tt_[i] = tt;
+    for (int g = 0; 64 * g < M; ++g) {
+      const uint4 m4 = *reinterpret_cast<const uint4*>(masks + 4 * g);
+      auto u64 = [](uint32_t lo, uint32_t hi) {
+        return static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo))) |
+               (static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi))) << 32);
+      };
+      const unsigned long long cmask = u64(m4.x, m4.y);
+      if (!cmask) continue;
+      const unsigned long long mvmask = u64(m4.z, m4.w);
+      const int j = 64 * g + lane;
+      const int jc = j < M ? j : M - 1;
+      const float4 R0 = rec[jc], R1 = rec[M + jc], R2 = rec[2 * M + jc];
+      unsigned long long ms = cmask & ~mvmask;
+      while (ms) {
+        const Rec o = rec_of_lane<DIMS, false>(R0, R1, R2, __builtin_ctzll(ms));
+        ms &= ms - 1;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, false>(o, tt_[i], p[i]), S[i], r2[i]);
+      }
+      unsigned long long mm = mvmask;
+      while (mm) {
+        const Rec o = rec_of_lane<DIMS, true>(R0, R1, R2, __builtin_ctzll(mm));
+        mm &= mm - 1;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, true>(o, tt_[i], p[i]), S[i], r2[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const float rv = bound_push<DIMS>(v[i], vmax, dv[i]);
+    const float ra = bound_push<DIMS>(ac[i], amax, da[i]);
+    if (LAST) {
+      r2[i] += rv;
+      r2[i] += ra;
+    }
+  }
+  if (box.on) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) {
+        const float e = fminf(fmaxf(p[i][x], box.lo[x]), box.hi[x]) - p[i][x];
+        S[i][x] += e;
+        if (LAST) r2[i] = fmaf(e, e, r2[i]);
+      }
+  }
+}
+
+template <int DIMS, int AS, bool BF16>
+__device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first, int stride, int total) {
+  static_assert(AS == 4 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
+  constexpr int SPW = 16 / AS;  // samples per wave
+  constexpr int NI = 4 / AS;    // items per lane and time block
+  extern __shared__ float4 sm4[];
+  float* sm = reinterpret_cast<float*>(sm4);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, WPB = blockDim.x >> 6;
+  const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv, D4 = round4(D);
+  const int NB = (K + 15) >> 4, G = (M + 63) >> 6, SPB = WPB * SPW;
+  const WaveLayout l = wave_layout(DIMS, nv, M, NB, WPB, SPW, a.mode);
+  // column layout (MFMA state): col = AS * cs + cx, coefficient rows 4 q + r;
+  // item layout (forward rows, push-outs): step ti of columns 4 q + 0..3
+  const int q = lane >> 4, col = lane & 15, cs = col / AS, cx = col % AS, ti = lane & 15;
+  float4* rec = reinterpret_cast<float4*>(sm + l.rec);
+  const float4* wtab = reinterpret_cast<const float4*>(sm + l.wtab);
+  float* wr = sm + l.wave + w * l.wave_floats;
+  uint32_t* cwords = reinterpret_cast<uint32_t*>(wr + l.cache);
+  const int cstride = l.cstride;  // cache words per time block
+
+  // W operands of every time block, once per block
+  {
+    float4* wt = reinterpret_cast<float4*>(sm + l.wtab);
+    for (int e = tid; e < NB * kWtabV4 * 64; e += blockDim.x) {
+      const int ll = e & 63, i = (e >> 6) % kWtabV4, tb = (e >> 6) / kWtabV4;
+      float v[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int j = 4 * i + h;
+        int t, d, c;
+        if (j < 12) {  // forward B operand: W[t][d][coefficient of chunk j % 4, row ll / 16]
+          d = j >> 2;
+          t = 16 * tb + (ll & 15);
+          c = coef_of(ll >> 4, j & 3);
+        } else {       // right-hand-side A operand: W[t][d][coefficient of column ll % 16]
+          const int jj = j - 12;
+          d = jj >> 2;
+          t = 16 * tb + 4 * (ll >> 4) + (jj & 3);
+          c = coef_of((ll & 15) >> 2, ll & 3);
+        }
+        v[h] = (t < K && c < nv) ? a.W[(t * 3 + d) * nv + c] : 0.0f;
+      }
+      wt[e] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  float Am[4];
+  const int crow = coef_of(col >> 2, col & 3);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ck = coef_of(q, r);
+    Am[r] = (crow < nv && ck < nv) ? a.M11[crow * nv + ck] : 0.0f;
+  }
+  s4 Mhi, Mlo;
+  if constexpr (BF16) {
+    Mhi = pack_bf16(Am[0], Am[1], Am[2], Am[3]);
+    Mlo = pack_bf16(Am[0] - from_bf16(Mhi[0]), Am[1] - from_bf16(Mhi[1]),
+                    Am[2] - from_bf16(Mhi[2]), Am[3] - from_bf16(Mhi[3]));
+  }
+  const bool chunk3 = nv > 12;
+  const float rho = a.rho;
+  const f4 zf = {0.0f, 0.0f, 0.0f, 0.0f};
+  // half the time window of a 16-step block
+  const float thalf = a.dt * 7.5f;
+
+  int cur_prob = -1;
+  for (int tile = first; tile < total; tile += stride) {
+    const int prob = tile / a.blocks_per_problem;
+    const int s0 = (tile - prob * a.blocks_per_problem) * SPB;
+    const int ns = min(SPB, a.N - s0);
+    const int sw0 = w * SPW;  // this wave's first sample in the tile
+    const int nsw = max(0, min(SPW, ns - sw0));
+    // (every reader of the previous tile's records and staging is done)
+    __syncthreads();
+    if (prob != cur_prob) build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
+    cur_prob = prob;
+    float* xs = sm + l.stage;
+    if (a.mode == kFromInput) {
+      const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(s0) * D;
+      for (int i = tid; i < ns * D; i += blockDim.x) xs[(i / D) * D4 + i % D] = src[i];
+    } else {
+      float* sMu = xs + SPB * D4;
+      float* sL = sMu + D4;
+      float* sZ = sL + round4(D * D);
+      const float* mu = a.mu + prob * a.mu_stride;
+      const float* Lm = a.L + prob * a.L_stride;
+      for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
+      for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
+      if (a.mode == kFromNoise) {
+        const float* z = a.noise + prob * a.noise_stride + static_cast<int64_t>(s0) * D;
+        for (int i = tid; i < ns * D; i += blockDim.x) sZ[(i / D) * D4 + i % D] = z[i];
+      } else {
+        const int nq = D4 / 4;
+        const uint32_t stream_id = a.stream_base + static_cast<uint32_t>(prob);
+        for (int i = tid; i < ns * nq; i += blockDim.x) {
+          const int s = i / nq, qq = i - s * nq;
+          float z[4];
+          philox_normals4(a.seed, static_cast<uint32_t>(s0 + s), static_cast<uint32_t>(qq),
+                          static_cast<uint32_t>(a.iter), stream_id, z);
+          *reinterpret_cast<float4*>(sZ + s * D4 + 4 * qq) = make_float4(z[0], z[1], z[2], z[3]);
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < ns * D; i += blockDim.x) {
+        const int s = i / D, d = i - s * D;
+        const float* zz = sZ + s * D4;
+        const float* Lr = sL + d * D;
+        float x = sMu[d];
+        for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
+        xs[s * D4 + d] = x;
+      }
+      __syncthreads();
+      if (a.xi_src) {
+        float* dst = a.xi_src + prob * a.xi_src_stride + static_cast<int64_t>(s0) * D;
+        for (int i = tid; i < ns * D; i += blockDim.x) dst[i] = xs[(i / D) * D4 + i % D];
+      }
+    }
+    __syncthreads();
+    const bool colok = (cx < DIMS) && (cs < nsw);
+    const float* bc = a.bc + prob * a.bc_stride;
+    f4 xi;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = coef_of(q, r);
+      xi[r] = (colok && c < nv) ? xs[(sw0 + cs) * D4 + cx * nv + c] : 0.0f;
+    }
+    // (every wave has its samples: the staging area becomes the waves' regions)
+    __syncthreads();
+    if (nsw == 0) continue;
+
+    // planes of padding columns (axis slots >= DIMS) are read as zeros; no
+    // time block has a candidate cache yet
+    if constexpr (AS == 4) {
+#pragma unroll
+      for (int x = DIMS; x < 4; ++x)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) wr[(d * 4 + x) * kPlane + lane] = 0.0f;
+    }
+    if (lane < NB) cwords[lane * cstride] = 0u;
+    wave_lds_sync();
+    // reuse slack of the candidate caches: the smallest cull radius of the scene
+    float slack = INFINITY;
+    for (int j = lane; j < M; j += 64) slack = fminf(slack, rec[j].w);
+    slack = M > 0 ? wave_min(slack) : 1.0f;
+
+    f4 xb = xi;
+    f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
+    uint32_t pairs = 0;
+
+    // One time block: forward rows p/v/a of columns 4 q + 0..3 at step
+    // 16 tb + ti (item layout), then the push-outs of this lane's items with
+    // the block's candidate cache.
+    auto block_items = [&](int tb, const float4 (&wv)[kWtabV4], auto last_tag, float p[NI][DIMS],
+                           float v[NI][DIMS], float ac[NI][DIMS], float S[NI][DIMS],
+                           float dv[NI][DIMS], float da[NI][DIMS], float r2[NI], bool ok[NI]) {
+      constexpr bool LAST = decltype(last_tag)::value;
+      f4 Y0 = mfma(xb[0], wv[0].x, zf), Y1 = mfma(xb[0], wv[1].x, zf), Y2 = mfma(xb[0], wv[2].x, zf);
+      Y0 = mfma(xb[1], wv[0].y, Y0);
+      Y1 = mfma(xb[1], wv[1].y, Y1);
+      Y2 = mfma(xb[1], wv[2].y, Y2);
+      Y0 = mfma(xb[2], wv[0].z, Y0);
+      Y1 = mfma(xb[2], wv[1].z, Y1);
+      Y2 = mfma(xb[2], wv[2].z, Y2);
+      if (chunk3) {
+        Y0 = mfma(xb[3], wv[0].w, Y0);
+        Y1 = mfma(xb[3], wv[1].w, Y1);
+        Y2 = mfma(xb[3], wv[2].w, Y2);
+      }
+      const int t = 16 * tb + ti;
+      uint32_t nok = 0;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        ok[i] = (t < K) && ((4 * q) / AS + i < nsw);
+        nok += static_cast<uint32_t>(__builtin_popcountll(__ballot(ok[i])));
+#pragma unroll
+        for (int x = 0; x < DIMS; ++x) {
+          p[i][x] = Y0[AS * i + x];
+          v[i][x] = Y1[AS * i + x];
+          ac[i][x] = Y2[AS * i + x];
+        }
+      }
+      const float tmid = a.dt * (static_cast<float>(16 * tb) + 7.5f);
+      wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack, ok, p,
+                                      v, ac, a.vmax, a.amax, a.box, S, dv, da, r2, lane,
+                                      cwords + tb * cstride, nok, pairs);
+    };
+    auto load_w = [&](int tb, float4 (&wv)[kWtabV4], int i0, int i1) {
+#pragma unroll
+      for (int i = 0; i < kWtabV4; ++i)
+        if (i >= i0 && i < i1) wv[i] = wtab[(tb * kWtabV4 + i) * 64 + lane];
+    };
+
+    // ---- projection iterations ---------------------------------------------------
+    for (int k = 0; k < a.n_iter; ++k) {
+      const bool lowp = BF16 && (k < a.bf16_iters);
+      f4 lvl[3] = {zf, zf, zf};
+      f4 g = zf;
+      // per-block partial right-hand sides into the pairwise tree over 8
+      // slots, as a running stack (slots past the horizon hold zeros)
+      auto tree = [&](int b, f4 part) {
+        if (b & 1) {
+          part = lvl[0] + part;
+          if (b & 2) {
+            part = lvl[1] + part;
+            if (b & 4) g = lvl[2] + part;
+            else lvl[2] = part;
+          } else {
+            lvl[1] = part;
+          }
+        } else {
+          lvl[0] = part;
+        }
+      };
+      for (int tb = 0; tb < NB; ++tb) {
+        float4 wv[kWtabV4];
+        load_w(tb, wv, 0, 3);
+        float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+        bool ok[NI];
+        block_items(tb, wv, std::false_type{}, p, v, ac, S, dv, da, r2, ok);
+        load_w(tb, wv, 3, 6);
+        // push-outs to the column layout through the planes
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int x = 0; x < DIMS; ++x) {
+            const int r = AS * i + x;
+            wr[(0 * 4 + r) * kPlane + lane] = S[i][x];
+            wr[(1 * 4 + r) * kPlane + lane] = dv[i][x];
+            wr[(2 * 4 + r) * kPlane + lane] = da[i][x];
+          }
+        wave_lds_sync();
+        f4 B[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
+        wave_lds_sync();
+        f4 part;
+        if (lowp) {
+          f4 gg = zf;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const float4 A4 = wv[3 + d];
+            gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
+                           pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
+          }
+          part = gg;
+        } else {
+          // the two accumulation chains of the time-split shape
+          f4 acc0 = zf, acc1 = zf;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const float4 A4 = wv[3 + d];
+            acc0 = mfma(A4.x, B[d][0], acc0);
+            acc1 = mfma(A4.y, B[d][1], acc1);
+            acc0 = mfma(A4.z, B[d][2], acc0);
+            acc1 = mfma(A4.w, B[d][3], acc1);
+          }
+          part = acc0 + acc1;
+        }
+        tree(tb, part);
+      }
+      for (int tb = NB; tb < kWaveMaxBlocks; ++tb) tree(tb, zf);
+      lam += rho * g;
+      if (k == 0) {
+        // Pi and c0 = M12 b enter the first step only
+        float Ap[4];
+        f4 c0v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = coef_of(q, r);
+          Ap[r] = (crow < nv && c < nv) ? a.Pi[crow * nv + c] : 0.0f;
+          float sacc = 0.0f;
+          if (colok && c < nv)
+            for (int i = 0; i < 6; ++i) sacc = fmaf(a.M12[c * 6 + i], bc[cx * 6 + i], sacc);
+          c0v[r] = sacc;
+        }
+        const f4 u = lam + rho * g;
+        const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
+        f4 h1 = mfma(Ap[2], xi[2], zf);
+        const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], zf));
+        f4 h3 = mfma(Am[2], u[2], zf);
+        if (chunk3) {
+          h1 = mfma(Ap[3], xi[3], h1);
+          h3 = mfma(Am[3], u[3], h3);
+        }
+        xb = (h0 + h1) + (h2 + h3);
+      } else if (lowp) {
+        const f4 u = (xi - xb) + lam + rho * g;
+        const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
+        const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
+                                u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
+        xb = xb + mfma_bf16(Mhi, uh, mfma_bf16(Mlo, uh, mfma_bf16(Mhi, ul, zf)));
+      } else {
+        const f4 u = (xi - xb) + lam + rho * g;
+        xb = mfma(Am[2], u[2], mfma(Am[1], u[1], mfma(Am[0], u[0], xb)));
+        if (chunk3) xb = mfma(Am[3], u[3], xb);
+      }
+    }
+
+    // ---- residual and cost of the returned iterate, summed in t order --------------
+    float sg[DIMS], ug[DIMS], iuu = 0.0f;
+    if (a.cost.kind != 0) {
+      float uu = 0.0f;
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) {
+        sg[x] = bc[x * 6 + 0];
+        ug[x] = bc[x * 6 + 3] - sg[x];
+        uu = fmaf(ug[x], ug[x], uu);
+      }
+      iuu = uu > 0.0f ? 1.0f / uu : 0.0f;
+    }
+    float racc = 0.0f, cacc = 0.0f;
+    for (int tb = 0; tb < NB; ++tb) {
+      float4 wv[kWtabV4];
+      load_w(tb, wv, 0, 3);
+      float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+      bool ok[NI];
+      block_items(tb, wv, std::true_type{}, p, v, ac, S, dv, da, r2, ok);
+      // per-(t, sample) residual^2 and cost through this wave's planes
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        float cc = 0.0f;
+        if (a.cost.kind == 0) {
+#pragma unroll
+          for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[i][x], ac[i][x], cc);
+        } else {
+          cc = weighted_cost<DIMS>(p[i], v[i], ac[i], a.cost, sg, ug, iuu);
+        }
+        float* f = wr + 2 * (ti * SPW + (4 * q) / AS + i);
+        f[0] = ok[i] ? r2[i] : 0.0f;
+        f[1] = ok[i] ? cc : 0.0f;
+      }
+      wave_lds_sync();
+      if (lane < nsw) {
+        const int nt = min(16, K - 16 * tb);
+        for (int t = 0; t < nt; ++t) {
+          const float* f = wr + 2 * (t * SPW + lane);
+          racc += f[0];
+          cacc += f[1];
+        }
+      }
+      wave_lds_sync();
+    }
+    if (lane < nsw) {
+      const int s = s0 + sw0 + lane;
+      const float r = sqrtf(racc);
+      const int64_t nb = prob * a.n_stride + s;
+      const int64_t dense = static_cast<int64_t>(prob) * a.N + s;
+      if (a.resid) a.resid[nb] = r;
+      if (a.c1) a.c1[nb] = cacc;
+      if (a.resid2) a.resid2[dense] = r;
+      if (a.c12) a.c12[dense] = cacc;
+    }
+    if (a.pair_count && lane == 0) atomicAdd(a.pair_count, static_cast<unsigned long long>(pairs));
+    if (colok) {
+      float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0 + sw0 + cs) * D + cx * nv;
+      float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0 + sw0 + cs) * D + cx * nv
+                              : nullptr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = coef_of(q, r);
+        if (c < nv) {
+          dst[c] = xb[r];
+          if (dst2) dst2[c] = xb[r];
+        }
+      }
+    }
+  }
+}
+
+// Whole-horizon shape: one block of blockDim / 64 waves per tile of
+// (blockDim / 64) * 16 / AS samples of one problem; with a grid smaller
+// than `total` (persistent launch) blocks loop over tiles.  XCD-aware block
+// order as project_kernel.
+template <int DIMS, int AS, bool BF16>
+__global__ __launch_bounds__(1024) void project_wave_kernel(ProjArgs a, int total) {
+  const int G = gridDim.x;
+  int lb = blockIdx.x;
+  if ((G & 7) == 0) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  project_wave_block<DIMS, AS, BF16>(a, lb, G, total);
+}
+
 // Per-row push-outs e(xi) - F xi, [N][M + 2][K][dims] (parity hook): one
 // thread per (sample, t), the same record table and per-pair push-out
 // arithmetic as the projection kernel, one obstacle at a time.
@@ -1375,9 +2008,27 @@ hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, h
   return hipGetLastError();
 }
 
+template <int DIMS, int AS, bool BF16>
+hipError_t launch_wave_shape(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s,
+                             KEvents ev) {
+  if (a.persistent) {
+    const void* fn = reinterpret_cast<const void*>(&project_wave_kernel<DIMS, AS, BF16>);
+    const int grid = std::min(total, resident_blocks(fn, threads, lds));
+    launch_k(project_wave_kernel<DIMS, AS, BF16>, dim3(grid), dim3(threads), lds, s, ev, a, total);
+  } else {
+    launch_k(project_wave_kernel<DIMS, AS, BF16>, dim3(total), dim3(threads), lds, s, ev, a, total);
+  }
+  return hipGetLastError();
+}
+
 template <int DIMS, bool BF16>
 hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s,
                        KEvents ev) {
+  if (a.row_tiles == 0) {  // whole-horizon shape (n_steps <= 128, checked by the caller)
+    if constexpr (DIMS == 2)
+      if (a.axis_slots == 2) return launch_wave_shape<DIMS, 2, BF16>(a, total, threads, lds, s, ev);
+    return launch_wave_shape<DIMS, 4, BF16>(a, total, threads, lds, s, ev);
+  }
   if (a.resid_hist || a.traj) {  // default shape only (checked by the caller)
     const dim3 g(total), b(threads);
     if (threads <= 512) {
@@ -1410,39 +2061,76 @@ hipError_t launch_dims(const ProjArgs& a, int total, int threads, size_t lds, hi
 
 }  // namespace
 
-bool tiling_valid(int dims, int axis_slots, int row_tiles) {
+bool tiling_valid(int dims, int axis_slots, int row_tiles, int K) {
   if (axis_slots == 8) return row_tiles == 1;  // 2 samples per block, more blocks for small N
+  if (row_tiles == 0)  // one wave per sample group over the whole horizon
+    return (axis_slots == 4 || (axis_slots == 2 && dims == 2)) && K <= 16 * kWaveMaxBlocks;
   return (axis_slots == 4 || (axis_slots == 2 && dims == 2)) && (row_tiles == 1 || row_tiles == 2);
 }
 
-int samples_per_block(int axis_slots) { return 16 / axis_slots; }
+// Largest dynamic LDS a block may use on the current device (cached).
+size_t device_lds_limit() {
+  static std::mutex mu;
+  static size_t lim[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!lim[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 << 10;
+    lim[dev] = static_cast<size_t>(v);
+  }
+  return lim[dev];
+}
+
+size_t wave_lds_bytes(const ProjArgs& a, int wpb) {
+  return sizeof(float) * static_cast<size_t>(wave_layout(a.dims, a.nv, a.M, (a.K + 15) / 16, wpb,
+                                                         16 / a.axis_slots, a.mode).total);
+}
+
+// Waves per block of the whole-horizon shape: the most (16, 12, 8 or 4)
+// whose LDS (the block's W table and records, a region per wave) fits.
+int wave_block_waves(const ProjArgs& a) {
+  const size_t limit = device_lds_limit();
+  for (int wpb : {16, 12, 8}) 
+    if (wave_lds_bytes(a, wpb) <= limit) return wpb;
+  return 4;
+}
+
+int samples_per_block(const ProjArgs& a) {
+  return (a.row_tiles == 0 ? wave_block_waves(a) : 1) * (16 / a.axis_slots);
+}
 
 int project_threads(int K, int row_tiles) { return 64 * waves_for(K, row_tiles); }
 
 size_t project_lds_bytes(const ProjArgs& a) {
+  if (a.row_tiles == 0) return wave_lds_bytes(a, wave_block_waves(a));
   const int NB = waves_for(a.K, a.row_tiles) * a.row_tiles;
   return sizeof(float) *
          static_cast<size_t>(layout(a.dims, a.nv, a.M, NB, partial_slots(a.K, a.row_tiles),
-                                    samples_per_block(a.axis_slots), a.mode).total);
+                                    16 / a.axis_slots, a.mode).total);
 }
 
 void set_default_tiling(ProjArgs& a) {
   a.axis_slots = 4;
   a.row_tiles = 1;
   a.persistent = 0;
-  a.S = samples_per_block(a.axis_slots);
+  a.S = samples_per_block(a);
 }
 
 hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s, hipEvent_t start,
                           hipEvent_t stop) {
-  if (!tiling_valid(a.dims, a.axis_slots, a.row_tiles) || a.S != samples_per_block(a.axis_slots) ||
+  if (!tiling_valid(a.dims, a.axis_slots, a.row_tiles, a.K) || a.S != samples_per_block(a) ||
       a.blocks_per_problem != (a.N + a.S - 1) / a.S)
     return hipErrorInvalidValue;
   if ((a.resid_hist || a.traj) && (a.axis_slots != 4 || a.row_tiles != 1 || a.persistent))
     return hipErrorInvalidValue;
   if (a.resid_hist && n_problems != 1) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(a);
-  const int threads = project_threads(a.K, a.row_tiles);
+  const int threads = a.row_tiles == 0 ? 64 * (a.S / (16 / a.axis_slots))
+                                       : project_threads(a.K, a.row_tiles);
   const int total = n_problems * a.blocks_per_problem;
   if (total <= 0) return hipSuccess;
   const bool bf = a.bf16_iters > 0;

@@ -5,7 +5,9 @@
 // per block, which doubles the block count for small batches), in how many
 // 16-step time blocks one wave carries (1 or 2: more independent items per
 // lane, fewer waves per block), and in the grid (one block per tile, or a
-// persistent grid of resident blocks looping over tiles).  All candidates
+// persistent grid of resident blocks looping over tiles), or whether one wave
+// owns a sample group over the whole horizon (no block barrier per
+// iteration; for batches large enough to fill the chip).  All candidates
 // compute bit-identical results, so the choice only affects time: each
 // candidate runs one warm-up launch, then two timed launches of the caller's
 // real arguments (outputs redirected by the caller) in each of two passes
@@ -18,13 +20,14 @@
 
 namespace priest {
 
-std::vector<TileCfg> tile_candidates(int dims) {
+std::vector<TileCfg> tile_candidates(int dims, int K) {
   std::vector<TileCfg> out;
   const int slots[3] = {4, 2, 8};
-  for (int rt = 1; rt <= 2; ++rt)
+  const int rts[3] = {1, 2, 0};
+  for (int rt : rts)
     for (int s : slots)
       for (int pers = 0; pers <= 1; ++pers)
-        if (tiling_valid(dims, s, rt)) out.push_back(TileCfg{s, rt, pers});
+        if (tiling_valid(dims, s, rt, K)) out.push_back(TileCfg{s, rt, pers});
   return out;
 }
 
@@ -32,7 +35,7 @@ void apply_tiling(ProjArgs& a, const TileCfg& t) {
   a.axis_slots = t.axis_slots;
   a.row_tiles = t.row_tiles;
   a.persistent = t.persistent;
-  a.S = samples_per_block(t.axis_slots);
+  a.S = samples_per_block(a);
   a.blocks_per_problem = (a.N + a.S - 1) / a.S;
 }
 

@@ -149,7 +149,36 @@ def test_autotuner_picks_a_candidate_and_keeps_results(P):
 
 def test_set_tiling_rejects_non_candidates(P):
     prob = P.Problem.from_workload(W.C3)
-    for bad in [(2, 1, 0), (3, 1, 0), (4, 3, 0), (4, 1, 2), (8, 2, 0), (16, 1, 0)]:
+    for bad in [(2, 1, 0), (3, 1, 0), (4, 3, 0), (4, 1, 2), (8, 2, 0), (16, 1, 0), (2, 0, 0),
+                (8, 0, 0), (4, -1, 0)]:
         with pytest.raises(P.PriestError):
             prob.set_tiling(bad)
+    assert (4, 0, 0) in prob.tiling_candidates() and (4, 0, 1) in prob.tiling_candidates()
     prob.close()
+    # the whole-horizon shape holds at most 8 time blocks (n_steps <= 128)
+    long = P.Problem.from_workload(W.with_changes(W.C2, n_steps=129, horizon=20.0))
+    assert all(c[1] != 0 for c in long.tiling_candidates())
+    with pytest.raises(P.PriestError):
+        long.set_tiling((2, 0, 0))
+    long.close()
+
+
+def test_whole_horizon_shape_matches_oracle(P):
+    """The whole-horizon shape (one wave per sample group over every time
+    block) against the oracle directly, 3D and 2D, with a ragged last group."""
+    for wl, n, shape in ((W.with_changes(W.C3, n_obs=40), 37, (4, 0, 0)),
+                         (W.C2, 45, (2, 0, 1))):
+        say(f"tilings: whole-horizon shape {shape} vs the oracle ({wl.name}, N={n})")
+        prob = P.Problem.from_workload(wl)
+        op = oracle_problem(wl)
+        bc, obs = W.scene(wl, 0)
+        xi = W.samples(wl, 8, n=n).astype(np.float32)
+        prob.set_tiling(shape)
+        xo, r, c1 = prob.project(t32(bc), t32(obs), t32(xi), 25)
+        torch.cuda.synchronize()
+        assert prob.last_tiling() == (shape, False)
+        pr = O.project(op, bc, obs, xi.astype(np.float64), 25)
+        check_projection(op, bc, obs, xi, xo.cpu().numpy().astype(np.float64), pr.xi_bar, 25,
+                         label=f"whole horizon {wl.name}")
+        np.testing.assert_allclose(r.cpu().numpy(), pr.resid, atol=2e-3 * max(1, pr.resid.max()))
+        prob.close()
