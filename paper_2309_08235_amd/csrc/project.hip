@@ -358,8 +358,11 @@ __device__ __forceinline__ void zero_push(const Rec& o, float s[DIMS], float& r2
   }
 }
 
+// Push-out of a norm bound |w| <= wmax (eqs. (11a)-(11b)): d = w (wmax/|w| - 1)
+// when violated, else 0; r2 += |d|^2 as one explicit fma (ww f) f + r2, so
+// that every kernel rounds it the same way.
 template <int DIMS>
-__device__ __forceinline__ float bound_push(const float w[DIMS], float wmax, float d[DIMS]) {
+__device__ __forceinline__ void bound_push(const float w[DIMS], float wmax, float d[DIMS], float& r2) {
   float ww = 0.0f;
 #pragma unroll
   for (int x = 0; x < DIMS; ++x) ww = fmaf(w[x], w[x], ww);
@@ -367,7 +370,7 @@ __device__ __forceinline__ float bound_push(const float w[DIMS], float wmax, flo
   if (ww > wmax * wmax) f = fmaf(wmax, rsq(ww), -1.0f);
 #pragma unroll
   for (int x = 0; x < DIMS; ++x) d[x] = w[x] * f;
-  return ww * f * f;
+  r2 = fmaf(ww * f, f, r2);
 }
 
 // Weighted trajectory cost of one (sample, step) item: acceleration,
@@ -739,8 +742,8 @@ __device__ __forceinline__ void item_push(const float4* rec, int M, const float 
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (ok[i]) {
-      r2[i] += bound_push<DIMS>(v[i], vmax, dv[i]);
-      r2[i] += bound_push<DIMS>(ac[i], amax, da[i]);
+      bound_push<DIMS>(v[i], vmax, dv[i], r2[i]);
+      bound_push<DIMS>(ac[i], amax, da[i], r2[i]);
     }
   // workspace bounds: rows -P and P of G, whose targets min(tau, G xi_bar)
   // add clamp(p, lo, hi) - p to the position rows
@@ -1406,8 +1409,12 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
 // Items that are not valid still get finite push-outs, which the caller
 // masks where they matter (steps past the horizon meet zero W rows in the
 // right-hand side; columns of absent samples are never written out).
+// Returns which row types (bit 0: obstacles and bounds on the positions,
+// bit 1: velocity, bit 2: acceleration) have a nonzero push-out on some
+// valid item of the wave; the others are zero on every valid item (for the
+// velocity and acceleration rows they are then not computed at all).
 template <int DIMS, bool LAST, int NI>
-__device__ __forceinline__ void wave_block_push(const float4* rec, int M, float tt, float tmid, float thalf,
+__device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, float tt, float tmid, float thalf,
                                                 float slack, const bool ok[NI], const float p[NI][DIMS],
                                                 const float v[NI][DIMS], const float ac[NI][DIMS],
                                                 float vmax, float amax, const Box& box, float S[NI][DIMS],
@@ -1473,15 +1480,37 @@ __device__ __forceinline__ void wave_block_push(const float4* rec, int M, float 
       }
     }
   }
+  // velocity / acceleration bounds: skipped for the wave when no valid item
+  // exceeds them (then every push-out of the row type is zero)
+  // (r2 += |d|^2 as the explicit fma of bound_push; with f = 0 it leaves r2
+  // unchanged, so items without a violation need no update)
+  uint32_t nz = 0;
+  auto bounds = [&](const float (*w)[DIMS], float wmax, float (*d)[DIMS], uint32_t bit) {
+    float ww[NI];
+    bool any = false;
 #pragma unroll
-  for (int i = 0; i < NI; ++i) {
-    const float rv = bound_push<DIMS>(v[i], vmax, dv[i]);
-    const float ra = bound_push<DIMS>(ac[i], amax, da[i]);
-    if (LAST) {
-      r2[i] += rv;
-      r2[i] += ra;
+    for (int i = 0; i < NI; ++i) {
+      ww[i] = 0.0f;
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) ww[i] = fmaf(w[i][x], w[i][x], ww[i]);
+      any = any || (ok[i] && ww[i] > wmax * wmax);
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) d[i][x] = 0.0f;
     }
-  }
+    if (__ballot(any) != 0ull) {
+      nz |= bit;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        float f = 0.0f;
+        if (ww[i] > wmax * wmax) f = fmaf(wmax, rsq(ww[i]), -1.0f);
+#pragma unroll
+        for (int x = 0; x < DIMS; ++x) d[i][x] = w[i][x] * f;
+        if (LAST) r2[i] = fmaf(ww[i] * f, f, r2[i]);
+      }
+    }
+  };
+  bounds(v, vmax, dv, 2u);
+  bounds(ac, amax, da, 4u);
   if (box.on) {
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -1492,6 +1521,15 @@ __device__ __forceinline__ void wave_block_push(const float4* rec, int M, float 
         if (LAST) r2[i] = fmaf(e, e, r2[i]);
       }
   }
+  if (ncand || box.on) {
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) any = any || (ok[i] && S[i][x] != 0.0f);
+    if (__ballot(any) != 0ull) nz |= 1u;
+  }
+  return nz;
 }
 
 template <int DIMS, int AS, bool BF16>
@@ -1675,9 +1713,9 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         }
       }
       const float tmid = a.dt * (static_cast<float>(16 * tb) + 7.5f);
-      wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack, ok, p,
-                                      v, ac, a.vmax, a.amax, a.box, S, dv, da, r2, lane,
-                                      cwords + tb * cstride, nok, pairs);
+      return wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
+                                             ok, p, v, ac, a.vmax, a.amax, a.box, S, dv, da, r2, lane,
+                                             cwords + tb * cstride, nok, pairs);
     };
     auto load_w = [&](int tb, float4 (&wv)[kWtabV4], int i0, int i1) {
 #pragma unroll
@@ -1711,46 +1749,55 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         load_w(tb, wv, 0, 3);
         float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
         bool ok[NI];
-        block_items(tb, wv, std::false_type{}, p, v, ac, S, dv, da, r2, ok);
-        load_w(tb, wv, 3, 6);
-        // push-outs to the column layout through the planes
+        const uint32_t nz = block_items(tb, wv, std::false_type{}, p, v, ac, S, dv, da, r2, ok);
+        // Right-hand side of the row types with a nonzero push-out.  The
+        // products of an all-zero row type are exact zeros, and an
+        // accumulator that starts at +0 is unchanged by adding them, so
+        // skipping them leaves the partial bit for bit as in the full chains.
+        f4 part = zf;
+        if (nz) {
+          const float (*src[3])[DIMS] = {S, dv, da};
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
+          for (int d = 0; d < 3; ++d)
+            if (nz & (1u << d)) {
 #pragma unroll
-          for (int x = 0; x < DIMS; ++x) {
-            const int r = AS * i + x;
-            wr[(0 * 4 + r) * kPlane + lane] = S[i][x];
-            wr[(1 * 4 + r) * kPlane + lane] = dv[i][x];
-            wr[(2 * 4 + r) * kPlane + lane] = da[i][x];
+              for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int x = 0; x < DIMS; ++x) wr[(d * 4 + AS * i + x) * kPlane + lane] = src[d][i][x];
+            }
+          wave_lds_sync();
+          f4 B[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (nz & (1u << d)) {
+              B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
+              wv[3 + d] = wtab[(tb * kWtabV4 + 3 + d) * 64 + lane];
+            }
+          wave_lds_sync();
+          if (lowp) {
+            f4 gg = zf;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if (nz & (1u << d)) {
+                const float4 A4 = wv[3 + d];
+                gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
+                               pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
+              }
+            part = gg;
+          } else {
+            // the two accumulation chains of the time-split shape
+            f4 acc0 = zf, acc1 = zf;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if (nz & (1u << d)) {
+                const float4 A4 = wv[3 + d];
+                acc0 = mfma(A4.x, B[d][0], acc0);
+                acc1 = mfma(A4.y, B[d][1], acc1);
+                acc0 = mfma(A4.z, B[d][2], acc0);
+                acc1 = mfma(A4.w, B[d][3], acc1);
+              }
+            part = acc0 + acc1;
           }
-        wave_lds_sync();
-        f4 B[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-          B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
-        wave_lds_sync();
-        f4 part;
-        if (lowp) {
-          f4 gg = zf;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const float4 A4 = wv[3 + d];
-            gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
-                           pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
-          }
-          part = gg;
-        } else {
-          // the two accumulation chains of the time-split shape
-          f4 acc0 = zf, acc1 = zf;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const float4 A4 = wv[3 + d];
-            acc0 = mfma(A4.x, B[d][0], acc0);
-            acc1 = mfma(A4.y, B[d][1], acc1);
-            acc0 = mfma(A4.z, B[d][2], acc0);
-            acc1 = mfma(A4.w, B[d][3], acc1);
-          }
-          part = acc0 + acc1;
         }
         tree(tb, part);
       }
@@ -1918,8 +1965,9 @@ __global__ void offsets_kernel(ProjArgs a, const float* xi, float* out) {
     for (int x = 0; x < DIMS; ++x) o[(j * K + t) * DIMS + x] = S[x];
   }
   float dv[DIMS], da[DIMS];
-  bound_push<DIMS>(v, a.vmax, dv);
-  bound_push<DIMS>(ac, a.amax, da);
+  float r2b = 0.0f;
+  bound_push<DIMS>(v, a.vmax, dv, r2b);
+  bound_push<DIMS>(ac, a.amax, da, r2b);
   for (int x = 0; x < DIMS; ++x) {
     o[(M * K + t) * DIMS + x] = dv[x];
     o[((M + 1) * K + t) * DIMS + x] = da[x];
