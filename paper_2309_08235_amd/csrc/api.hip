@@ -136,6 +136,7 @@ struct priest_problem {
   float* dM12 = nullptr;   // [nv][6]
   double* d64 = nullptr;   // scratch for the FP64 factorisation
   std::vector<float> hW, hM11, hPi, hM12;
+  float bscale[3] = {0.0f, 0.0f, 0.0f};  // ProjArgs::bscale
   std::mutex graph_mu;
   std::vector<GraphEntry> graphs;
   int device = 0;
@@ -240,6 +241,7 @@ ProjArgs base_args(const priest_problem* p) {
   a.M11 = p->dM11;
   a.Pi = p->dPi;
   a.M12 = p->dM12;
+  for (int x = 0; x < 3; ++x) a.bscale[x] = p->bscale[x];
   return a;
 }
 
@@ -592,6 +594,22 @@ int32_t priest_init_problem(const priest_problem_desc* desc, void* stream, pries
       p->hW[(k * 3 + 1) * nv + i] = static_cast<float>(Pd[k * nv + i]);
       p->hW[(k * 3 + 2) * nv + i] = static_cast<float>(Pdd[k * nv + i]);
     }
+  // Displacement budgets of the whole-horizon shape: a change Delta of the
+  // coefficients moves row type d of step t by |W_t,d Delta| <= S_d max|Delta|
+  // per axis (S_d = max_t sum_j |W_t,d,j| over the FP32 rows, rounded up), so
+  // a slack of sigma (per axis for p, Euclidean for v and a) lasts while the
+  // summed max|Delta| stays below sigma / S_d (p) or sigma / (sqrt(dims) S_d).
+  for (int x = 0; x < 3; ++x) {
+    double sm = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double r = 0.0;
+      for (int i = 0; i < nv; ++i) r += std::fabs(static_cast<double>(p->hW[(k * 3 + x) * nv + i]));
+      sm = std::max(sm, r);
+    }
+    sm *= 1.0 + 1e-6;
+    if (x > 0) sm *= std::sqrt(static_cast<double>(d.dims));
+    p->bscale[x] = sm > 0.0 ? static_cast<float>((1.0 - 1e-6) / sm) : INFINITY;
+  }
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   double *dQ = nullptr, *dA = nullptr;

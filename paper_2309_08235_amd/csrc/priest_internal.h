@@ -50,6 +50,10 @@ struct ProjArgs {
   uint32_t stream_base;        // Philox counter word 3 = stream_base + problem
   uint64_t seed;               // Philox key
   float rho, dt, vmax, amax;   // vmax/amax may be +inf
+  // whole-horizon shape: coefficient displacement allowed per unit of slack
+  // of the position (per axis), velocity and acceleration rows (Euclidean):
+  // 1 / S_d, S_d = max_t sum_j |W_t,d,j|, times 1 / sqrt(dims) for d > 0
+  float bscale[3];
   Box box;                     // workspace bounds (box.on = 0: none)
   int32_t traj;                // 1: obstacle rows are paths [K * dims] + (a, b)
   CostArgs cost;               // c1 of the final pass

@@ -187,13 +187,6 @@ __device__ __forceinline__ void row_max4(float v, float out[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) out[q] = lane_f(v, 16 * q);
 }
-__device__ __forceinline__ float wave_max(float v) {
-  v = fmaxf(v, dpp<0xB1>(v));
-  v = fmaxf(v, dpp<0x4E>(v));
-  v = fmaxf(v, dpp<0x124>(v));
-  v = fmaxf(v, dpp<0x128>(v));
-  return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
-}
 
 struct Rec {  // one obstacle record held in (uniform) registers
   float cx, cy, cz, vx, vy, vz, a, a2, ia2, ib2;
@@ -1289,10 +1282,10 @@ struct WaveLayout {  // offsets into dynamic LDS, in floats
 // operands (rows P, Pdot, Pddot x 4 coefficient chunks) and the 12
 // right-hand-side A operands (row types x 4 time chunks); wave: per wave 12
 // transpose planes (3 quantities x 4 column residues), then per time block
-// its candidate cache: word 0 = 1 + number of candidates (0: none yet),
-// words 4..35 the box of each row of 16 lanes grown by the reuse slack
-// (low corner, high corner as float4), then 4 mask words per obstacle group
-// (static, moving; 64 bits each); stage: sampler staging of the block's
+// its candidate cache: words 0..31 the box of each row of 16 lanes grown by
+// the reuse slack (low corner, high corner as float4), then 4 mask words per
+// obstacle group (static, moving; 64 bits each); stage: sampler staging of
+// the block's
 // samples, aliasing the wave regions (used before any wave iterates).
 __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int NB, int WPB, int SPW,
                                                   int mode) {
@@ -1302,7 +1295,7 @@ __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int N
   l.rec = o;  o += 12 * M;
   l.wtab = o; o += NB * kWtabV4 * 64 * 4;
   l.cache = 12 * kPlane;
-  l.cstride = 36 + 4 * G;
+  l.cstride = 32 + 4 * G;
   l.wave_floats = round4(l.cache + NB * l.cstride);
   l.wave = o; o += WPB * l.wave_floats;
   l.stage = l.wave;
@@ -1311,6 +1304,32 @@ __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int N
   if (l.stage + stage > o) o = l.stage + stage;
   l.total = o;
   return l;
+}
+
+// Wave-wide maximum / minimum of floats that are >= +0 (or +inf / NaN),
+// compared as their bit patterns, which orders them as floats (NaN above
+// +inf): integer max / min with DPP operands within each row (xor 1, xor 2,
+// half-row mirror, row mirror), then the rows combined through row
+// broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2 and 3).
+// (Lanes of rows that a broadcast leaves unwritten hold undefined values
+// afterwards; lane 63, the only one read, takes its operands from written
+// lanes only: lanes 15 and 47 after the row steps, lane 31 after the first
+// broadcast.)
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dppu(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, ROWS, 0xF, true));
+}
+template <bool MAX>
+__device__ __forceinline__ float wave_reduce_nn(float x) {
+  auto op = [](uint32_t a, uint32_t b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+  uint32_t v = __float_as_uint(x);
+  v = op(v, dppu<0xB1>(v));
+  v = op(v, dppu<0x4E>(v));
+  v = op(v, dppu<0x141>(v));
+  v = op(v, dppu<0x140>(v));
+  v = op(v, dppu<0x142, 0xA>(v));
+  v = op(v, dppu<0x143, 0xC>(v));
+  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63)));
 }
 
 // Minimum / maximum over each row of 16 lanes, left in every lane of the row.
@@ -1332,12 +1351,11 @@ __device__ __forceinline__ float row16_max(float v) {
 // gets the bounding box of its valid items; an obstacle is a candidate if its
 // sphere, grown by sqrt(DIMS) * slack and by |v| * (half window) for a moving
 // obstacle (centre taken at the window's middle), comes near any row's box.
-// The cache stays valid while every valid item lies in its row's box grown
-// by `slack` per axis: such an item is at most sqrt(DIMS) * slack from the
-// box, so a skipped obstacle stays farther than its cull radius (a * 1.001 +
-// 1e-4 beyond the surface) from every item, where the push-out is exactly
-// zero.  Writes the grown boxes, the masks and the state word; returns the
-// candidate count.
+// While every valid item lies in its row's box grown by `slack` per axis, it
+// is at most sqrt(DIMS) * slack from the box, so a skipped obstacle stays
+// farther than its cull radius (a * 1.001 + 1e-4 beyond the surface) from
+// every item, where the push-out is exactly zero.  Writes the grown boxes and
+// the masks; returns the candidate count.
 template <int DIMS, int NI>
 __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, const float p[NI][DIMS],
                                                     const bool ok[NI], float tmid, float thalf,
@@ -1355,7 +1373,7 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
     hi[x] = row16_max(mx);
   }
   if ((lane & 15) == 0) {
-    float* bx = reinterpret_cast<float*>(cw) + 4 + 8 * (lane >> 4);
+    float* bx = reinterpret_cast<float*>(cw) + 8 * (lane >> 4);
     *reinterpret_cast<float4*>(bx) = make_float4(lo[0] - slack, lo[1] - slack,
                                                  DIMS == 3 ? lo[DIMS - 1] - slack : 0.0f, 0.0f);
     *reinterpret_cast<float4*>(bx + 4) = make_float4(hi[0] + slack, hi[1] + slack,
@@ -1369,9 +1387,9 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
       blo[x][q] = lane_f(lo[x], 16 * q);
       bhi[x][q] = lane_f(hi[x], 16 * q);
     }
+  uint32_t* masks = cw + 32;
   const float grow = (DIMS == 3 ? 1.7320508f : 1.4142136f) * slack * 1.0001f;
   uint32_t ncand = 0;
-  uint32_t* masks = cw + 36;
   for (int g = 0; 64 * g < M; ++g) {
     const int j = 64 * g + lane;
     const int jc = j < M ? j : M - 1;
@@ -1398,105 +1416,127 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
     }
     ncand += static_cast<uint32_t>(__builtin_popcountll(mask));
   }
-  if (lane == 0) cw[0] = 1u + ncand;
   wave_lds_sync();
   return ncand;
 }
 
 // Push-outs of this lane's items in one 16-step block of the whole-horizon
 // shape (the per-pair and per-bound arithmetic of item_push, in the same
-// canonical obstacle order), with the block's candidate cache in LDS.
-// Items that are not valid still get finite push-outs, which the caller
-// masks where they matter (steps past the horizon meet zero W rows in the
-// right-hand side; columns of absent samples are never written out).
-// Returns which row types (bit 0: obstacles and bounds on the positions,
-// bit 1: velocity, bit 2: acceleration) have a nonzero push-out on some
-// valid item of the wave; the others are zero on every valid item (for the
-// velocity and acceleration rows they are then not computed at all).
+// canonical obstacle order) for the row types in `comp` (bit 0: obstacles
+// and workspace bounds on the positions, bit 1: velocity, bit 2:
+// acceleration); the push-outs of the other row types are zero on every
+// valid item and are left at zero.  Position push-outs use the block's
+// candidate cache.  With `test`, every valid item is first checked against
+// its row's grown box: the cache is rebuilt if one is outside (or there is no
+// cache yet, ncand = ~0), and pmargin receives the smallest distance per axis
+// from a valid item to its grown box (slack after a rebuild).  Items that are not valid
+// still get finite push-outs, which the caller masks where they matter
+// (steps past the horizon meet zero W rows in the right-hand side; columns of
+// absent samples are never written out).  Returns which row types have a
+// nonzero push-out on some valid item; wwv / wwa receive the largest |v|^2 /
+// |a|^2 over the valid items (not in the final pass).
 template <int DIMS, bool LAST, int NI>
-__device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, float tt, float tmid, float thalf,
-                                                float slack, const bool ok[NI], const float p[NI][DIMS],
-                                                const float v[NI][DIMS], const float ac[NI][DIMS],
-                                                float vmax, float amax, const Box& box, float S[NI][DIMS],
-                                                float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
-                                                int lane, uint32_t* cw, uint32_t nok, uint32_t& pairs) {
+__device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, float tt, float tmid,
+                                                    float thalf, float slack, uint32_t comp,
+                                                    bool test, const bool ok[NI],
+                                                    const float p[NI][DIMS], const float v[NI][DIMS],
+                                                    const float ac[NI][DIMS], float vmax, float amax,
+                                                    const Box& box, float S[NI][DIMS],
+                                                    float dv[NI][DIMS], float da[NI][DIMS],
+                                                    float r2[NI], int lane, uint32_t* cw,
+                                                    uint32_t& ncand, uint32_t nok, uint32_t& pairs,
+                                                    float& wwv, float& wwa, float& pmargin) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
-    for (int x = 0; x < DIMS; ++x) S[i][x] = 0.0f;
+    for (int x = 0; x < DIMS; ++x) {
+      S[i][x] = 0.0f;
+      dv[i][x] = 0.0f;
+      da[i][x] = 0.0f;
+    }
     r2[i] = 0.0f;
   }
-  // reuse test: every valid item inside its row's grown box
-  const uint32_t state = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(cw[0]));
-  uint32_t ncand = state - 1u;
-  bool rebuild = state == 0u;
-  if (!rebuild) {
-    const float* bx = reinterpret_cast<const float*>(cw) + 4 + 8 * (lane >> 4);
-    const float4 glo = *reinterpret_cast<const float4*>(bx);
-    const float4 ghi = *reinterpret_cast<const float4*>(bx + 4);
-    const float gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
-    bool out = false;
+  if (comp & 1u) {
+    if (test) {
+      bool rebuild = ncand == ~0u;
+      if (!rebuild) {
+        const float* bx = reinterpret_cast<const float*>(cw) + 8 * (lane >> 4);
+        const float4 glo = *reinterpret_cast<const float4*>(bx);
+        const float4 ghi = *reinterpret_cast<const float4*>(bx + 4);
+        const float gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
+        bool out = false;
+        float mu = INFINITY;
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int x = 0; x < DIMS; ++x) {
-        const int xx = (DIMS == 3 || x < 2) ? x : 2;
-        out = out || (ok[i] && !(p[i][x] >= gl[xx] && p[i][x] <= gh[xx]));
+          for (int x = 0; x < DIMS; ++x) {
+            const int xx = (DIMS == 3 || x < 2) ? x : 2;
+            const float d0 = p[i][x] - gl[xx], d1 = gh[xx] - p[i][x];
+            out = out | (ok[i] & !((d0 >= 0.0f) & (d1 >= 0.0f)));
+            mu = fminf(mu, ok[i] ? fminf(d0, d1) : INFINITY);
+          }
+        rebuild = __ballot(out) != 0ull;
+        // (every valid distance is >= 0 here; the mask turns -0 into +0)
+        if (!rebuild) pmargin = wave_reduce_nn<false>(__uint_as_float(__float_as_uint(mu) & 0x7fffffffu));
       }
-    rebuild = __ballot(out) != 0ull;
-  }
-  if (rebuild) ncand = wave_block_cull<DIMS, NI>(rec, M, p, ok, tmid, thalf, slack, lane, cw);
-  if (ncand) {
-    pairs += ncand * nok;
-    const uint32_t* masks = cw + 36;
-    float tt_[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) tt_[i] = tt;
-    for (int g = 0; 64 * g < M; ++g) {
-      const uint4 m4 = *reinterpret_cast<const uint4*>(masks + 4 * g);
-      auto u64 = [](uint32_t lo, uint32_t hi) {
-        return static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo))) |
-               (static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi))) << 32);
-      };
-      const unsigned long long cmask = u64(m4.x, m4.y);
-      if (!cmask) continue;
-      const unsigned long long mvmask = u64(m4.z, m4.w);
-      const int j = 64 * g + lane;
-      const int jc = j < M ? j : M - 1;
-      const float4 R0 = rec[jc], R1 = rec[M + jc], R2 = rec[2 * M + jc];
-      unsigned long long ms = cmask & ~mvmask;
-      while (ms) {
-        const Rec o = rec_of_lane<DIMS, false>(R0, R1, R2, __builtin_ctzll(ms));
-        ms &= ms - 1;
-#pragma unroll
-        for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, false>(o, tt_[i], p[i]), S[i], r2[i]);
+      if (rebuild) {
+        ncand = wave_block_cull<DIMS, NI>(rec, M, p, ok, tmid, thalf, slack, lane, cw);
+        pmargin = slack;
       }
-      unsigned long long mm = mvmask;
-      while (mm) {
-        const Rec o = rec_of_lane<DIMS, true>(R0, R1, R2, __builtin_ctzll(mm));
-        mm &= mm - 1;
+    }
+    if (ncand) {
+      const uint32_t* masks = cw + 32;
+      pairs += ncand * nok;
+      float tt_[NI];
 #pragma unroll
-        for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, true>(o, tt_[i], p[i]), S[i], r2[i]);
+      for (int i = 0; i < NI; ++i) tt_[i] = tt;
+      for (int g = 0; 64 * g < M; ++g) {
+        const uint4 m4 = *reinterpret_cast<const uint4*>(masks + 4 * g);
+        auto u64 = [](uint32_t lo, uint32_t hi) {
+          return static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(lo))) |
+                 (static_cast<unsigned long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(hi))) << 32);
+        };
+        const unsigned long long cmask = u64(m4.x, m4.y);
+        if (!cmask) continue;
+        const unsigned long long mvmask = u64(m4.z, m4.w);
+        const int j = 64 * g + lane;
+        const int jc = j < M ? j : M - 1;
+        const float4 R0 = rec[jc], R1 = rec[M + jc], R2 = rec[2 * M + jc];
+        unsigned long long ms = cmask & ~mvmask;
+        while (ms) {
+          const Rec o = rec_of_lane<DIMS, false>(R0, R1, R2, __builtin_ctzll(ms));
+          ms &= ms - 1;
+#pragma unroll
+          for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, false>(o, tt_[i], p[i]), S[i], r2[i]);
+        }
+        unsigned long long mm = mvmask;
+        while (mm) {
+          const Rec o = rec_of_lane<DIMS, true>(R0, R1, R2, __builtin_ctzll(mm));
+          mm &= mm - 1;
+#pragma unroll
+          for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, true>(o, tt_[i], p[i]), S[i], r2[i]);
+        }
       }
     }
   }
-  // velocity / acceleration bounds: skipped for the wave when no valid item
-  // exceeds them (then every push-out of the row type is zero)
-  // (r2 += |d|^2 as the explicit fma of bound_push; with f = 0 it leaves r2
-  // unchanged, so items without a violation need no update)
+  // velocity / acceleration bounds: the push-outs of a row type are computed
+  // only when some valid item exceeds its bound (r2 += |d|^2 as the explicit
+  // fma of bound_push; with f = 0 it leaves r2 unchanged, so items without a
+  // violation need no update)
   uint32_t nz = 0;
-  auto bounds = [&](const float (*w)[DIMS], float wmax, float (*d)[DIMS], uint32_t bit) {
+  auto bounds = [&](const float (*w)[DIMS], float wmax, float (*d)[DIMS], uint32_t bit, float& wwm) {
     float ww[NI];
     bool any = false;
+    float m = 0.0f;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       ww[i] = 0.0f;
 #pragma unroll
       for (int x = 0; x < DIMS; ++x) ww[i] = fmaf(w[i][x], w[i][x], ww[i]);
-      any = any || (ok[i] && ww[i] > wmax * wmax);
-#pragma unroll
-      for (int x = 0; x < DIMS; ++x) d[i][x] = 0.0f;
+      any = any | (ok[i] & (ww[i] > wmax * wmax));
+      m = ok[i] ? fmaxf(m, ww[i]) : m;
     }
+    if (!LAST) wwm = wave_reduce_nn<true>(m);
     if (__ballot(any) != 0ull) {
       nz |= bit;
 #pragma unroll
@@ -1509,9 +1549,9 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
       }
     }
   };
-  bounds(v, vmax, dv, 2u);
-  bounds(ac, amax, da, 4u);
-  if (box.on) {
+  if (comp & 2u) bounds(v, vmax, dv, 2u, wwv);
+  if (comp & 4u) bounds(ac, amax, da, 4u, wwa);
+  if ((comp & 1u) && box.on) {
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -1521,7 +1561,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
         if (LAST) r2[i] = fmaf(e, e, r2[i]);
       }
   }
-  if (ncand || box.on) {
+  if ((comp & 1u) && (ncand || box.on)) {
     bool any = false;
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -1541,7 +1581,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, WPB = blockDim.x >> 6;
   const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv, D4 = round4(D);
-  const int NB = (K + 15) >> 4, G = (M + 63) >> 6, SPB = WPB * SPW;
+  const int NB = (K + 15) >> 4, SPB = WPB * SPW;
   const WaveLayout l = wave_layout(DIMS, nv, M, NB, WPB, SPW, a.mode);
   // column layout (MFMA state): col = AS * cs + cx, coefficient rows 4 q + r;
   // item layout (forward rows, push-outs): step ti of columns 4 q + 0..3
@@ -1669,9 +1709,8 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
 #pragma unroll
         for (int d = 0; d < 3; ++d) wr[(d * 4 + x) * kPlane + lane] = 0.0f;
     }
-    if (lane < NB) cwords[lane * cstride] = 0u;
     wave_lds_sync();
-    // reuse slack of the candidate caches: the smallest cull radius of the scene
+    // reuse slack of the candidate masks: the smallest cull radius of the scene
     float slack = INFINITY;
     for (int j = lane; j < M; j += 64) slack = fminf(slack, rec[j].w);
     slack = M > 0 ? wave_min(slack) : 1.0f;
@@ -1680,24 +1719,74 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
     f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
     uint32_t pairs = 0;
 
-    // One time block: forward rows p/v/a of columns 4 q + 0..3 at step
-    // 16 tb + ti (item layout), then the push-outs of this lane's items with
-    // the block's candidate cache.
-    auto block_items = [&](int tb, const float4 (&wv)[kWtabV4], auto last_tag, float p[NI][DIMS],
-                           float v[NI][DIMS], float ac[NI][DIMS], float S[NI][DIMS],
-                           float dv[NI][DIMS], float da[NI][DIMS], float r2[NI], bool ok[NI]) {
+    // Displacement budgets.  Lane tb < NB holds, for time block tb, how much
+    // more the coefficients may move (summed max |change| over this wave's
+    // valid columns) before its positions may leave the grown boxes of its
+    // candidate cache (Bp) or its velocities / accelerations may exceed
+    // their bounds (Bv, Ba), and the block's candidate count (ncl).  A row
+    // type whose budget is left is not evaluated: its push-outs are zero on
+    // every valid item; with no budget left the positions are tested against
+    // the grown boxes and the cache is rebuilt only if an item is outside.
+    // The budgets come from the last evaluation: a change
+    // Delta moves row type d by at most S_d max|Delta| (bscale), and the
+    // MFMA rounding of the two evaluations, at most 3e-6 S_d X with X a bound
+    // on max |xi_bar|, is taken off with margin (1e-5 X); the factor 0.99899
+    // covers the rounding of the budget arithmetic.
+    float Bp = -1.0f, Bv = -1.0f, Ba = -1.0f;
+    uint32_t ncl = ~0u;  // no cache yet
+    const uint32_t blocks = (1u << NB) - 1u;
+    uint32_t mP = blocks, mV = blocks, mA = blocks;  // blocks to evaluate
+    float X;
+    {
+      float m = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(xi[r]));
+      X = wave_reduce_nn<true>(colok ? m : 0.0f) * 1.000002f;
+    }
+    auto budget = [&](float A) { return fmaf(A, 0.99899f, -1.0e-5f * X); };
+    auto bound_budget = [&](float wmax, float wwm, float scale) {
+      // (v_sqrt_f32 is within 1 ulp)
+      return budget((wmax * 0.999999f - __builtin_amdgcn_sqrtf(wwm) * 1.000001f) * scale);
+    };
+
+    // One time block: forward rows of the row types in `comp` (bit 0:
+    // positions, 1: velocities, 2: accelerations) of columns 4 q + 0..3 at
+    // step 16 tb + ti (item layout), then the push-outs of this lane's items.
+    auto block_items = [&](int tb, uint32_t comp, bool test, uint32_t& ncand, auto last_tag,
+                           float p[NI][DIMS], float v[NI][DIMS], float ac[NI][DIMS],
+                           float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
+                           bool ok[NI], float& wwv, float& wwa, float& pm) {
       constexpr bool LAST = decltype(last_tag)::value;
-      f4 Y0 = mfma(xb[0], wv[0].x, zf), Y1 = mfma(xb[0], wv[1].x, zf), Y2 = mfma(xb[0], wv[2].x, zf);
-      Y0 = mfma(xb[1], wv[0].y, Y0);
-      Y1 = mfma(xb[1], wv[1].y, Y1);
-      Y2 = mfma(xb[1], wv[2].y, Y2);
-      Y0 = mfma(xb[2], wv[0].z, Y0);
-      Y1 = mfma(xb[2], wv[1].z, Y1);
-      Y2 = mfma(xb[2], wv[2].z, Y2);
-      if (chunk3) {
-        Y0 = mfma(xb[3], wv[0].w, Y0);
-        Y1 = mfma(xb[3], wv[1].w, Y1);
-        Y2 = mfma(xb[3], wv[2].w, Y2);
+      const float4* wt = wtab + tb * kWtabV4 * 64 + lane;
+      f4 Y0 = zf, Y1 = zf, Y2 = zf;
+      if (comp == 7u) {
+        const float4 w0 = wt[0], w1 = wt[64], w2 = wt[128];
+        Y0 = mfma(xb[0], w0.x, zf);
+        Y1 = mfma(xb[0], w1.x, zf);
+        Y2 = mfma(xb[0], w2.x, zf);
+        Y0 = mfma(xb[1], w0.y, Y0);
+        Y1 = mfma(xb[1], w1.y, Y1);
+        Y2 = mfma(xb[1], w2.y, Y2);
+        Y0 = mfma(xb[2], w0.z, Y0);
+        Y1 = mfma(xb[2], w1.z, Y1);
+        Y2 = mfma(xb[2], w2.z, Y2);
+        if (chunk3) {
+          Y0 = mfma(xb[3], w0.w, Y0);
+          Y1 = mfma(xb[3], w1.w, Y1);
+          Y2 = mfma(xb[3], w2.w, Y2);
+        }
+      } else {
+        // the same chains, one row type at a time
+        auto chain = [&](const float4 w) {
+          f4 Y = mfma(xb[0], w.x, zf);
+          Y = mfma(xb[1], w.y, Y);
+          Y = mfma(xb[2], w.z, Y);
+          if (chunk3) Y = mfma(xb[3], w.w, Y);
+          return Y;
+        };
+        if (comp & 1u) Y0 = chain(wt[0]);
+        if (comp & 2u) Y1 = chain(wt[64]);
+        if (comp & 4u) Y2 = chain(wt[128]);
       }
       const int t = 16 * tb + ti;
       uint32_t nok = 0;
@@ -1714,13 +1803,9 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
       }
       const float tmid = a.dt * (static_cast<float>(16 * tb) + 7.5f);
       return wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
-                                             ok, p, v, ac, a.vmax, a.amax, a.box, S, dv, da, r2, lane,
-                                             cwords + tb * cstride, nok, pairs);
-    };
-    auto load_w = [&](int tb, float4 (&wv)[kWtabV4], int i0, int i1) {
-#pragma unroll
-      for (int i = 0; i < kWtabV4; ++i)
-        if (i >= i0 && i < i1) wv[i] = wtab[(tb * kWtabV4 + i) * 64 + lane];
+                                             comp, test, ok, p, v, ac, a.vmax, a.amax, a.box, S,
+                                             dv, da, r2, lane, cwords + tb * cstride, ncand, nok,
+                                             pairs, wwv, wwa, pm);
     };
 
     // ---- projection iterations ---------------------------------------------------
@@ -1745,64 +1830,87 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         }
       };
       for (int tb = 0; tb < NB; ++tb) {
-        float4 wv[kWtabV4];
-        load_w(tb, wv, 0, 3);
-        float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-        bool ok[NI];
-        const uint32_t nz = block_items(tb, wv, std::false_type{}, p, v, ac, S, dv, da, r2, ok);
-        // Right-hand side of the row types with a nonzero push-out.  The
-        // products of an all-zero row type are exact zeros, and an
-        // accumulator that starts at +0 is unchanged by adding them, so
-        // skipping them leaves the partial bit for bit as in the full chains.
+        const uint32_t bit = 1u << tb;
+        uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
+        const bool test = (mP & bit) != 0u;
+        uint32_t comp = ((mV & bit) ? 2u : 0u) | ((mA & bit) ? 4u : 0u);
+        if (test || ncand || a.box.on) comp |= 1u;
         f4 part = zf;
-        if (nz) {
-          const float (*src[3])[DIMS] = {S, dv, da};
-#pragma unroll
-          for (int d = 0; d < 3; ++d)
-            if (nz & (1u << d)) {
-#pragma unroll
-              for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int x = 0; x < DIMS; ++x) wr[(d * 4 + AS * i + x) * kPlane + lane] = src[d][i][x];
-            }
-          wave_lds_sync();
-          f4 B[3];
-#pragma unroll
-          for (int d = 0; d < 3; ++d)
-            if (nz & (1u << d)) {
-              B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
-              wv[3 + d] = wtab[(tb * kWtabV4 + 3 + d) * 64 + lane];
-            }
-          wave_lds_sync();
-          if (lowp) {
-            f4 gg = zf;
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-              if (nz & (1u << d)) {
-                const float4 A4 = wv[3 + d];
-                gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
-                               pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
-              }
-            part = gg;
-          } else {
-            // the two accumulation chains of the time-split shape
-            f4 acc0 = zf, acc1 = zf;
+        if (comp) {
+          float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+          bool ok[NI];
+          float wwv = 0.0f, wwa = 0.0f, pm = 0.0f;
+          const uint32_t nz = block_items(tb, comp, test, ncand, std::false_type{}, p, v, ac, S, dv,
+                                          da, r2, ok, wwv, wwa, pm);
+          // new budgets of the row types evaluated here
+          if (test) {
+            const float bp = budget(pm * a.bscale[0]);
+            Bp = lane == tb ? bp : Bp;
+            ncl = lane == tb ? ncand : ncl;
+          }
+          if (comp & 2u) {
+            const float bv = (nz & 2u) ? -1.0f : bound_budget(a.vmax, wwv, a.bscale[1]);
+            Bv = lane == tb ? bv : Bv;
+          }
+          if (comp & 4u) {
+            const float ba = (nz & 4u) ? -1.0f : bound_budget(a.amax, wwa, a.bscale[2]);
+            Ba = lane == tb ? ba : Ba;
+          }
+          // Right-hand side of the row types with a nonzero push-out.  The
+          // products of an all-zero row type are exact zeros, and an
+          // accumulator that starts at +0 is unchanged by adding them, so
+          // skipping them leaves the partial bit for bit as in the full chains.
+          if (nz) {
+            const float (*src[3])[DIMS] = {S, dv, da};
 #pragma unroll
             for (int d = 0; d < 3; ++d)
               if (nz & (1u << d)) {
-                const float4 A4 = wv[3 + d];
-                acc0 = mfma(A4.x, B[d][0], acc0);
-                acc1 = mfma(A4.y, B[d][1], acc1);
-                acc0 = mfma(A4.z, B[d][2], acc0);
-                acc1 = mfma(A4.w, B[d][3], acc1);
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                  for (int x = 0; x < DIMS; ++x) wr[(d * 4 + AS * i + x) * kPlane + lane] = src[d][i][x];
               }
-            part = acc0 + acc1;
+            wave_lds_sync();
+            f4 B[3];
+            float4 wa[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if (nz & (1u << d)) {
+                B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
+                wa[d] = wtab[(tb * kWtabV4 + 3 + d) * 64 + lane];
+              }
+            wave_lds_sync();
+            if (lowp) {
+              f4 gg = zf;
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if (nz & (1u << d)) {
+                  const float4 A4 = wa[d];
+                  gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
+                                 pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
+                }
+              part = gg;
+            } else {
+              // the two accumulation chains of the time-split shape
+              f4 acc0 = zf, acc1 = zf;
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if (nz & (1u << d)) {
+                  const float4 A4 = wa[d];
+                  acc0 = mfma(A4.x, B[d][0], acc0);
+                  acc1 = mfma(A4.y, B[d][1], acc1);
+                  acc0 = mfma(A4.z, B[d][2], acc0);
+                  acc1 = mfma(A4.w, B[d][3], acc1);
+                }
+              part = acc0 + acc1;
+            }
           }
         }
         tree(tb, part);
       }
       for (int tb = NB; tb < kWaveMaxBlocks; ++tb) tree(tb, zf);
       lam += rho * g;
+      const f4 xold = xb;
       if (k == 0) {
         // Pi and c0 = M12 b enter the first step only
         float Ap[4];
@@ -1837,6 +1945,22 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         xb = mfma(Am[2], u[2], mfma(Am[1], u[1], mfma(Am[0], u[0], xb)));
         if (chunk3) xb = mfma(Am[3], u[3], xb);
       }
+      // every block's budgets shrink by the largest coefficient change of
+      // the wave's valid columns (rounded up)
+      {
+        float m = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(xb[r] - xold[r]));
+        const float dl = wave_reduce_nn<true>(colok ? m : 0.0f) * 1.000002f;
+        X += dl;
+        Bp -= dl;
+        Bv -= dl;
+        Ba -= dl;
+        const bool inb = lane < NB;
+        mP = static_cast<uint32_t>(__ballot(inb && !(Bp >= 0.0f)));
+        mV = static_cast<uint32_t>(__ballot(inb && !(Bv >= 0.0f)));
+        mA = static_cast<uint32_t>(__ballot(inb && !(Ba >= 0.0f)));
+      }
     }
 
     // ---- residual and cost of the returned iterate, summed in t order --------------
@@ -1853,11 +1977,12 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
     }
     float racc = 0.0f, cacc = 0.0f;
     for (int tb = 0; tb < NB; ++tb) {
-      float4 wv[kWtabV4];
-      load_w(tb, wv, 0, 3);
       float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
       bool ok[NI];
-      block_items(tb, wv, std::true_type{}, p, v, ac, S, dv, da, r2, ok);
+      uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
+      float wwv = 0.0f, wwa = 0.0f, pm = 0.0f;
+      block_items(tb, 7u, (mP >> tb) & 1u, ncand, std::true_type{}, p, v, ac, S, dv, da, r2, ok, wwv,
+                  wwa, pm);
       // per-(t, sample) residual^2 and cost through this wave's planes
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
