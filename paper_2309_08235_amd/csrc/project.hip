@@ -42,6 +42,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -1259,10 +1260,23 @@ __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* task
 // item lane writes its four column values to four planes, and each column
 // lane reads its four time steps from one plane with a 16-byte read.
 //
-// Each time block keeps its obstacle candidate cache (the item positions it
-// was built from, the candidate masks, a valid flag) in the wave's LDS
-// region between iterations, so the block loop needs no registers per
-// block and is not unrolled.
+// Each time block keeps its obstacle candidate cache (the grown boxes of
+// the item positions it was built from and the candidate masks) in the
+// wave's LDS region between iterations, so the block loop is not unrolled.
+//
+// Rows that cannot push are not evaluated.  Between two iterations the
+// coefficients change by Delta, which moves row type d of any step by at
+// most S_d max|Delta| (S_d: the largest absolute row sum of W's rows of that
+// type).  Each wave keeps, per time block and row type, a budget: the margin
+// found at the last evaluation (the distance of the items to the cache's
+// grown boxes, or of |v|, |a| to v_max, a_max) over S_d, less the rounding
+// of two MFMA evaluations, less the max|Delta| of every iteration since.
+// While it is positive the row type's push-outs are exactly zero on every
+// valid item, as a full evaluation would find: its forward MFMAs, bound
+// checks and right-hand side are skipped.  Positions with obstacle
+// candidates are always evaluated; when a position budget runs out the
+// items are checked against the grown boxes, and the cache is rebuilt only
+// if one has left its box.
 //
 // The arithmetic per sample is that of the time-split shape: the same
 // product chains per 16-step block (operands swapped in the forward rows,
@@ -1285,8 +1299,8 @@ struct WaveLayout {  // offsets into dynamic LDS, in floats
 // its candidate cache: words 0..31 the box of each row of 16 lanes grown by
 // the reuse slack (low corner, high corner as float4), then 4 mask words per
 // obstacle group (static, moving; 64 bits each); stage: sampler staging of
-// the block's
-// samples, aliasing the wave regions (used before any wave iterates).
+// the block's samples, aliasing the wave regions (used before any wave
+// iterates).
 __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int NB, int WPB, int SPW,
                                                   int mode) {
   WaveLayout l{};
@@ -2140,11 +2154,22 @@ int resident_blocks(const void* fn, int threads, size_t lds) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
-  int dev = 0, cus = 0;
+  int dev = 0, cus = 0, smem_cu = 0, thr_cu = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
+  // the query does not always bound the count by the block's dynamic LDS and
+  // threads: cap it by the CU's LDS and thread slots
+  if (lds > 0 &&
+      hipDeviceGetAttribute(&smem_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      smem_cu > 0)
+    per_cu = std::max(1, std::min(per_cu, static_cast<int>(static_cast<size_t>(smem_cu) / lds)));
+  if (hipDeviceGetAttribute(&thr_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) ==
+          hipSuccess &&
+      thr_cu > 0)
+    per_cu = std::max(1, std::min(per_cu, thr_cu / threads));
   const int v = per_cu * cus;
   if (n < 64) {
     keys[n] = OccKey{fn, threads, lds};
