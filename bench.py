@@ -40,6 +40,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector / MFMA peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_kernel_c3_traffic.txt")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "project_kernel_c3_mfma.txt")
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: one FP32 op per lane-cycle
 KERNEL_SOURCES = ("paper_2309_08235_amd/csrc/project.hip", "paper_2309_08235_amd/csrc/priest_internal.h")
 
 
@@ -80,22 +82,56 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per projection launch at the headline shape, from the
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/ (null when the
-    kernel sources changed since the counters were taken)."""
+def profile_values(path):
+    """key: value lines of a profiles/ summary, or None when the file is
+    missing or the kernel sources changed since its counters were taken."""
     try:
         vals = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
-        if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-            return None
-        return float(vals["hbm_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except OSError:
         return None
+    return vals if vals.get("kernel_source_sha256_16") == kernel_source_hash() else None
+
+
+def measured_traffic():
+    """HBM bytes per projection launch at the headline shape, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/ (null when the
+    kernel sources changed since the counters were taken)."""
+    vals = profile_values(TRAFFIC_FILE)
+    try:
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_execution(kernel_ms):
+    """What the projection kernel executed per launch at the headline shape,
+    from the rocprofv3 SQ counter summary in profiles/ (null when the kernel
+    sources changed since): MFMA instructions and their flops (2048 per
+    16x16x4 FP32 MFMA), VALU instructions, the MFMA busy share of SIMD
+    cycles, and the VALU lane operations per second against one FP32 op per
+    lane and cycle."""
+    vals = profile_values(COUNTER_FILE)
+    if not vals:
+        return None
+    try:
+        mfma = float(vals["mfma_instructions_per_launch"])
+        valu = float(vals["valu_instructions_per_launch"])
+        busy = float(vals["mfma_busy_frac"])
+    except (KeyError, ValueError):
+        return None
+    t = kernel_ms * 1e-3
+    return {"mfma_instructions_per_launch": mfma, "mfma_flops_per_launch": mfma * 2048,
+            "mfma_tflops": round(mfma * 2048 / t / 1e12, 3),
+            "mfma_frac": round(mfma * 2048 / t / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "mfma_busy_frac": busy, "valu_instructions_per_launch": valu,
+            "valu_lane_ops_frac": round(valu * 64 / t / VALU_LANE_OPS_PEAK, 4),
+            "source": "profiles/project_kernel_c3_mfma.txt (rocprofv3 SQ counters, same kernel "
+                      "sources), per launch over the same plans"}
 
 
 def cpu_baseline(wl, n_sample: int, gpu_results=None, extra=None):
@@ -190,12 +226,17 @@ def mfma_flops(dims: int, nv: int, K: int) -> float:
 
 
 def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note, pairs_per_launch):
-    """Roofline of the fused projection kernel.  The work per launch is the
-    dense part (per sample and iteration, plus the forward rows of the final
-    residual pass) and the obstacle pairs the kernel evaluated, counted on
-    the device (pairs dropped by culling contribute exact zeros and are not
-    work the kernel does).  mfma_useful_* is the share of the three dense
-    products alone (their unpadded flops) against the FP32 matrix peak."""
+    """Roofline of the fused projection kernel against its algorithmic work:
+    per sample and iteration the dense part of the AM iteration (forward
+    rows, push-out arithmetic outside the obstacle terms, right-hand side,
+    KKT step; plus the forward rows of the final residual pass) and the
+    obstacle pairs the kernel evaluated, counted on the device (pairs
+    dropped by culling contribute exact zeros and are not work the kernel
+    does).  dense_rows_* is the share of the three dense products (their
+    unpadded flops) against the FP32 matrix peak.  The kernel does not
+    evaluate rows whose push-outs it has proven zero, so it executes fewer
+    MFMAs than the dense products hold; the counts it executed are under
+    `executed` (from the profile counters)."""
     n, it = n_samples_per_launch, wl.n_proj_iters
     fwd = 6 * wl.dims * wl.n_coeff * wl.n_steps * n
     dense = dense_flops(wl.dims, wl.n_coeff, wl.n_steps) * n * it + fwd
@@ -210,9 +251,11 @@ def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note, pai
             "kernel_ms": round(avg_ms, 4), "launches": launches,
             "flops_per_launch": flops, "pairs_evaluated_per_launch": pairs_per_launch,
             "pairs_evaluated_frac": round(pairs_per_launch / all_pairs, 5) if all_pairs else None,
-            "mfma_useful_flops_per_launch": useful,
-            "mfma_useful_tflops": round(mfma, 3),
-            "mfma_useful_frac": round(mfma / PEAK_FP32_TFLOPS, 4),
+            "dense_rows_flops_per_launch": useful,
+            "dense_rows_tflops": round(mfma, 3),
+            "dense_rows_frac": round(mfma / PEAK_FP32_TFLOPS, 4),
+            "work": "algorithmic: dense AM-iteration flops per sample-iteration (evaluated or "
+                    "proven zero) + evaluated obstacle pairs",
             "timing": note}
 
 
@@ -522,6 +565,7 @@ def headline_c3(P, W, args):
                           "graph; its wall time is instrumented_ms_per_step", pairs / wl.n_cem)
     roof["instrumented_ms_per_step"] = round(wall_instr / args.steps * 1e3, 3)
     roof["traffic"] = measured_traffic()
+    roof["executed"] = measured_execution(roof["kernel_ms"])
     roof["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE "
                             "(profiles/project_kernel_c3_traffic.txt), null if the kernel sources "
                             "changed since")
