@@ -458,7 +458,8 @@ def unfused_baseline(P, W, reps: int):
     return out
 
 
-def serving(P, W, n_requests: int, plain_limit_s: float):
+def serving(P, W, n_requests: int, plain_limit_s: float, sweep_requests: int = 2048,
+            slo_ms: float = 10.0):
     """Continuous-batching service: the Poisson request stream of many robots
     (mixed N, M, K) replayed in real time through the server, and the same
     stream through one priest_plan call per request (the plain form)."""
@@ -479,6 +480,7 @@ def serving(P, W, n_requests: int, plain_limit_s: float):
     bad = sum(1 for c in done if c.status != 0)
     srv.close()
     plain, _ = S.run_plain(reqs, wl, realtime=True, time_limit=plain_limit_s)
+    sweep = serving_sweep(P, W, S, wl, sweep_requests, slo_ms)
     return {"workload": wl.name, "robots": wl.n_robots, "requests": n_requests,
             "offered_req_per_s": round(n_requests / span, 1),
             "offered_tflop_per_s": round(offered_flop / span / 1e12, 2),
@@ -486,7 +488,58 @@ def serving(P, W, n_requests: int, plain_limit_s: float):
             "continuous_batching": batched_line, "nonfinite_results": bad,
             "plain_per_request": plain,
             "plain_note": f"one priest_plan per request, FIFO, synchronised; stopped after "
-                          f"{plain_limit_s} s if behind"}
+                          f"{plain_limit_s} s if behind",
+            "equal_p99": sweep}
+
+
+def serving_sweep(P, W, S, wl, n_requests: int, slo_ms: float):
+    """The same kind of request stream at several offered rates (the robots'
+    Poisson clocks sped up or slowed down), through a fresh server and
+    through the plain per-request form.  A form sustains a rate if its p99
+    latency (arrival to result) stays within the SLO and it completes every
+    request; the comparison is the highest rate each form sustains."""
+    server_scales = (1.0, 1.5, 2.0, 2.25, 2.5, 2.75, 3.0, 4.0, 8.0)
+    plain_scales = (0.25, 0.5, 0.6, 0.7, 0.8, 1.0, 1.5)
+    curve = {"server": [], "plain": []}
+
+    def point(scale, summary):
+        return {"rate_scale": scale, "offered_req_per_s": summary.get("offered_req_per_s"),
+                "plans_per_s": summary["plans_per_s"], "p50_ms": summary["latency_ms"]["p50"],
+                "p99_ms": summary["latency_ms"]["p99"], "completed": summary["requests"],
+                "within_slo": bool(summary["latency_ms"]["p99"] <= slo_ms
+                                   and summary["requests"] == n_requests)}
+
+    for sc in server_scales:
+        reqs = W.serving_requests(wl, n_requests=n_requests, rate_scale=sc)
+        srv = S.Server.for_workload(wl, max_active=1024, memory_budget=2 << 30)
+        S.prepare_shapes(srv, reqs)
+        summ, _ = S.run_stream(srv, reqs, wl, realtime=True)
+        srv.close()
+        pt = point(sc, summ)
+        pt["max_active"] = summ["max_active"]
+        curve["server"].append(pt)
+    for sc in plain_scales:
+        reqs = W.serving_requests(wl, n_requests=n_requests, rate_scale=sc)
+        summ, _ = S.run_plain(reqs, wl, realtime=True, time_limit=4.0 * reqs[-1].arrival + 2.0)
+        summ["offered_req_per_s"] = round(n_requests / reqs[-1].arrival, 1)
+        curve["plain"].append(point(sc, summ))
+
+    def best(points):
+        ok = [q for q in points if q["within_slo"]]
+        if not ok:
+            return None
+        q = max(ok, key=lambda q: q["offered_req_per_s"])
+        return {"offered_req_per_s": q["offered_req_per_s"], "plans_per_s": q["plans_per_s"],
+                "p99_ms": q["p99_ms"]}
+
+    bs, bp = best(curve["server"]), best(curve["plain"])
+    return {"slo_p99_ms": slo_ms, "requests_per_point": n_requests, "curve": curve,
+            "max_sustained_under_slo": {"server": bs, "plain": bp},
+            "server_over_plain": (round(bs["plans_per_s"] / bp["plans_per_s"], 2)
+                                  if bs and bp else None),
+            "note": "highest offered rate of the sweep at which the form's p99 stays within the "
+                    "SLO with every request completed; the server's top rate is a lower bound "
+                    "when it still meets the SLO there"}
 
 
 def headline_c3(P, W, args):
@@ -738,6 +791,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-plain-limit", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-sweep-requests", type=int, default=2048)
+    ap.add_argument("--serve-slo-ms", type=float, default=10.0)
+    ap.add_argument("--only-serve", action="store_true",
+                    help="run only the serving section (profiling runs)")
     ap.add_argument("--only-unfused", action="store_true",
                     help="run only the unfused-baseline section (profiling runs)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -767,6 +824,11 @@ def main():
     if args.only_unfused:
         print(json.dumps({"unfused_baseline": unfused_baseline(P, W, reps=2)}), flush=True)
         return
+    if args.only_serve:
+        print(json.dumps({"serving": serving(P, W, args.serve_requests, args.serve_plain_limit,
+                                             args.serve_sweep_requests, args.serve_slo_ms)}),
+              flush=True)
+        return
 
     h = headline_c3(P, W, args)
     wl = W.C3
@@ -788,7 +850,8 @@ def main():
 
     serve_line = None
     if not args.no_serve:
-        serve_line = serving(P, W, args.serve_requests, args.serve_plain_limit)
+        serve_line = serving(P, W, args.serve_requests, args.serve_plain_limit,
+                             args.serve_sweep_requests, args.serve_slo_ms)
         print("[bench] serving done", file=sys.stderr, flush=True)
 
     cpu = None
