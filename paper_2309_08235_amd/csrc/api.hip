@@ -809,7 +809,7 @@ int32_t priest_project_hist(priest_problem* p, const float* bc, const float* obs
 int32_t priest_project_unfused_workspace_size(const priest_problem* p, int32_t N, size_t* bytes) {
   if (!p || !bytes) return fail(PRIEST_ERR_INVALID, "problem and bytes are required");
   if (N < 0 || N > PRIEST_MAX_SAMPLES) return fail(PRIEST_ERR_INVALID, "N must be in [0, %d]", PRIEST_MAX_SAMPLES);
-  *bytes = unfused_layout(N, p->desc.n_steps, p->desc.dims, p->desc.n_coeff).total;
+  *bytes = unfused_layout(N, p->desc.n_steps, p->desc.dims, p->desc.n_coeff, p->desc.n_obs).total;
   return PRIEST_OK;
 }
 

@@ -2,17 +2,26 @@
 //
 // The same projection iteration (Appendix eqs. (15a)-(15g)) as three kernels
 // per iteration, every intermediate going through HBM, no MFMA, no culling:
-//   forward : p, v, a of every (sample, t)                 -> pva  [N][3][dims][K]
-//   push    : push-outs of every (sample, t), all obstacles -> delta [N][3][dims][K]
-//             (and |delta|^2 summed per item on the final pass)
+//   forward : p, v, a of every (sample, t)                 -> pva
+//   push    : push-outs of every (sample, t), all obstacles -> delta
+//             (and |delta|^2 per item on the final pass)
 //   update  : g = W^T delta per (sample, axis), lambda += rho g, QP step through
 //             the fixed KKT block (the same k = 0 full form / k > 0 increment
 //             form as the fused kernel)
 // followed after the last iteration by forward + push and a per-sample sum of
-// the residual and c1.  The obstacle loop of `push` is the elementwise pass
-// whose HBM throughput the benchmark reports.  Intermediates are laid out per
-// sample as [row type][axis][t], so consecutive threads (consecutive t) and
-// the update's lanes touch consecutive addresses.
+// the residual and c1.
+//
+// Intermediates are stored in tiles of 64 samples, sample-fastest inside a
+// tile: [tile][row type][t][sample in tile][axis] (r2: [tile][t][sample in
+// tile]), so that every pass streams consecutive addresses across
+// consecutive lanes and each wave walks one contiguous region: forward and
+// push take one sample per lane at a fixed t, and the update takes one
+// (sample, axis) row per lane (or per group of lanes for small batches) and
+// walks (row type, t), the same offset for every lane.  The operands a wave
+// applies are then the same for all its lanes and come through scalar
+// loads: W's rows (padded to 16 and ordered by (row type, t) in the
+// workspace), M11 and Pi, and the obstacles placed at the wave's step
+// (centre + velocity t dt, written per step into the workspace once per call).
 #include <algorithm>
 #include <type_traits>
 
@@ -21,163 +30,336 @@
 namespace priest {
 namespace {
 
-// Obstacle record of the push kernel (2D circles / 3D spheres and
-// ellipsoids): centre, velocity, a, a^2, 1/a^2, 1/b^2.
-struct ORec {
-  float cx, cy, cz, vx, vy, vz, a, a2, ia2, ib2;
-};
 
-// One thread per time step t (blockIdx.y picks a chunk of kFwdT steps); a
-// block runs through `spb` consecutive samples.  The thread keeps its three
-// basis rows in registers (entries c >= n_coeff zeroed), and a sample's
-// coefficients are block-uniform (staged in LDS as zero-padded rows of 16
-// and read as four 16-byte broadcasts per axis), so each sample costs
-// 3 dims coalesced row stores.
-constexpr int kFwdT = 128;
-constexpr int kFwdMaxSpb = 16;
+constexpr float kUfTiny = 1.0e-36f;
+// Added to the canonical component of every offset (x in 2D, z in 3D): below
+// half an ulp of any offset above about 2e-8, so those are unchanged; an
+// offset of exactly zero becomes 1e-15 along the canonical axis, whose
+// push-out is the semi-axis up to rounding (1e-30 / b^2 stays above the clamp
+// for semi-axes up to 1000).
+constexpr float kUfNudge = 1.0e-15f;
 
-__global__ __launch_bounds__(kFwdT) void uf_forward(const float* __restrict__ W,
-                                                    const float* __restrict__ xb, int N, int K,
-                                                    int nv, int dims, int spb,
-                                                    float* __restrict__ pva) {
-  const int t = blockIdx.y * kFwdT + threadIdx.x;
-  const bool live = t < K;
-  const int tc = live ? t : K - 1;
-  float w[3][kMaxNV];
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int c = 0; c < kMaxNV; ++c)
-      w[d][c] = W[(tc * 3 + d) * nv + (c < nv ? c : nv - 1)] * (c < nv ? 1.0f : 0.0f);
-  const int s0 = blockIdx.x * spb;
-  const int s1 = min(N, s0 + spb);
-  static_assert(kMaxNV == 16, "coefficient rows are staged as four float4");
-  __shared__ float4 sx[kFwdMaxSpb * 3 * 4];  // [sample][axis][16], zero-padded
-  for (int j = threadIdx.x; j < (s1 - s0) * dims * 16; j += kFwdT) {
-    const int k = j / (dims * 16), rem = j - k * dims * 16, ax = rem >> 4, c = rem & 15;
-    reinterpret_cast<float*>(sx)[j] =
-        c < nv ? xb[static_cast<int64_t>(s0 + k) * dims * nv + ax * nv + c] : 0.0f;
+constexpr int kUfTile = 64;  // samples per tile of the intermediates
+
+// pva / delta index of (row type d, step t, sample s, axis x).
+__device__ __forceinline__ int64_t soa(int d, int t, int s, int x, int K, int dims) {
+  const int tile = s / kUfTile, si = s - tile * kUfTile;
+  return ((static_cast<int64_t>(tile) * 3 * K + d * K + t) * kUfTile + si) * dims + x;
+}
+
+// One thread per sample and chunk of kFwdTC steps.  Blocks go to the 8 XCDs
+// in turn, so block b works on group 8 (b / 8 / n_chunk) + b % 8 of 256
+// samples, chunk (b / 8) % n_chunk: all chunks of a group run on one XCD
+// close together and read its coefficients through that XCD's L2.  The
+// sample's coefficients in registers; the chunk's W rows, staged in LDS as
+// rows of 16 (zero-padded), are the same for every lane of a wave.
+constexpr int kFwdTC = 10;
+
+template <int DIMS>
+__global__ __launch_bounds__(256) void uf_forward(const float* __restrict__ W,
+                                                  const float* __restrict__ xb, int N, int K,
+                                                  int nv, int n_chunk, float* __restrict__ pva) {
+  static_assert(kMaxNV == 16, "W rows are staged as four float4");
+  __shared__ float4 sw[kFwdTC * 3 * 4];
+  const int kb = blockIdx.x >> 3;
+  const int grp = (kb / n_chunk) * 8 + (blockIdx.x & 7), chunk = kb - (kb / n_chunk) * n_chunk;
+  if (grp * 256 >= N) return;
+  const int t0 = chunk * kFwdTC, nt = min(kFwdTC, K - t0);
+  for (int j = threadIdx.x; j < nt * 3 * 16; j += blockDim.x) {
+    const int row = j >> 4, c = j & 15;
+    reinterpret_cast<float*>(sw)[j] = c < nv ? W[(t0 * 3 + row) * nv + c] : 0.0f;
   }
   __syncthreads();
-  for (int s = s0; s < s1; ++s) {
-    const float4* x = sx + (s - s0) * dims * 4;
-    float* o = pva + static_cast<int64_t>(s) * 3 * dims * K + t;
+  const int s = grp * 256 + threadIdx.x;
+  if (s >= N) return;
+  float x[DIMS][kMaxNV];
+  const float* xs = xb + static_cast<int64_t>(s) * DIMS * nv;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      if (ax >= dims) break;
-      float xv[kMaxNV];
+  for (int ax = 0; ax < DIMS; ++ax)
+#pragma unroll
+    for (int c = 0; c < kMaxNV; ++c) x[ax][c] = c < nv ? xs[ax * nv + c] : 0.0f;
+#pragma unroll 2
+  for (int tl = 0; tl < nt; ++tl) {
+    const int t = t0 + tl;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float acc[DIMS];
+#pragma unroll
+      for (int ax = 0; ax < DIMS; ++ax) acc[ax] = 0.0f;
 #pragma unroll
       for (int c4 = 0; c4 < 4; ++c4) {
-        const float4 v = x[ax * 4 + c4];
-        xv[4 * c4] = v.x;
-        xv[4 * c4 + 1] = v.y;
-        xv[4 * c4 + 2] = v.z;
-        xv[4 * c4 + 3] = v.w;
+        const float4 w = sw[(tl * 3 + d) * 4 + c4];
+        const float wc[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+          for (int ax = 0; ax < DIMS; ++ax) acc[ax] = fmaf(wc[h], x[ax][4 * c4 + h], acc[ax]);
       }
+      float* o = pva + soa(d, t, s, 0, K, DIMS);
+      if constexpr (DIMS == 2) {
+        *reinterpret_cast<float2*>(o) = make_float2(acc[0], acc[1]);
+      } else {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int c = 0; c < kMaxNV; ++c) acc = fmaf(w[d][c], xv[c], acc);
-        if (live) o[(d * dims + ax) * K] = acc;
+        for (int ax = 0; ax < DIMS; ++ax) o[ax] = acc[ax];
       }
     }
   }
 }
 
-template <int DIMS, bool LAST>
-__global__ void uf_push(const float* __restrict__ pva, const float* __restrict__ obs, int N, int K,
-                        int M, float dt, float vmax, float amax, Box box,
-                        float* __restrict__ delta, float* __restrict__ r2out) {
-  extern __shared__ ORec orec[];
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    const float* o = obs + 8 * j;
-    const float a = o[6], b = (DIMS == 3) ? o[7] : o[6];
-    orec[j] = ORec{o[0], o[1], DIMS == 3 ? o[2] : 0.0f, o[3], o[4], DIMS == 3 ? o[5] : 0.0f,
-                   a, a * a, 1.0f / (a * a), 1.0f / (b * b)};
-  }
-  __syncthreads();
+// One thread per item (t, sample), consecutive samples in consecutive lanes.
+// Once per call: W's rows padded to 16 in (row type, t) order, and every
+// obstacle at every step, (centre + velocity t dt, a), then the shape terms
+// (a^2, 1/a^2, 1/b^2, 0) per obstacle.
+__global__ void uf_prep(const float* __restrict__ W, const float* __restrict__ obs, int K, int nv,
+                        int M, int dims, float dt, float* __restrict__ w16,
+                        float4* __restrict__ cen) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N * K) return;
-  const int sm = i / K, t = i - sm * K;
-  const float tt = dt * static_cast<float>(t);
-  const float* in = pva + static_cast<int64_t>(sm) * 3 * DIMS * K + t;
-  float p[DIMS], w[2][DIMS];
-  for (int x = 0; x < DIMS; ++x) {
-    p[x] = in[x * K];
-    w[0][x] = in[(DIMS + x) * K];
-    w[1][x] = in[(2 * DIMS + x) * K];
+  if (i < 3 * K * 16) {
+    const int e = i >> 4, c = i & 15, d = e / K, t = e - d * K;
+    w16[i] = c < nv ? W[(t * 3 + d) * nv + c] : 0.0f;
   }
+  if (i < K * M) {
+    const int t = i / M, j = i - t * M;
+    const float* o = obs + 8 * j;
+    const float tt = dt * static_cast<float>(t);
+    cen[i] = make_float4(fmaf(o[3], tt, o[0]), fmaf(o[4], tt, o[1]),
+                         dims == 3 ? fmaf(o[5], tt, o[2]) : 0.0f, o[6]);
+  }
+  if (i < M) {
+    const float* o = obs + 8 * i;
+    const float a = o[6], b = dims == 3 ? o[7] : o[6];
+    cen[static_cast<int64_t>(K) * M + i] = make_float4(a * a, 1.0f / (a * a), 1.0f / (b * b), 0.0f);
+  }
+}
+
+// One thread per item; a wave's 64 lanes share one step t (one tile row),
+// so its obstacles come from that step's row of `cen` through scalar loads.
+template <int DIMS, bool LAST>
+__global__ __launch_bounds__(256) void uf_push(const float* __restrict__ pva,
+                                               const float4* __restrict__ cen, int N, int K, int M,
+                                               float vmax, float amax, Box box,
+                                               float* __restrict__ delta,
+                                               float* __restrict__ r2out) {
+  // item i = (tile, t, sample in tile), the order of the intermediates
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per_tile = static_cast<int64_t>(K) * kUfTile;
+  const int tile = static_cast<int>(i / per_tile);
+  const int rem = static_cast<int>(i - tile * per_tile);
+  const int t = __builtin_amdgcn_readfirstlane(rem / kUfTile);  // the same in the whole wave
+  const int s = tile * kUfTile + (rem - (rem / kUfTile) * kUfTile);
+  const float4* oc = cen + static_cast<int64_t>(t) * M;
+  const float4* shp = cen + static_cast<int64_t>(K) * M;
+  if (s >= N) return;
+
+  float w[3][DIMS];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float* in = pva + soa(d, t, s, 0, K, DIMS);
+    if constexpr (DIMS == 2) {
+      const float2 v = *reinterpret_cast<const float2*>(in);
+      w[d][0] = v.x;
+      w[d][1] = v.y;
+    } else {
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) w[d][x] = in[x];
+    }
+  }
+  const float* p = w[0];
   float S[DIMS];
+#pragma unroll
   for (int x = 0; x < DIMS; ++x) S[x] = 0.0f;
   float r2 = 0.0f;
+#pragma unroll 4
   for (int j = 0; j < M; ++j) {
-    const ORec o = orec[j];
+    const float4 c = oc[j];
     float d[DIMS];
-    d[0] = p[0] - fmaf(o.vx, tt, o.cx);
-    d[1] = p[1] - fmaf(o.vy, tt, o.cy);
-    if constexpr (DIMS == 3) d[2] = p[2] - fmaf(o.vz, tt, o.cz);
+    d[0] = p[0] - c.x;
+    d[1] = p[1] - c.y;
+    if constexpr (DIMS == 3) d[2] = p[2] - c.z;
+    d[DIMS == 2 ? 0 : 2] += kUfNudge;
     const float h = fmaf(d[1], d[1], d[0] * d[0]);
     float q, f, len2;
     if constexpr (DIMS == 2) {
       q = h;
       len2 = h;
-      f = fmaf(o.a, __builtin_amdgcn_rsqf(fmaxf(q, 1.0e-30f)), -1.0f);
-      if (LAST) f = (q < o.a2) ? f : 0.0f;
+      f = fmaf(c.w, __builtin_amdgcn_rsqf(fmaxf(q, kUfTiny)), -1.0f);
+      if (LAST) f = (q < shp[j].x) ? f : 0.0f;
     } else {
-      q = fmaf(d[2] * d[2], o.ib2, h * o.ia2);
+      const float4 sh = shp[j];
+      q = fmaf(d[2] * d[2], sh.z, h * sh.y);
       len2 = fmaf(d[2], d[2], h);
-      f = __builtin_amdgcn_rsqf(fmaxf(q, 1.0e-30f)) - 1.0f;
+      f = __builtin_amdgcn_rsqf(fmaxf(q, kUfTiny)) - 1.0f;
       if (LAST) f = (q < 1.0f) ? f : 0.0f;
     }
     f = fmaxf(f, 0.0f);
+#pragma unroll
     for (int x = 0; x < DIMS; ++x) S[x] = fmaf(d[x], f, S[x]);
     if (LAST) r2 = fmaf(len2 * f, f, r2);
-    if (q == 0.0f) {  // canonical direction of a zero offset
-      if constexpr (DIMS == 2) {
-        S[0] += o.a;
-        if (LAST) r2 += o.a2;
-      } else {
-        const float bb = __builtin_amdgcn_rsqf(o.ib2);
-        S[2] += bb;
-        if (LAST) r2 = fmaf(bb, bb, r2);
-      }
-    }
   }
   if (box.on)  // workspace bounds: clamp(p, lo, hi) - p on the position rows
+#pragma unroll
     for (int x = 0; x < DIMS; ++x) {
       const float e = fminf(fmaxf(p[x], box.lo[x]), box.hi[x]) - p[x];
       S[x] += e;
       if (LAST) r2 = fmaf(e, e, r2);
     }
-  float* out = delta + static_cast<int64_t>(sm) * 3 * DIMS * K + t;
-  for (int x = 0; x < DIMS; ++x) out[x * K] = S[x];
+  float dl[3][DIMS];
+#pragma unroll
+  for (int x = 0; x < DIMS; ++x) dl[0][x] = S[x];
+#pragma unroll
   for (int k = 0; k < 2; ++k) {
     const float wm = k == 0 ? vmax : amax;
     float ww = 0.0f;
-    for (int x = 0; x < DIMS; ++x) ww = fmaf(w[k][x], w[k][x], ww);
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) ww = fmaf(w[k + 1][x], w[k + 1][x], ww);
     float f = 0.0f;
     if (ww > wm * wm) f = fmaf(wm, __builtin_amdgcn_rsqf(ww), -1.0f);
-    for (int x = 0; x < DIMS; ++x) out[((k + 1) * DIMS + x) * K] = w[k][x] * f;
-    if (LAST) r2 += ww * f * f;
+#pragma unroll
+    for (int x = 0; x < DIMS; ++x) dl[k + 1][x] = w[k + 1][x] * f;
+    if (LAST) r2 = fmaf(ww * f, f, r2);
   }
-  if (LAST) r2out[i] = r2;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float* out = delta + soa(d, t, s, 0, K, DIMS);
+    if constexpr (DIMS == 2) {
+      *reinterpret_cast<float2*>(out) = make_float2(dl[d][0], dl[d][1]);
+    } else {
+#pragma unroll
+      for (int x = 0; x < DIMS; ++x) out[x] = dl[d][x];
+    }
+  }
+  if (LAST) r2out[i] = r2;  // [tile][t][sample in tile]
 }
 
-// A group of `tpr` consecutive lanes (a power of two up to 64) per
-// (sample, axis) row: g = W^T delta over the row's 3K entries, lambda +=
-// rho g, and the QP step through the fixed KKT block.  The group streams
-// its three K-long delta rows in VW-wide loads, lane `sub` taking vectors
-// sub, sub + tpr, ... (consecutive lanes read consecutive addresses), and an
-// xor butterfly inside the group sums g; every lane of the group then
-// forms the step and lane 0 stores it.  W, M11 and Pi are staged in LDS with
-// rows zero-padded to 16 entries, so the per-row loops run to 16 without
-// conditions and entries c >= n_coeff stay zero.  tpr grows for small
-// batches so that enough lanes stream.
-constexpr int kUpdT = 128;
+// A group of `tpr` consecutive lanes (a power of two up to 16) per (sample,
+// axis) row: g = W^T delta over the row's 3K entries, lane `sub` of the
+// group taking entries sub, sub + tpr, ... (with one lane per row, each load
+// is coalesced across the wave), an xor butterfly summing the group's
+// partials; then lambda += rho g and the QP step through the fixed KKT
+// block, stored by the group's lane 0.  tpr grows for small batches so that
+// enough lanes stream.
+constexpr int kUpdT = 256;
 
-template <int VW>
-__global__ __launch_bounds__(kUpdT) void uf_update(const float* __restrict__ W,
+// The QP step of one (sample s, axis ax) row from its g: lambda += rho g and
+// xi_bar through the fixed KKT block (k = 0 full form, k > 0 increment form).
+__device__ __forceinline__ void uf_row_step(const float g[kMaxNV], int s, int ax, int nv, int dims,
+                                            float rho, int first, const float* __restrict__ M11,
+                                            const float* __restrict__ Pi,
+                                            const float* __restrict__ M12,
+                                            const float* __restrict__ bc,
+                                            const float* __restrict__ xi, float* __restrict__ xb,
+                                            float* __restrict__ lam) {
+  auto cl = [nv](int c) { return c < nv ? c : nv - 1; };
+  const int64_t base = static_cast<int64_t>(s) * dims * nv + ax * nv;
+  float u[kMaxNV], x0[kMaxNV], xo[kMaxNV], l[kMaxNV];
+#pragma unroll
+  for (int c = 0; c < kMaxNV; ++c) {
+    const bool in = c < nv;
+    x0[c] = in ? xi[base + cl(c)] : 0.0f;
+    xo[c] = in ? xb[base + cl(c)] : 0.0f;
+    l[c] = in ? lam[base + cl(c)] + rho * g[c] : 0.0f;
+    u[c] = in ? (first ? l[c] + rho * g[c] : (x0[c] - xo[c]) + l[c] + rho * g[c]) : 0.0f;
+  }
+  float bcv[6];
+  if (first)
+#pragma unroll
+    for (int e = 0; e < 6; ++e) bcv[e] = bc[ax * 6 + e];
+#pragma unroll
+  for (int r = 0; r < kMaxNV; ++r) {
+    if (r >= nv) break;
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kMaxNV; ++c) {
+      if (c >= nv) break;
+      acc = fmaf(M11[r * nv + c], u[c], acc);
+    }
+    float nx;
+    if (first) {
+      float h = 0.0f, c0 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < kMaxNV; ++c) {
+        if (c >= nv) break;
+        h = fmaf(Pi[r * nv + c], x0[c], h);
+      }
+#pragma unroll
+      for (int e = 0; e < 6; ++e) c0 = fmaf(M12[r * 6 + e], bcv[e], c0);
+      nx = (h + c0) + acc;
+    } else {
+      nx = xo[r] + acc;
+    }
+    lam[base + r] = l[r];
+    xb[base + r] = nx;
+  }
+}
+
+// Large batches: one block per `tiles` tiles of 64 samples (2 in 2D, 1 in
+// 3D: 256 or 192 rows (sample, axis)) x kUpdParts parts of the row's 3K
+// entries (a contiguous range per part), so that a launch is about one round
+// of resident blocks.  A wave holds 64 consecutive rows of one part, so each
+// entry is a 256-byte load across the wave and the same W row for every lane
+// (an LDS broadcast); the parts' partial g are summed
+// through LDS in part order and the first part's lanes take the QP step.
+constexpr int kUpdParts = 4;
+
+__global__ __launch_bounds__(1024) void uf_update_tile(
+    const float4* __restrict__ w16, const float* __restrict__ M11, const float* __restrict__ Pi,
+    const float* __restrict__ M12, const float* __restrict__ bc, const float* __restrict__ delta,
+    const float* __restrict__ xi, float* __restrict__ xb, float* __restrict__ lam, int N, int K,
+    int nv, int dims, float rho, int first, int tiles) {
+  extern __shared__ float4 swe[];  // [3K][16] W rows, then the partials [parts - 1][block rows][16]
+  const int E = 3 * K, trows = kUfTile * dims, rows = tiles * trows;
+  for (int j = threadIdx.x; j < E * 4; j += blockDim.x) swe[j] = w16[j];
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(swe + E * 4);
+  // (rows is a multiple of 64: every wave lies in one part)
+  const int part = threadIdx.x / rows, rl = threadIdx.x - part * rows;
+  const int tile = blockIdx.x * tiles + rl / trows, rt = rl - (rl / trows) * trows;
+  const int e_lo = (E * part) / kUpdParts, e_hi = (E * (part + 1)) / kUpdParts;
+  float g[kMaxNV];
+#pragma unroll
+  for (int c = 0; c < kMaxNV; ++c) g[c] = 0.0f;
+  // (a tile past the last sample, up to the layout's even tile count, only
+  // reads workspace and stores nothing)
+  const float* dl = delta + static_cast<int64_t>(tile) * E * trows + rt;
+  constexpr int kU = 16;  // loads in flight per lane
+  for (int e0 = e_lo; e0 < e_hi; e0 += kU) {
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u;
+      v[u] = e < e_hi ? dl[static_cast<int64_t>(e) * trows] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = min(e0 + u, e_hi - 1);  // (v = 0 past the end)
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const float4 w = swe[e * 4 + c4];
+        g[4 * c4 + 0] = fmaf(w.x, v[u], g[4 * c4 + 0]);
+        g[4 * c4 + 1] = fmaf(w.y, v[u], g[4 * c4 + 1]);
+        g[4 * c4 + 2] = fmaf(w.z, v[u], g[4 * c4 + 2]);
+        g[4 * c4 + 3] = fmaf(w.w, v[u], g[4 * c4 + 3]);
+      }
+    }
+  }
+  if (part > 0)
+#pragma unroll
+    for (int c = 0; c < kMaxNV; ++c) red[((part - 1) * rows + rl) * kMaxNV + c] = g[c];
+  __syncthreads();
+  if (part > 0) return;
+  for (int q = 1; q < kUpdParts; ++q)
+#pragma unroll
+    for (int c = 0; c < kMaxNV; ++c) g[c] += red[((q - 1) * rows + rl) * kMaxNV + c];
+  const int r = tile * trows + rt;
+  if (r >= N * dims) return;
+  uf_row_step(g, r / dims, r - (r / dims) * dims, nv, dims, rho, first, M11, Pi, M12, bc, xi, xb,
+              lam);
+}
+
+// Small batches: a group of `tpr` consecutive lanes (a power of two up to
+// 16) per (sample, axis) row, lane `sub` taking entries sub, sub + tpr, ...,
+// an xor butterfly summing the group's partials, W's rows from an LDS copy.
+__global__ __launch_bounds__(kUpdT) void uf_update(const float4* __restrict__ w16,
                                                    const float* __restrict__ M11,
                                                    const float* __restrict__ Pi,
                                                    const float* __restrict__ M12,
@@ -187,98 +369,45 @@ __global__ __launch_bounds__(kUpdT) void uf_update(const float* __restrict__ W,
                                                    float* __restrict__ xb, float* __restrict__ lam,
                                                    int N, int K, int nv, int dims, float rho,
                                                    int first, int tpr) {
-  static_assert(kMaxNV == 16, "LDS rows are padded to 16 entries");
-  extern __shared__ float4 sm4[];
-  float* sW = reinterpret_cast<float*>(sm4);  // [3K][16]
-  float* sM = sW + 3 * K * 16;                 // M11 [16][16]
-  float* sP = sM + 256;                        // Pi  [16][16]
-  for (int j = threadIdx.x; j < 3 * K * 16; j += kUpdT) {
-    const int row = j >> 4, c = j & 15;
-    sW[j] = c < nv ? W[row * nv + c] : 0.0f;
-  }
-  for (int j = threadIdx.x; j < 256; j += kUpdT) {
-    const int row = j >> 4, c = j & 15;
-    const bool in = row < nv && c < nv;
-    sM[j] = in ? M11[row * nv + c] : 0.0f;
-    sP[j] = in ? Pi[row * nv + c] : 0.0f;
-  }
+  extern __shared__ float4 swe[];  // [3K][16]: entry e = d K + t holds W's row (t, d)
+  for (int j = threadIdx.x; j < 3 * K * 4; j += kUpdT) swe[j] = w16[j];
   __syncthreads();
   const int tid = blockIdx.x * kUpdT + threadIdx.x;
-  const int rowi = tid / tpr, sub = tid - rowi * tpr;
-  if (rowi >= N * dims) return;  // whole groups leave together (tpr divides 64)
-  const int s = rowi / dims, ax = rowi - s * dims;
-  float g[16];
+  const int row = tid / tpr, sub = tid - row * tpr;
+  if (row >= N * dims) return;  // whole groups leave together (tpr divides 64)
+  const int s = row / dims, ax = row - s * dims;
+  float g[kMaxNV];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) g[c] = 0.0f;
-  const float* dl = delta + static_cast<int64_t>(s) * 3 * dims * K;
-  using VT = typename std::conditional<VW == 4, float4, typename std::conditional<VW == 2, float2, float>::type>::type;
+  for (int c = 0; c < kMaxNV; ++c) g[c] = 0.0f;
+  const float* dl = delta + soa(0, 0, s, ax, K, dims);  // entry (d, t) at + (d K + t) 64 dims
+  const int64_t step = static_cast<int64_t>(kUfTile) * dims;
+  const int E = 3 * K;
+  constexpr int kU = 16;  // loads in flight per lane
+  for (int e0 = sub; e0 < E; e0 += kU * tpr) {
+    float v[kU];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const VT* row = reinterpret_cast<const VT*>(dl + (d * dims + ax) * K);
-#pragma unroll 4
-    for (int q = sub; q < K / VW; q += tpr) {
-      const VT v = row[q];
-      const float* vv = reinterpret_cast<const float*>(&v);
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * tpr;
+      v[u] = e < E ? dl[e * step] : 0.0f;
+    }
 #pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        const float4* w4 = reinterpret_cast<const float4*>(sW + ((q * VW + e) * 3 + d) * 16);
+    for (int u = 0; u < kU; ++u) {
+      const int e = min(e0 + u * tpr, E - 1);  // (v = 0 past the end)
 #pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4) {
-          const float4 w = w4[c4];
-          g[4 * c4 + 0] = fmaf(w.x, vv[e], g[4 * c4 + 0]);
-          g[4 * c4 + 1] = fmaf(w.y, vv[e], g[4 * c4 + 1]);
-          g[4 * c4 + 2] = fmaf(w.z, vv[e], g[4 * c4 + 2]);
-          g[4 * c4 + 3] = fmaf(w.w, vv[e], g[4 * c4 + 3]);
-        }
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const float4 w = swe[e * 4 + c4];
+        g[4 * c4 + 0] = fmaf(w.x, v[u], g[4 * c4 + 0]);
+        g[4 * c4 + 1] = fmaf(w.y, v[u], g[4 * c4 + 1]);
+        g[4 * c4 + 2] = fmaf(w.z, v[u], g[4 * c4 + 2]);
+        g[4 * c4 + 3] = fmaf(w.w, v[u], g[4 * c4 + 3]);
       }
     }
   }
   for (int m = 1; m < tpr; m <<= 1)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) g[c] += __shfl_xor(g[c], m, 64);
-  auto cl = [nv](int c) { return c < nv ? c : nv - 1; };
-  const int64_t base = static_cast<int64_t>(s) * dims * nv + ax * nv;
-  float u[16], x0[16], xo[16], l[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const bool in = c < nv;
-    x0[c] = in ? xi[base + cl(c)] : 0.0f;
-    xo[c] = xb[base + cl(c)];
-    l[c] = lam[base + cl(c)] + rho * g[c];
-    u[c] = in ? (first ? l[c] + rho * g[c] : (x0[c] - xo[c]) + l[c] + rho * g[c]) : 0.0f;
-  }
-  float c0[16];
-  if (first) {
-    float bcv[6];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) bcv[e] = bc[ax * 6 + e];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      float a = 0.0f;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) a = fmaf(M12[cl(r) * 6 + e], bcv[e], a);
-      c0[r] = a;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc = fmaf(sM[r * 16 + c], u[c], acc);
-    float nx;
-    if (first) {
-      float h = 0.0f;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) h = fmaf(sP[r * 16 + c], x0[c], h);
-      nx = (h + c0[r]) + acc;
-    } else {
-      nx = xo[r] + acc;
-    }
-    if (r < nv && sub == 0) {
-      lam[base + r] = l[r];
-      xb[base + r] = nx;
-    }
-  }
+    for (int c = 0; c < kMaxNV; ++c) g[c] += __shfl_xor(g[c], m, 64);
+  if (sub != 0) return;
+  uf_row_step(g, s, ax, nv, dims, rho, first, M11, Pi, M12, bc, xi, xb, lam);
 }
 
 __global__ void uf_finish(const float* __restrict__ r2, const float* __restrict__ pva, int N, int K,
@@ -286,10 +415,11 @@ __global__ void uf_finish(const float* __restrict__ r2, const float* __restrict_
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
   float rr = 0.0f, cc = 0.0f;
+  const int tile = s / kUfTile, si = s - tile * kUfTile;
   for (int t = 0; t < K; ++t) {
-    rr += r2[static_cast<int64_t>(s) * K + t];
-    const float* a = pva + static_cast<int64_t>(s) * 3 * dims * K + 2 * dims * K + t;
-    for (int x = 0; x < dims; ++x) cc = fmaf(a[x * K], a[x * K], cc);
+    rr += r2[(static_cast<int64_t>(tile) * K + t) * kUfTile + si];
+    const float* a = pva + soa(2, t, s, 0, K, dims);
+    for (int x = 0; x < dims; ++x) cc = fmaf(a[x], a[x], cc);
   }
   if (resid) resid[s] = sqrtf(rr);
   if (c1) c1[s] = cc;
@@ -310,16 +440,20 @@ __global__ void uf_copy(const float* __restrict__ src, float* __restrict__ dst, 
 
 }  // namespace
 
-UnfusedLayout unfused_layout(int N, int K, int dims, int nv) {
+UnfusedLayout unfused_layout(int N, int K, int dims, int nv, int M) {
   auto al = [](size_t n) { return (n + 255) & ~static_cast<size_t>(255); };
   UnfusedLayout l{};
   size_t o = 0;
-  const size_t items = static_cast<size_t>(N) * K;
+  // tiles rounded up to even: a 2D update block reads two whole tiles
+  const size_t tiles = static_cast<size_t>(((N + kUfTile - 1) / kUfTile + 1) / 2 * 2);
+  const size_t items = tiles * kUfTile * K;
   l.pva = o;   o += al(sizeof(float) * items * 3 * dims);
   l.delta = o; o += al(sizeof(float) * items * 3 * dims);
   l.r2 = o;    o += al(sizeof(float) * items);
   l.xb = o;    o += al(sizeof(float) * static_cast<size_t>(N) * dims * nv);
   l.lam = o;   o += al(sizeof(float) * static_cast<size_t>(N) * dims * nv);
+  l.w16 = o;   o += al(sizeof(float) * 3 * K * 16);
+  l.cen = o;   o += al(sizeof(float) * 4 * (static_cast<size_t>(K) + 1) * M);
   l.total = o;
   return l;
 }
@@ -327,54 +461,62 @@ UnfusedLayout unfused_layout(int N, int K, int dims, int nv) {
 hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, float* resid,
                           float* c1, char* ws, hipStream_t s) {
   const int N = a.N, K = a.K, nv = a.nv, dims = a.dims, M = a.M;
-  const UnfusedLayout l = unfused_layout(N, K, dims, nv);
+  const UnfusedLayout l = unfused_layout(N, K, dims, nv, M);
   float* pva = reinterpret_cast<float*>(ws + l.pva);
   float* delta = reinterpret_cast<float*>(ws + l.delta);
   float* r2 = reinterpret_cast<float*>(ws + l.r2);
   float* xb = reinterpret_cast<float*>(ws + l.xb);
   float* lam = reinterpret_cast<float*>(ws + l.lam);
+  float* w16 = reinterpret_cast<float*>(ws + l.w16);
+  float4* cen = reinterpret_cast<float4*>(ws + l.cen);
   const int64_t nD = static_cast<int64_t>(N) * dims * nv;
-  const int items = N * K;
+  const int64_t items = static_cast<int64_t>((N + kUfTile - 1) / kUfTile) * kUfTile * K;
   const dim3 b256(256);
-  const dim3 g_items((items + 255) / 256);
-  // forward: blocks of kFwdT time steps over spb samples, about 2048+ blocks
-  const int spb = std::max(1, std::min(kFwdMaxSpb, N / 2048));
-  const dim3 g_fwd((N + spb - 1) / spb, (K + kFwdT - 1) / kFwdT), b_fwd(kFwdT);
-  // update: tpr lanes per (sample, axis) row, raised only until about 64k
-  // lanes stream (at most 16 per row: at N = 64000, 2D, one lane per row
-  // takes 98 us, two 102 us and four 109 us; at N = 1000 sixteen take 14 us
-  // against 52 us for one); W, M11 and Pi padded in LDS
+  const dim3 g_items(static_cast<unsigned>((items + 255) / 256));
+  const int n_chunk = (K + kFwdTC - 1) / kFwdTC, n_grp = (N + 255) / 256;
+  const dim3 g_fwd(static_cast<unsigned>(((n_grp + 7) / 8) * 8 * n_chunk));
+  // update: tpr lanes per (sample, axis) row, raised until about 64k lanes
+  // stream
   int tpr = 1;
   while (tpr < 16 && static_cast<int64_t>(N) * dims * tpr < (64 << 10)) tpr *= 2;
   const dim3 g_upd(static_cast<unsigned>((static_cast<int64_t>(N) * dims * tpr + kUpdT - 1) / kUpdT));
-  const dim3 b_upd(kUpdT);
-  const size_t lds_upd = sizeof(float) * (3 * K * 16 + 2 * 256);
+  const int ut = dims == 2 ? 2 : 1;  // tiles per update block: 1024 / 768 threads
+  const int n_tiles = (N + kUfTile - 1) / kUfTile;
+  const dim3 g_tiles(static_cast<unsigned>((n_tiles + ut - 1) / ut));
+  const size_t lds_tile =
+      sizeof(float) * (3 * K * 16 + (kUpdParts - 1) * ut * kUfTile * dims * kMaxNV);
   const dim3 g_nD(static_cast<unsigned>((nD + 255) / 256)), g_N((N + 255) / 256);
-  const size_t lds = sizeof(ORec) * (M > 0 ? M : 1);
+  const size_t lds_upd = sizeof(float) * 3 * K * 16;
+  const int n_prep = std::max(3 * K * 16, K * M);
+  hipLaunchKernelGGL(uf_prep, dim3((n_prep + 255) / 256), b256, 0, s, a.W, a.obs, K, nv, M, dims,
+                     a.dt, w16, cen);
   hipLaunchKernelGGL(uf_init, g_nD, b256, 0, s, xi_in, xb, lam, nD);
+  auto forward = [&]() {
+    if (dims == 2) hipLaunchKernelGGL(uf_forward<2>, g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+    else hipLaunchKernelGGL(uf_forward<3>, g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+  };
   auto push = [&](bool last) {
     if (dims == 2) {
-      if (last) hipLaunchKernelGGL((uf_push<2, true>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
-      else hipLaunchKernelGGL((uf_push<2, false>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
+      if (last) hipLaunchKernelGGL((uf_push<2, true>), g_items, b256, 0, s, pva, cen, N, K, M, a.vmax, a.amax, a.box, delta, r2);
+      else hipLaunchKernelGGL((uf_push<2, false>), g_items, b256, 0, s, pva, cen, N, K, M, a.vmax, a.amax, a.box, delta, r2);
     } else {
-      if (last) hipLaunchKernelGGL((uf_push<3, true>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
-      else hipLaunchKernelGGL((uf_push<3, false>), g_items, b256, lds, s, pva, a.obs, N, K, M, a.dt, a.vmax, a.amax, a.box, delta, r2);
+      if (last) hipLaunchKernelGGL((uf_push<3, true>), g_items, b256, 0, s, pva, cen, N, K, M, a.vmax, a.amax, a.box, delta, r2);
+      else hipLaunchKernelGGL((uf_push<3, false>), g_items, b256, 0, s, pva, cen, N, K, M, a.vmax, a.amax, a.box, delta, r2);
     }
   };
   for (int k = 0; k < a.n_iter; ++k) {
-    hipLaunchKernelGGL(uf_forward, g_fwd, b_fwd, 0, s, a.W, xb, N, K, nv, dims, spb, pva);
+    forward();
     push(false);
-    if (K % 4 == 0)
-      hipLaunchKernelGGL(uf_update<4>, g_upd, b_upd, lds_upd, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta,
-                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
-    else if (K % 2 == 0)
-      hipLaunchKernelGGL(uf_update<2>, g_upd, b_upd, lds_upd, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta,
-                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
+    if (tpr == 1)
+      hipLaunchKernelGGL(uf_update_tile, g_tiles, dim3(ut * kUfTile * dims * kUpdParts), lds_tile,
+                         s, reinterpret_cast<const float4*>(w16), a.M11, a.Pi, a.M12, a.bc, delta,
+                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, ut);
     else
-      hipLaunchKernelGGL(uf_update<1>, g_upd, b_upd, lds_upd, s, a.W, a.M11, a.Pi, a.M12, a.bc, delta,
+      hipLaunchKernelGGL(uf_update, g_upd, dim3(kUpdT), lds_upd, s,
+                         reinterpret_cast<const float4*>(w16), a.M11, a.Pi, a.M12, a.bc, delta,
                          xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
   }
-  hipLaunchKernelGGL(uf_forward, g_fwd, b_fwd, 0, s, a.W, xb, N, K, nv, dims, spb, pva);
+  forward();
   push(true);
   hipLaunchKernelGGL(uf_finish, g_N, b256, 0, s, r2, pva, N, K, dims, resid, c1);
   hipLaunchKernelGGL(uf_copy, g_nD, b256, 0, s, xb, xi_out, nD);
