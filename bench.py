@@ -795,6 +795,8 @@ def main():
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
     ap.add_argument("--only-serve", action="store_true",
                     help="run only the serving section (profiling runs)")
+    ap.add_argument("--only-c2", action="store_true",
+                    help="run only the single 2D plan section (profiling runs)")
     ap.add_argument("--only-unfused", action="store_true",
                     help="run only the unfused-baseline section (profiling runs)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -823,6 +825,11 @@ def main():
         del src, dst
     if args.only_unfused:
         print(json.dumps({"unfused_baseline": unfused_baseline(P, W, reps=2)}), flush=True)
+        return
+    if args.only_c2:
+        c2 = single_plan_c2(P, W, args)
+        print(json.dumps({"c2_single_plan": c2["section"], "mixed_precision": c2["mixed"]}),
+              flush=True)
         return
     if args.only_serve:
         print(json.dumps({"serving": serving(P, W, args.serve_requests, args.serve_plain_limit,
