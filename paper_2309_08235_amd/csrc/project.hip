@@ -191,6 +191,7 @@ __device__ __forceinline__ void row_max4(float v, float out[4]) {
 
 struct Rec {  // one obstacle record held in (uniform) registers
   float cx, cy, cz, vx, vy, vz, a, a2, ia2, ib2;
+  float mab;  // smaller semi-axis (3D; read only for clearance bounds)
   bool moving;
 };
 
@@ -270,6 +271,7 @@ template <int DIMS>
 struct PairTerm {
   float d[DIMS];
   float f, len2;
+  float sq;  // sqrt(q) from the same rsq (for clearance bounds; unused otherwise)
 };
 
 // Added to the canonical component of every offset (x in 2D, z in 3D): it is
@@ -298,16 +300,32 @@ __device__ __forceinline__ PairTerm<DIMS> pair_term(const Rec& o, float tt, cons
   if constexpr (DIMS == 2) {
     q = h;
     r.len2 = h;
-    f = fmaf(o.a, rsq(fmaxf(q, kTiny)), -1.0f);
+    const float rq = rsq(fmaxf(q, kTiny));
+    f = fmaf(o.a, rq, -1.0f);
+    r.sq = q * rq;
     if (LAST) f = (q < o.a2) ? f : 0.0f;
   } else {
     q = fmaf(r.d[2] * r.d[2], o.ib2, h * o.ia2);
     r.len2 = fmaf(r.d[2], r.d[2], h);
-    f = rsq(fmaxf(q, kTiny)) - 1.0f;
+    const float rq = rsq(fmaxf(q, kTiny));
+    f = rq - 1.0f;
+    r.sq = q * rq;
     if (LAST) f = (q < 1.0f) ? f : 0.0f;
   }
   r.f = fmaxf(f, 0.0f);
   return r;
+}
+
+// Lower bound on how far (Euclidean) the item may move before this pair's
+// push-out, as the kernel computes it, can become nonzero: the push is zero
+// while the scaled distance sqrt(q) (|d| / a in 2D) stays >= 1 + 1e-5, where
+// the rounding of q, rsq and the factor cannot make f positive; the scaled
+// distance changes by at most |move| / (smaller semi-axis); sqrt(q) from the
+// rsq is taken 1e-6 low.  Negative inside that margin.
+template <int DIMS>
+__device__ __forceinline__ float pair_clearance(const Rec& o, const PairTerm<DIMS>& t) {
+  if constexpr (DIMS == 2) return fmaf(t.sq, 0.999999f, -1.00001f * o.a);
+  return fmaf(t.sq, 0.999999f, -1.00001f) * o.mab;
 }
 
 // ACC: also accumulate the squared push-out length into r2.
@@ -336,6 +354,8 @@ __device__ __forceinline__ Rec rec_of_lane(const float4& R0, const float4& R1, c
   r.a2 = lane_f(R2.y, b);
   r.ia2 = (DIMS == 3) ? lane_f(R2.z, b) : 0.0f;
   r.ib2 = (DIMS == 3) ? lane_f(R2.w, b) : 0.0f;
+  // (3D keeps b = rsq(1/b^2) in place of a^2)
+  r.mab = (DIMS == 3) ? fminf(lane_f(R2.x, b), r.a2) : r.a;
   return r;
 }
 
@@ -1273,10 +1293,12 @@ __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* task
 // of two MFMA evaluations, less the max|Delta| of every iteration since.
 // While it is positive the row type's push-outs are exactly zero on every
 // valid item, as a full evaluation would find: its forward MFMAs, bound
-// checks and right-hand side are skipped.  Positions with obstacle
-// candidates are always evaluated; when a position budget runs out the
-// items are checked against the grown boxes, and the cache is rebuilt only
-// if one has left its box.
+// checks and right-hand side are skipped.  A position budget is the smaller
+// of the items' margin to the grown boxes and their clearance to every
+// candidate obstacle (pair_clearance, over sqrt(dims)), and exists only
+// while no position push-out is nonzero; when it runs out the items are
+// checked against the grown boxes, and the cache is rebuilt only if one has
+// left its box.
 //
 // The arithmetic per sample is that of the time-split shape: the same
 // product chains per 16-step block (operands swapped in the forward rows,
@@ -1443,7 +1465,9 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
 // candidate cache.  With `test`, every valid item is first checked against
 // its row's grown box: the cache is rebuilt if one is outside (or there is no
 // cache yet, ncand = ~0), and pmargin receives the smallest distance per axis
-// from a valid item to its grown box (slack after a rebuild).  Items that are not valid
+// from a valid item to its grown box (slack after a rebuild); lclear (per
+// lane) takes the smallest clearance of its valid items to the candidates
+// (pair_clearance; not in the final pass).  Items that are not valid
 // still get finite push-outs, which the caller masks where they matter
 // (steps past the horizon meet zero W rows in the right-hand side; columns of
 // absent samples are never written out).  Returns which row types have a
@@ -1459,7 +1483,8 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
                                                     float dv[NI][DIMS], float da[NI][DIMS],
                                                     float r2[NI], int lane, uint32_t* cw,
                                                     uint32_t& ncand, uint32_t nok, uint32_t& pairs,
-                                                    float& wwv, float& wwa, float& pmargin) {
+                                                    float& wwv, float& wwa, float& pmargin,
+                                                    float& lclear) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
@@ -1521,14 +1546,22 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
           const Rec o = rec_of_lane<DIMS, false>(R0, R1, R2, __builtin_ctzll(ms));
           ms &= ms - 1;
 #pragma unroll
-          for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, false>(o, tt_[i], p[i]), S[i], r2[i]);
+          for (int i = 0; i < NI; ++i) {
+            const PairTerm<DIMS> pt = pair_term<DIMS, LAST, false>(o, tt_[i], p[i]);
+            pair_add<DIMS, LAST>(o, pt, S[i], r2[i]);
+            if (!LAST) lclear = fminf(lclear, ok[i] ? pair_clearance<DIMS>(o, pt) : INFINITY);
+          }
         }
         unsigned long long mm = mvmask;
         while (mm) {
           const Rec o = rec_of_lane<DIMS, true>(R0, R1, R2, __builtin_ctzll(mm));
           mm &= mm - 1;
 #pragma unroll
-          for (int i = 0; i < NI; ++i) pair_add<DIMS, LAST>(o, pair_term<DIMS, LAST, true>(o, tt_[i], p[i]), S[i], r2[i]);
+          for (int i = 0; i < NI; ++i) {
+            const PairTerm<DIMS> pt = pair_term<DIMS, LAST, true>(o, tt_[i], p[i]);
+            pair_add<DIMS, LAST>(o, pt, S[i], r2[i]);
+            if (!LAST) lclear = fminf(lclear, ok[i] ? pair_clearance<DIMS>(o, pt) : INFINITY);
+          }
         }
       }
     }
@@ -1769,7 +1802,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
     auto block_items = [&](int tb, uint32_t comp, bool test, uint32_t& ncand, auto last_tag,
                            float p[NI][DIMS], float v[NI][DIMS], float ac[NI][DIMS],
                            float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
-                           bool ok[NI], float& wwv, float& wwa, float& pm) {
+                           bool ok[NI], float& wwv, float& wwa, float& pm, float& lcl) {
       constexpr bool LAST = decltype(last_tag)::value;
       const float4* wt = wtab + tb * kWtabV4 * 64 + lane;
       f4 Y0 = zf, Y1 = zf, Y2 = zf;
@@ -1819,7 +1852,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
       return wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
                                              comp, test, ok, p, v, ac, a.vmax, a.amax, a.box, S,
                                              dv, da, r2, lane, cwords + tb * cstride, ncand, nok,
-                                             pairs, wwv, wwa, pm);
+                                             pairs, wwv, wwa, pm, lcl);
     };
 
     // ---- projection iterations ---------------------------------------------------
@@ -1848,17 +1881,28 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
         const bool test = (mP & bit) != 0u;
         uint32_t comp = ((mV & bit) ? 2u : 0u) | ((mA & bit) ? 4u : 0u);
-        if (test || ncand || a.box.on) comp |= 1u;
+        // (while the position budget lasts, every valid item is inside its
+        // grown box and clear of every candidate: no obstacle can push)
+        if (test || a.box.on) comp |= 1u;
         f4 part = zf;
         if (comp) {
           float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
           bool ok[NI];
-          float wwv = 0.0f, wwa = 0.0f, pm = 0.0f;
+          float wwv = 0.0f, wwa = 0.0f, pm = 0.0f, lcl = INFINITY;
           const uint32_t nz = block_items(tb, comp, test, ncand, std::false_type{}, p, v, ac, S, dv,
-                                          da, r2, ok, wwv, wwa, pm);
-          // new budgets of the row types evaluated here
+                                          da, r2, ok, wwv, wwa, pm, lcl);
+          // new budgets of the row types evaluated here; the position budget
+          // is the smaller of the grown-box margin (per axis) and the
+          // candidates' clearance (Euclidean, over sqrt(dims)), or none while
+          // some position push-out is nonzero
           if (test) {
-            const float bp = budget(pm * a.bscale[0]);
+            float bp = -1.0f;
+            if (!(nz & 1u)) {
+              float cl = INFINITY;
+              if (ncand) cl = wave_reduce_nn<false>(__uint_as_float(__float_as_uint(fmaxf(lcl, 0.0f)) & 0x7fffffffu));
+              const float m = fminf(pm, cl * (DIMS == 3 ? 0.57735026f : 0.70710678f));
+              if (m > 0.0f) bp = budget(m * a.bscale[0]);
+            }
             Bp = lane == tb ? bp : Bp;
             ncl = lane == tb ? ncand : ncl;
           }
@@ -1994,9 +2038,9 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
       float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
       bool ok[NI];
       uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
-      float wwv = 0.0f, wwa = 0.0f, pm = 0.0f;
+      float wwv = 0.0f, wwa = 0.0f, pm = 0.0f, lcl = INFINITY;
       block_items(tb, 7u, (mP >> tb) & 1u, ncand, std::true_type{}, p, v, ac, S, dv, da, r2, ok, wwv,
-                  wwa, pm);
+                  wwa, pm, lcl);
       // per-(t, sample) residual^2 and cost through this wave's planes
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
