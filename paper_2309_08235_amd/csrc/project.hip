@@ -20,8 +20,8 @@
 //             velocity / acceleration push-outs w * min(0, w_max/|w| - 1)
 //   transpose back to the column layout
 //   RHS       g_partial = W^T delta per 16-step block (MFMA, the sum over t
-//             is the MFMA reduction); the partials of all blocks summed
-//             through LDS in one fixed pairwise order (one barrier)
+//             is the MFMA reduction); the partials of all blocks added in
+//             time-block order through LDS (one barrier)
 //   update    lambda += rho g (eq. (15e)); QP of eq. (15g) through the fixed
 //             KKT block, redone identically by every wave (MFMA):
 //               k = 0 : xi_bar = Pi xi + c0 + M11 (lambda + rho g)
@@ -35,7 +35,7 @@
 //
 // Tile shapes (AS, RT) and the persistent grid change only which lanes and
 // blocks do the work: every sample goes through the same operations in the
-// same order (per-column MFMA, per-16-step partials in one pairwise tree,
+// same order (per-column MFMA, per-16-step partials added in time-block order,
 // culled obstacles contribute exact zeros), so every shape gives bit-identical
 // results and the autotuner may pick any of them.
 #include "priest_internal.h"
@@ -106,7 +106,7 @@ struct Layout {  // offsets into dynamic LDS, in floats
 // cm: per-wave obstacle candidate masks (4 words per 64 obstacles); xs: the
 // block's samples; mu/L/z: sampler staging.  NB = 16-step blocks of the
 // launch, SPB = samples per block.
-// MB: partial slots per buffer, the power of two >= NB the sum tree runs over
+// MB: partial slots per buffer, a compile-time bound >= NB for the sum
 // (slots NB..MB-1 hold zeros).
 __host__ __device__ inline Layout layout(int dims, int nv, int M, int NB, int MB, int SPB, int mode) {
   Layout l{};
@@ -1087,29 +1087,14 @@ __device__ __forceinline__ void project_block(const ProjArgs& a, int first, int 
           *reinterpret_cast<f4*>(gp + (w * RT + rt) * 256 + lane * 4) = G[rt];
       }
       __syncthreads();
-      // g = sum of the NB block partials, in the pairwise order of a balanced
-      // tree over MB slots (empty slots are zero, which leaves every partial
-      // sum unchanged): a running stack of subtree sums, one level per bit.
-      f4 g;
-      {
-        const f4 zg = {0.0f, 0.0f, 0.0f, 0.0f};
-        f4 lvl[6];
+      // g = +0 + the block partials added one by one in time-block order
+      // (slots NB..MB-1 hold +0, which leaves the sum unchanged).  No partial
+      // is -0 (its MFMA chains start at +0), so neither is any sum, and a
+      // partial of exact zeros leaves the sum as it is: the whole-horizon
+      // shape adds only its nonzero partials and gets the same bits.
+      f4 g = {0.0f, 0.0f, 0.0f, 0.0f};
   #pragma unroll
-        for (int b = 0; b < MB; ++b) {
-          f4 v = zg;
-          v = *reinterpret_cast<const f4*>(gp + b * 256 + lane * 4);
-  #pragma unroll
-          for (int e = 0; e < 6; ++e) {
-            if ((b >> e) & 1) {
-              v = lvl[e] + v;
-            } else {
-              lvl[e] = v;
-              break;
-            }
-          }
-          if (b == MB - 1) g = v;
-        }
-      }
+      for (int b = 0; b < MB; ++b) g = g + *reinterpret_cast<const f4*>(gp + b * 256 + lane * 4);
       if constexpr (HIST) {
         // ||F xi_bar^k - e^{k+1}|| per sample, summed over t in order
         if (tid < ns) {
@@ -1303,7 +1288,7 @@ __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* task
 // The arithmetic per sample is that of the time-split shape: the same
 // product chains per 16-step block (operands swapped in the forward rows,
 // the same products in the same order), the per-block partial right-hand
-// sides summed in the same pairwise tree over 8 slots, the same push-out,
+// sides added in the same time-block order, the same push-out,
 // multiplier and KKT steps, and the residual and cost summed in t order.
 // ---------------------------------------------------------------------------
 constexpr int kWaveMaxBlocks = 8;  // 16-step time blocks (n_steps <= 128)
@@ -1858,24 +1843,10 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
     // ---- projection iterations ---------------------------------------------------
     for (int k = 0; k < a.n_iter; ++k) {
       const bool lowp = BF16 && (k < a.bf16_iters);
-      f4 lvl[3] = {zf, zf, zf};
+      // right-hand side: the nonzero block partials added to +0 in time-block
+      // order, the sum of the time-split shape (an all-zero partial leaves it
+      // unchanged)
       f4 g = zf;
-      // per-block partial right-hand sides into the pairwise tree over 8
-      // slots, as a running stack (slots past the horizon hold zeros)
-      auto tree = [&](int b, f4 part) {
-        if (b & 1) {
-          part = lvl[0] + part;
-          if (b & 2) {
-            part = lvl[1] + part;
-            if (b & 4) g = lvl[2] + part;
-            else lvl[2] = part;
-          } else {
-            lvl[1] = part;
-          }
-        } else {
-          lvl[0] = part;
-        }
-      };
       for (int tb = 0; tb < NB; ++tb) {
         const uint32_t bit = 1u << tb;
         uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
@@ -1884,7 +1855,6 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         // (while the position budget lasts, every valid item is inside its
         // grown box and clear of every candidate: no obstacle can push)
         if (test || a.box.on) comp |= 1u;
-        f4 part = zf;
         if (comp) {
           float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
           bool ok[NI];
@@ -1919,6 +1889,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
           // accumulator that starts at +0 is unchanged by adding them, so
           // skipping them leaves the partial bit for bit as in the full chains.
           if (nz) {
+            f4 part;
             const float (*src[3])[DIMS] = {S, dv, da};
 #pragma unroll
             for (int d = 0; d < 3; ++d)
@@ -1962,11 +1933,10 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
                 }
               part = acc0 + acc1;
             }
+            g = g + part;
           }
         }
-        tree(tb, part);
       }
-      for (int tb = NB; tb < kWaveMaxBlocks; ++tb) tree(tb, zf);
       lam += rho * g;
       const f4 xold = xb;
       if (k == 0) {

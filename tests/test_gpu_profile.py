@@ -59,10 +59,20 @@ def test_pair_count_exact_when_obstacles_cover_or_avoid_everything(P, wl, N):
     big[:, :3] = 5.0
     big[:, 0] = 1025.0
     big[:, 6:8] = 1e3
-    want = N * wl.n_steps * wl.n_obs * (n_iter + 1)
+    per_pass = N * wl.n_steps * wl.n_obs
+    want = per_pass * (n_iter + 1)
     for c in prob.tiling_candidates():
         prob.set_tiling(c)
-        assert _count(P, prob, bc, big, xi, n_iter) == want, c
+        n = _count(P, prob, bc, big, xi, n_iter)
+        if c[1] != 0:
+            # time-split shapes evaluate every candidate pair on every pass
+            assert n == want, c
+        else:
+            # the whole-horizon shape evaluates a block's positions on the
+            # first pass, the final pass, and when its position budget (the
+            # items' clearance to the candidates, here about 15 m) runs out;
+            # every evaluation covers all M candidates of the block's items
+            assert 2 * per_pass <= n <= want and n % wl.n_obs == 0, (c, n, want)
     # bounded by the brute-force count on the real scene (which may cull
     # every pair); off means no count
     prob.set_tiling(None)
