@@ -359,6 +359,33 @@ __device__ __forceinline__ Rec rec_of_lane(const float4& R0, const float4& R1, c
   return r;
 }
 
+// Record j read from the LDS table by every lane of the wave (j the same in
+// all of them: a broadcast), with only the fields the push-out of a
+// DIMS-dimensional, static or moving obstacle reads: the same values as
+// rec_of_lane.
+template <int DIMS, bool MOVING>
+__device__ __forceinline__ Rec rec_at(const float4* rec, int M, int j) {
+  const float4 R0 = rec[j], R2 = rec[2 * M + j];
+  Rec r;
+  r.moving = MOVING;
+  r.cx = R0.x;
+  r.cy = R0.y;
+  r.cz = (DIMS == 3) ? R0.z : 0.0f;
+  r.vx = r.vy = r.vz = 0.0f;
+  if constexpr (MOVING) {
+    const float4 R1 = rec[M + j];
+    r.vx = R1.x;
+    r.vy = R1.y;
+    r.vz = (DIMS == 3) ? R1.z : 0.0f;
+  }
+  r.a = (DIMS == 2) ? R2.x : 0.0f;
+  r.a2 = R2.y;
+  r.ia2 = (DIMS == 3) ? R2.z : 0.0f;
+  r.ib2 = (DIMS == 3) ? R2.w : 0.0f;
+  r.mab = (DIMS == 3) ? fminf(R2.x, R2.y) : R2.x;
+  return r;
+}
+
 // Canonical push-out of a zero offset (+x by a in 2D, +z by b in 3D).
 template <int DIMS, bool LAST>
 __device__ __forceinline__ void zero_push(const Rec& o, float s[DIMS], float& r2) {
@@ -1523,12 +1550,9 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
         const unsigned long long cmask = u64(m4.x, m4.y);
         if (!cmask) continue;
         const unsigned long long mvmask = u64(m4.z, m4.w);
-        const int j = 64 * g + lane;
-        const int jc = j < M ? j : M - 1;
-        const float4 R0 = rec[jc], R1 = rec[M + jc], R2 = rec[2 * M + jc];
         unsigned long long ms = cmask & ~mvmask;
         while (ms) {
-          const Rec o = rec_of_lane<DIMS, false>(R0, R1, R2, __builtin_ctzll(ms));
+          const Rec o = rec_at<DIMS, false>(rec, M, 64 * g + __builtin_ctzll(ms));
           ms &= ms - 1;
 #pragma unroll
           for (int i = 0; i < NI; ++i) {
@@ -1539,7 +1563,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
         }
         unsigned long long mm = mvmask;
         while (mm) {
-          const Rec o = rec_of_lane<DIMS, true>(R0, R1, R2, __builtin_ctzll(mm));
+          const Rec o = rec_at<DIMS, true>(rec, M, 64 * g + __builtin_ctzll(mm));
           mm &= mm - 1;
 #pragma unroll
           for (int i = 0; i < NI; ++i) {
