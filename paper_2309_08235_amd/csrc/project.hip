@@ -1476,15 +1476,17 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
 // valid item and are left at zero.  Position push-outs use the block's
 // candidate cache.  With `test`, every valid item is first checked against
 // its row's grown box: the cache is rebuilt if one is outside (or there is no
-// cache yet, ncand = ~0), and pmargin receives the smallest distance per axis
-// from a valid item to its grown box (slack after a rebuild); lclear (per
-// lane) takes the smallest clearance of its valid items to the candidates
-// (pair_clearance; not in the final pass).  Items that are not valid
+// cache yet, ncand = ~0), and pmargin (per lane) receives the smallest
+// distance per axis from its valid items to its row's grown box (slack after
+// a rebuild); lclear (per lane) takes the smallest clearance of its valid
+// items to the candidates (pair_clearance; not in the final pass).  Items
+// that are not valid
 // still get finite push-outs, which the caller masks where they matter
 // (steps past the horizon meet zero W rows in the right-hand side; columns of
 // absent samples are never written out).  Returns which row types have a
 // nonzero push-out on some valid item; wwv / wwa receive the largest |v|^2 /
-// |a|^2 over the valid items (not in the final pass).
+// |a|^2 over the valid items when that row type has none (not in the final
+// pass).
 template <int DIMS, bool LAST, int NI>
 __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, float tt, float tmid,
                                                     float thalf, float slack, uint32_t comp,
@@ -1528,7 +1530,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
           }
         rebuild = __ballot(out) != 0ull;
         // (every valid distance is >= 0 here; the mask turns -0 into +0)
-        if (!rebuild) pmargin = wave_reduce_nn<false>(__uint_as_float(__float_as_uint(mu) & 0x7fffffffu));
+        if (!rebuild) pmargin = __uint_as_float(__float_as_uint(mu) & 0x7fffffffu);
       }
       if (rebuild) {
         ncand = wave_block_cull<DIMS, NI>(rec, M, p, ok, tmid, thalf, slack, lane, cw);
@@ -1592,8 +1594,9 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
       any = any | (ok[i] & (ww[i] > wmax * wmax));
       m = ok[i] ? fmaxf(m, ww[i]) : m;
     }
-    if (!LAST) wwm = wave_reduce_nn<true>(m);
-    if (__ballot(any) != 0ull) {
+    if (__ballot(any) == 0ull) {
+      if (!LAST) wwm = wave_reduce_nn<true>(m);
+    } else {
       nz |= bit;
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
@@ -1892,9 +1895,14 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
           if (test) {
             float bp = -1.0f;
             if (!(nz & 1u)) {
-              float cl = INFINITY;
-              if (ncand) cl = wave_reduce_nn<false>(__uint_as_float(__float_as_uint(fmaxf(lcl, 0.0f)) & 0x7fffffffu));
-              const float m = fminf(pm, cl * (DIMS == 3 ? 0.57735026f : 0.70710678f));
+              // (one reduction of both: rounding is monotone, so the smallest
+              // scaled clearance is the smallest clearance scaled)
+              float lm = pm;
+              if (ncand) {
+                const float c = fmaxf(lcl, 0.0f) * (DIMS == 3 ? 0.57735026f : 0.70710678f);
+                lm = fminf(lm, __uint_as_float(__float_as_uint(c) & 0x7fffffffu));
+              }
+              const float m = wave_reduce_nn<false>(lm);
               if (m > 0.0f) bp = budget(m * a.bscale[0]);
             }
             Bp = lane == tb ? bp : Bp;
