@@ -1874,7 +1874,12 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
       // order, the sum of the time-split shape (an all-zero partial leaves it
       // unchanged)
       f4 g = zf;
-      for (int tb = 0; tb < NB; ++tb) {
+      // (the blocks with a row type to evaluate, in ascending order; the
+      // others add nothing)
+      uint32_t todo = a.box.on ? blocks : (mP | mV | mA);
+      while (todo) {
+        const int tb = __builtin_ctz(todo);
+        todo &= todo - 1u;
         const uint32_t bit = 1u << tb;
         uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
         const bool test = (mP & bit) != 0u;
