@@ -1517,18 +1517,22 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
         const float4 glo = *reinterpret_cast<const float4*>(bx);
         const float4 ghi = *reinterpret_cast<const float4*>(bx + 4);
         const float gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
-        bool out = false;
+        // smallest signed distance of a valid item to its box, NaN if any is
+        // (IEEE minimum: NaN-propagating), so an item is outside or not a
+        // number exactly when the margin is not >= 0
         float mu = INFINITY;
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
+        for (int i = 0; i < NI; ++i) {
+          float mi = INFINITY;
 #pragma unroll
           for (int x = 0; x < DIMS; ++x) {
             const int xx = (DIMS == 3 || x < 2) ? x : 2;
-            const float d0 = p[i][x] - gl[xx], d1 = gh[xx] - p[i][x];
-            out = out | (ok[i] & !((d0 >= 0.0f) & (d1 >= 0.0f)));
-            mu = fminf(mu, ok[i] ? fminf(d0, d1) : INFINITY);
+            mi = __builtin_elementwise_minimum(
+                mi, __builtin_elementwise_minimum(p[i][x] - gl[xx], gh[xx] - p[i][x]));
           }
-        rebuild = __ballot(out) != 0ull;
+          mu = ok[i] ? __builtin_elementwise_minimum(mu, mi) : mu;
+        }
+        rebuild = __ballot(!(mu >= 0.0f)) != 0ull;
         // (every valid distance is >= 0 here; the mask turns -0 into +0)
         if (!rebuild) pmargin = __uint_as_float(__float_as_uint(mu) & 0x7fffffffu);
       }
