@@ -70,6 +70,39 @@ def test_projection_identical_across_tilings(P, label, wl, changes, N, precision
     prob.close()
 
 
+NONFINITE = [
+    # (label, workload, N, index of the sample made non-finite)
+    ("3d k100 m128", W.C3, 37, 5),
+    ("2d k100 m50", W.C2, 45, 9),
+]
+
+
+@pytest.mark.parametrize("label,wl,N,bad", NONFINITE, ids=[c[0] for c in NONFINITE])
+def test_nonfinite_sample_leaves_the_others_unchanged(P, label, wl, N, bad):
+    """A NaN coefficient in one sample: the samples that share its wave and
+    tile get the same results, bit for bit, as without it (each sample's
+    projection is independent of the others; with a NaN in the wave every
+    skipping budget is NaN, so nothing is skipped, while the finite run
+    skips), in every tile shape; the NaN sample's own result is not finite."""
+    say(f"tilings: non-finite sample {bad} of {N}, {label}")
+    prob = P.Problem.from_workload(wl)
+    bc, obs = W.scene(wl, 0)
+    xi = W.samples(wl, 13, n=N).astype(np.float32)
+    xin = xi.copy()
+    xin[bad, 3] = np.nan
+    keep = np.arange(N) != bad
+    for c in prob.tiling_candidates():
+        prob.set_tiling(c)
+        a = prob.project(t32(bc), t32(obs), t32(xi), 20)
+        b = prob.project(t32(bc), t32(obs), t32(xin), 20)
+        torch.cuda.synchronize()
+        for want, got in zip(a, b):
+            want, got = want.cpu().numpy(), got.cpu().numpy()
+            np.testing.assert_array_equal(got[keep], want[keep], err_msg=f"tiling {c}")
+        assert not np.all(np.isfinite(b[0].cpu().numpy()[bad])), f"tiling {c}"
+    prob.close()
+
+
 def test_packed_2d_tiling_matches_oracle(P):
     say("tilings: 8-samples-per-block shape vs the oracle (C2 scene, N=77)")
     w = W.C2
