@@ -1363,6 +1363,12 @@ __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int N
 // afterwards; lane 63, the only one read, takes its operands from written
 // lanes only: lanes 15 and 47 after the row steps, lane 31 after the first
 // broadcast.)
+// Ballot of a per-lane condition: the 64-bit lane mask, taken from the
+// condition itself (no round trip through an int).
+__device__ __forceinline__ unsigned long long wballot(bool c) {
+  return __builtin_amdgcn_ballot_w64(c);
+}
+
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ uint32_t dppu(uint32_t v) {
   return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, ROWS, 0xF, true));
@@ -1456,7 +1462,7 @@ __device__ __forceinline__ uint32_t wave_block_cull(const float4* rec, int M, co
       cand = cand || (d2 < rr * rr);
     }
     cand = cand && (j < M);
-    const unsigned long long mask = __ballot(cand), moving = __ballot(cand && R1.w != 0.0f);
+    const unsigned long long mask = wballot(cand), moving = wballot(cand && R1.w != 0.0f);
     if (lane == 0) {
       *reinterpret_cast<uint4*>(masks + 4 * g) =
           make_uint4(static_cast<uint32_t>(mask), static_cast<uint32_t>(mask >> 32),
@@ -1499,14 +1505,12 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
                                                     uint32_t& ncand, uint32_t nok, uint32_t& pairs,
                                                     float& wwv, float& wwa, float& pmargin,
                                                     float& lclear) {
+  // (dv / da are written below whenever their row type has a nonzero
+  // push-out, the only case in which they are read)
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
-    for (int x = 0; x < DIMS; ++x) {
-      S[i][x] = 0.0f;
-      dv[i][x] = 0.0f;
-      da[i][x] = 0.0f;
-    }
+    for (int x = 0; x < DIMS; ++x) S[i][x] = 0.0f;
     r2[i] = 0.0f;
   }
   if (comp & 1u) {
@@ -1532,7 +1536,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
           }
           mu = ok[i] ? __builtin_elementwise_minimum(mu, mi) : mu;
         }
-        rebuild = __ballot(!(mu >= 0.0f)) != 0ull;
+        rebuild = wballot(!(mu >= 0.0f)) != 0ull;
         // (every valid distance is >= 0 here; the mask turns -0 into +0)
         if (!rebuild) pmargin = __uint_as_float(__float_as_uint(mu) & 0x7fffffffu);
       }
@@ -1598,7 +1602,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
       any = any | (ok[i] & (ww[i] > wmax * wmax));
       m = ok[i] ? fmaxf(m, ww[i]) : m;
     }
-    if (__ballot(any) == 0ull) {
+    if (wballot(any) == 0ull) {
       if (!LAST) wwm = wave_reduce_nn<true>(m);
     } else {
       nz |= bit;
@@ -1630,7 +1634,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
     for (int i = 0; i < NI; ++i)
 #pragma unroll
       for (int x = 0; x < DIMS; ++x) any = any || (ok[i] && S[i][x] != 0.0f);
-    if (__ballot(any) != 0ull) nz |= 1u;
+    if (wballot(any) != 0ull) nz |= 1u;
   }
   return nz;
 }
@@ -1856,7 +1860,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
         ok[i] = (t < K) && ((4 * q) / AS + i < nsw);
-        nok += static_cast<uint32_t>(__builtin_popcountll(__ballot(ok[i])));
+        nok += static_cast<uint32_t>(__builtin_popcountll(wballot(ok[i])));
 #pragma unroll
         for (int x = 0; x < DIMS; ++x) {
           p[i][x] = Y0[AS * i + x];
@@ -2026,9 +2030,9 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         Bv -= dl;
         Ba -= dl;
         const bool inb = lane < NB;
-        mP = static_cast<uint32_t>(__ballot(inb && !(Bp >= 0.0f)));
-        mV = static_cast<uint32_t>(__ballot(inb && !(Bv >= 0.0f)));
-        mA = static_cast<uint32_t>(__ballot(inb && !(Ba >= 0.0f)));
+        mP = static_cast<uint32_t>(wballot(inb && !(Bp >= 0.0f)));
+        mV = static_cast<uint32_t>(wballot(inb && !(Bv >= 0.0f)));
+        mA = static_cast<uint32_t>(wballot(inb && !(Ba >= 0.0f)));
       }
     }
 
