@@ -294,13 +294,17 @@ __device__ __forceinline__ void uf_row_step(const float g[kMaxNV], int s, int ax
 
 // Large batches: one block per `tiles` tiles of 64 samples (2 in 2D, 1 in
 // 3D: 256 or 192 rows (sample, axis)) x kUpdParts parts of the row's 3K
-// entries (a contiguous range per part), so that a launch is about one round
-// of resident blocks.  A wave holds 64 consecutive rows of one part, so each
-// entry is a 256-byte load across the wave and the same W row for every lane
-// (an LDS broadcast); the parts' partial g are summed
-// through LDS in part order and the first part's lanes take the QP step.
+// entries (part p taking entries p, p + kUpdParts, ..., so that the block's
+// waves sweep the tile's region together), so that a launch is about one
+// round of resident blocks.  A wave holds 64 consecutive rows of one part, so
+// each entry is a 256-byte load across the wave and the same W row for every
+// lane (an LDS broadcast); the parts' partial g are summed through LDS in part
+// order and the first part's lanes take the QP step.  NVP: coefficients per
+// row rounded up to whole float4s of W (12 covers the usual 11; the padding
+// columns of W are zero, so they add nothing).
 constexpr int kUpdParts = 4;
 
+template <int NVP>
 __global__ __launch_bounds__(1024) void uf_update_tile(
     const float4* __restrict__ w16, const float* __restrict__ M11, const float* __restrict__ Pi,
     const float* __restrict__ M12, const float* __restrict__ bc, const float* __restrict__ delta,
@@ -314,26 +318,28 @@ __global__ __launch_bounds__(1024) void uf_update_tile(
   // (rows is a multiple of 64: every wave lies in one part)
   const int part = threadIdx.x / rows, rl = threadIdx.x - part * rows;
   const int tile = blockIdx.x * tiles + rl / trows, rt = rl - (rl / trows) * trows;
-  const int e_lo = (E * part) / kUpdParts, e_hi = (E * (part + 1)) / kUpdParts;
-  float g[kMaxNV];
+  static_assert(NVP % 4 == 0 && NVP <= kMaxNV, "whole float4s of W");
+  const int ne = (E - part + kUpdParts - 1) / kUpdParts;  // this part's entries
+  float g[NVP];
 #pragma unroll
-  for (int c = 0; c < kMaxNV; ++c) g[c] = 0.0f;
+  for (int c = 0; c < NVP; ++c) g[c] = 0.0f;
   // (a tile past the last sample, up to the layout's even tile count, only
   // reads workspace and stores nothing)
-  const float* dl = delta + static_cast<int64_t>(tile) * E * trows + rt;
+  const float* dl = delta + static_cast<int64_t>(tile) * E * trows + part * trows + rt;
+  const int64_t estride = static_cast<int64_t>(kUpdParts) * trows;
   constexpr int kU = 16;  // loads in flight per lane
-  for (int e0 = e_lo; e0 < e_hi; e0 += kU) {
+  for (int i0 = 0; i0 < ne; i0 += kU) {
     float v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u;
-      v[u] = e < e_hi ? dl[static_cast<int64_t>(e) * trows] : 0.0f;
+      const int i = i0 + u;
+      v[u] = i < ne ? dl[i * estride] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int e = min(e0 + u, e_hi - 1);  // (v = 0 past the end)
+      const int e = min(i0 + u, ne - 1) * kUpdParts + part;  // (v = 0 past the end)
 #pragma unroll
-      for (int c4 = 0; c4 < 4; ++c4) {
+      for (int c4 = 0; c4 < NVP / 4; ++c4) {
         const float4 w = swe[e * 4 + c4];
         g[4 * c4 + 0] = fmaf(w.x, v[u], g[4 * c4 + 0]);
         g[4 * c4 + 1] = fmaf(w.y, v[u], g[4 * c4 + 1]);
@@ -344,15 +350,18 @@ __global__ __launch_bounds__(1024) void uf_update_tile(
   }
   if (part > 0)
 #pragma unroll
-    for (int c = 0; c < kMaxNV; ++c) red[((part - 1) * rows + rl) * kMaxNV + c] = g[c];
+    for (int c = 0; c < NVP; ++c) red[((part - 1) * rows + rl) * NVP + c] = g[c];
   __syncthreads();
   if (part > 0) return;
   for (int q = 1; q < kUpdParts; ++q)
 #pragma unroll
-    for (int c = 0; c < kMaxNV; ++c) g[c] += red[((q - 1) * rows + rl) * kMaxNV + c];
+    for (int c = 0; c < NVP; ++c) g[c] += red[((q - 1) * rows + rl) * NVP + c];
   const int r = tile * trows + rt;
   if (r >= N * dims) return;
-  uf_row_step(g, r / dims, r - (r / dims) * dims, nv, dims, rho, first, M11, Pi, M12, bc, xi, xb,
+  float gg[kMaxNV];
+#pragma unroll
+  for (int c = 0; c < kMaxNV; ++c) gg[c] = c < NVP ? g[c] : 0.0f;
+  uf_row_step(gg, r / dims, r - (r / dims) * dims, nv, dims, rho, first, M11, Pi, M12, bc, xi, xb,
               lam);
 }
 
@@ -508,7 +517,7 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
     forward();
     push(false);
     if (tpr == 1)
-      hipLaunchKernelGGL(uf_update_tile, g_tiles, dim3(ut * kUfTile * dims * kUpdParts), lds_tile,
+      hipLaunchKernelGGL(nv <= 12 ? uf_update_tile<12> : uf_update_tile<16>, g_tiles, dim3(ut * kUfTile * dims * kUpdParts), lds_tile,
                          s, reinterpret_cast<const float4*>(w16), a.M11, a.Pi, a.M12, a.bc, delta,
                          xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, ut);
     else
