@@ -297,8 +297,10 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
  * (8 samples per block, two items per lane); one or two 16-step time blocks
  * per wave, or every time block of the horizon in one wave (blocks of 16
  * waves, each with its own samples); one block per tile or a persistent grid
- * of resident blocks that loop over tiles.  Every shape gives bit-identical
- * results.  By default the
+ * of resident blocks that loop over tiles (for the whole-horizon shape: one
+ * group of samples per wave, or four per wave that the block's waves draw
+ * from a shared counter, so that waves whose samples need fewer evaluations
+ * take more of them).  Every shape gives bit-identical results.  By default the
  * library times every candidate the first time a problem handle meets a new
  * (N, n_problems, sampling mode, precision) - one warm-up and two timed
  * launches of a shortened (<= 8 iteration) copy of the real launch, outputs
@@ -315,7 +317,9 @@ typedef struct priest_tiling {
                          each wave carries its samples over the whole horizon (4 axis slots,
                          or 2 in 2D; n_steps <= 128), no block barrier per iteration: for
                          batches large enough to fill the chip */
-  int32_t persistent; /* 1: grid of resident blocks looping over tiles */
+  int32_t persistent; /* 1: grid of resident blocks looping over tiles; with row_tiles 0:
+                         blocks of 4 sample groups per wave, drawn by the waves from a
+                         counter (one group per wave with 0) */
   int32_t reserved;   /* must be 0 */
 } priest_tiling;
 

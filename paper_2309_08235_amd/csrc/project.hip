@@ -1323,22 +1323,24 @@ constexpr int kPlane = 68;         // floats per transpose plane: 64 lanes + 4 (
 constexpr int kWtabV4 = 6;         // float4 per lane and time block in the W table
 
 struct WaveLayout {  // offsets into dynamic LDS, in floats
-  int rec, wtab, wave, wave_floats, cache, cstride, stage, total;
+  int rec, wtab, wave, wave_floats, cache, cstride, mul, ctr, total;
 };
 
 // rec: obstacle records; wtab: per time block and lane the 12 forward-row B
 // operands (rows P, Pdot, Pddot x 4 coefficient chunks) and the 12
 // right-hand-side A operands (row types x 4 time chunks); wave: per wave 12
-// transpose planes (3 quantities x 4 column residues), then per time block
-// its candidate cache: words 0..31 the box of each row of 16 lanes grown by
-// the reuse slack (low corner, high corner as float4), then 4 mask words per
-// obstacle group (static, moving; 64 bits each); stage: sampler staging of
-// the block's samples, aliasing the wave regions (used before any wave
-// iterates).
+// transpose planes (3 quantities x 4 column residues), which also stage the
+// wave's samples before it iterates (2 SPW D4 <= 768 floats), then per time
+// block its candidate cache: words 0..31 the box of each row of 16 lanes grown
+// by the reuse slack (low corner, high corner as float4), then 4 mask words
+// per obstacle group (static, moving; 64 bits each); mul: the problem's mean
+// and Cholesky factor (when the kernel draws the samples); ctr: the tile's
+// group counter.
 __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int NB, int WPB, int SPW,
                                                   int mode) {
   WaveLayout l{};
-  const int D = dims * nv, D4 = round4(D), G = (M + 63) / 64, SPB = WPB * SPW;
+  const int D = dims * nv, D4 = round4(D), G = (M + 63) / 64;
+  (void)SPW;
   int o = 0;
   l.rec = o;  o += 12 * M;
   l.wtab = o; o += NB * kWtabV4 * 64 * 4;
@@ -1346,13 +1348,13 @@ __host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int N
   l.cstride = 32 + 4 * G;
   l.wave_floats = round4(l.cache + NB * l.cstride);
   l.wave = o; o += WPB * l.wave_floats;
-  l.stage = l.wave;
-  int stage = SPB * D4;
-  if (mode != kFromInput) stage += D4 + round4(D * D) + SPB * D4;
-  if (l.stage + stage > o) o = l.stage + stage;
+  l.mul = o;
+  if (mode != kFromInput) o += D4 + round4(D * D);
+  l.ctr = o;  o += 4;
   l.total = o;
   return l;
 }
+static_assert(2 * 8 * ((3 * kMaxNV + 3) & ~3) <= 12 * kPlane, "a wave's samples fit its planes");
 
 // Wave-wide maximum / minimum of floats that are >= +0 (or +inf / NaN),
 // compared as their bit patterns, which orders them as floats (NaN above
@@ -1648,7 +1650,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, WPB = blockDim.x >> 6;
   const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv, D4 = round4(D);
-  const int NB = (K + 15) >> 4, SPB = WPB * SPW;
+  const int NB = (K + 15) >> 4, SPB = a.S;  // samples per block: SPW per group, 1 or 4 groups per wave
   const WaveLayout l = wave_layout(DIMS, nv, M, NB, WPB, SPW, a.mode);
   // column layout (MFMA state): col = AS * cs + cx, coefficient rows 4 q + r;
   // item layout (forward rows, push-outs): step ti of columns 4 q + 0..3
@@ -1703,407 +1705,425 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   // half the time window of a 16-step block
   const float thalf = a.dt * 7.5f;
 
+  // The tile's groups of SPW samples are drawn by the block's waves from a
+  // counter in LDS: a wave that finishes a group early takes the next one
+  // instead of idling until the slowest wave of the block is done.
+  int* ctr = reinterpret_cast<int*>(sm + l.ctr);
+  float* sMu = sm + l.mul;
+  float* sL = sMu + D4;
   int cur_prob = -1;
   for (int tile = first; tile < total; tile += stride) {
     const int prob = tile / a.blocks_per_problem;
     const int s0 = (tile - prob * a.blocks_per_problem) * SPB;
     const int ns = min(SPB, a.N - s0);
-    const int sw0 = w * SPW;  // this wave's first sample in the tile
-    const int nsw = max(0, min(SPW, ns - sw0));
-    // (every reader of the previous tile's records and staging is done)
+    const int ngroups = (ns + SPW - 1) / SPW;
+    // (every wave is done with the previous tile: records, mean, factor and
+    // counter may change)
     __syncthreads();
-    if (prob != cur_prob) build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
+    if (prob != cur_prob) {
+      build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
+      if (a.mode != kFromInput) {
+        const float* mu = a.mu + prob * a.mu_stride;
+        const float* Lm = a.L + prob * a.L_stride;
+        for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
+        for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
+      }
+    }
     cur_prob = prob;
-    float* xs = sm + l.stage;
-    if (a.mode == kFromInput) {
-      const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(s0) * D;
-      for (int i = tid; i < ns * D; i += blockDim.x) xs[(i / D) * D4 + i % D] = src[i];
-    } else {
-      float* sMu = xs + SPB * D4;
-      float* sL = sMu + D4;
-      float* sZ = sL + round4(D * D);
-      const float* mu = a.mu + prob * a.mu_stride;
-      const float* Lm = a.L + prob * a.L_stride;
-      for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
-      for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
-      if (a.mode == kFromNoise) {
-        const float* z = a.noise + prob * a.noise_stride + static_cast<int64_t>(s0) * D;
-        for (int i = tid; i < ns * D; i += blockDim.x) sZ[(i / D) * D4 + i % D] = z[i];
-      } else {
-        const int nq = D4 / 4;
-        const uint32_t stream_id = a.stream_base + static_cast<uint32_t>(prob);
-        for (int i = tid; i < ns * nq; i += blockDim.x) {
-          const int s = i / nq, qq = i - s * nq;
-          float z[4];
-          philox_normals4(a.seed, static_cast<uint32_t>(s0 + s), static_cast<uint32_t>(qq),
-                          static_cast<uint32_t>(a.iter), stream_id, z);
-          *reinterpret_cast<float4*>(sZ + s * D4 + 4 * qq) = make_float4(z[0], z[1], z[2], z[3]);
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < ns * D; i += blockDim.x) {
-        const int s = i / D, d = i - s * D;
-        const float* zz = sZ + s * D4;
-        const float* Lr = sL + d * D;
-        float x = sMu[d];
-        for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
-        xs[s * D4 + d] = x;
-      }
-      __syncthreads();
-      if (a.xi_src) {
-        float* dst = a.xi_src + prob * a.xi_src_stride + static_cast<int64_t>(s0) * D;
-        for (int i = tid; i < ns * D; i += blockDim.x) dst[i] = xs[(i / D) * D4 + i % D];
-      }
-    }
+    if (tid == 0) *ctr = 0;
     __syncthreads();
-    const bool colok = (cx < DIMS) && (cs < nsw);
     const float* bc = a.bc + prob * a.bc_stride;
-    f4 xi;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = coef_of(q, r);
-      xi[r] = (colok && c < nv) ? xs[(sw0 + cs) * D4 + cx * nv + c] : 0.0f;
-    }
-    // (every wave has its samples: the staging area becomes the waves' regions)
-    __syncthreads();
-    if (nsw == 0) continue;
-
-    // planes of padding columns (axis slots >= DIMS) are read as zeros; no
-    // time block has a candidate cache yet
-    if constexpr (AS == 4) {
-#pragma unroll
-      for (int x = DIMS; x < 4; ++x)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) wr[(d * 4 + x) * kPlane + lane] = 0.0f;
-    }
-    wave_lds_sync();
-    // reuse slack of the candidate masks: the smallest cull radius of the scene
-    float slack = INFINITY;
-    for (int j = lane; j < M; j += 64) slack = fminf(slack, rec[j].w);
-    slack = M > 0 ? wave_min(slack) : 1.0f;
-
-    f4 xb = xi;
-    f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
-    uint32_t pairs = 0;
-
-    // Displacement budgets.  Lane tb < NB holds, for time block tb, how much
-    // more the coefficients may move (summed max |change| over this wave's
-    // valid columns) before its positions may leave the grown boxes of its
-    // candidate cache (Bp) or its velocities / accelerations may exceed
-    // their bounds (Bv, Ba), and the block's candidate count (ncl).  A row
-    // type whose budget is left is not evaluated: its push-outs are zero on
-    // every valid item; with no budget left the positions are tested against
-    // the grown boxes and the cache is rebuilt only if an item is outside.
-    // The budgets come from the last evaluation: a change
-    // Delta moves row type d by at most S_d max|Delta| (bscale), and the
-    // MFMA rounding of the two evaluations, at most 3e-6 S_d X with X a bound
-    // on max |xi_bar|, is taken off with margin (1e-5 X); the factor 0.99899
-    // covers the rounding of the budget arithmetic.
-    float Bp = -1.0f, Bv = -1.0f, Ba = -1.0f;
-    uint32_t ncl = ~0u;  // no cache yet
-    const uint32_t blocks = (1u << NB) - 1u;
-    uint32_t mP = blocks, mV = blocks, mA = blocks;  // blocks to evaluate
-    float X;
-    {
-      float m = 0.0f;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(xi[r]));
-      X = wave_reduce_nn<true>(colok ? m : 0.0f) * 1.000002f;
-    }
-    auto budget = [&](float A) { return fmaf(A, 0.99899f, -1.0e-5f * X); };
-    auto bound_budget = [&](float wmax, float wwm, float scale) {
-      // (v_sqrt_f32 is within 1 ulp)
-      return budget((wmax * 0.999999f - __builtin_amdgcn_sqrtf(wwm) * 1.000001f) * scale);
-    };
-
-    // One time block: forward rows of the row types in `comp` (bit 0:
-    // positions, 1: velocities, 2: accelerations) of columns 4 q + 0..3 at
-    // step 16 tb + ti (item layout), then the push-outs of this lane's items.
-    auto block_items = [&](int tb, uint32_t comp, bool test, uint32_t& ncand, auto last_tag,
-                           float p[NI][DIMS], float v[NI][DIMS], float ac[NI][DIMS],
-                           float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
-                           bool ok[NI], float& wwv, float& wwa, float& pm, float& lcl) {
-      constexpr bool LAST = decltype(last_tag)::value;
-      const float4* wt = wtab + tb * kWtabV4 * 64 + lane;
-      f4 Y0 = zf, Y1 = zf, Y2 = zf;
-      if (comp == 7u) {
-        const float4 w0 = wt[0], w1 = wt[64], w2 = wt[128];
-        Y0 = mfma(xb[0], w0.x, zf);
-        Y1 = mfma(xb[0], w1.x, zf);
-        Y2 = mfma(xb[0], w2.x, zf);
-        Y0 = mfma(xb[1], w0.y, Y0);
-        Y1 = mfma(xb[1], w1.y, Y1);
-        Y2 = mfma(xb[1], w2.y, Y2);
-        Y0 = mfma(xb[2], w0.z, Y0);
-        Y1 = mfma(xb[2], w1.z, Y1);
-        Y2 = mfma(xb[2], w2.z, Y2);
-        if (chunk3) {
-          Y0 = mfma(xb[3], w0.w, Y0);
-          Y1 = mfma(xb[3], w1.w, Y1);
-          Y2 = mfma(xb[3], w2.w, Y2);
-        }
+    for (;;) {
+      int gi = 0;
+      if (lane == 0) gi = atomicAdd(ctr, 1);
+      gi = __builtin_amdgcn_readfirstlane(gi);
+      if (gi >= ngroups) break;
+      const int gs0 = s0 + gi * SPW;  // the group's first sample
+      const int nsw = min(SPW, ns - gi * SPW);
+      // the group's samples, staged in this wave's planes
+      float* xs = wr;
+      if (a.mode == kFromInput) {
+        const float* src = a.xi_in + prob * a.xi_in_stride + static_cast<int64_t>(gs0) * D;
+        for (int i = lane; i < nsw * D; i += 64) xs[(i / D) * D4 + i % D] = src[i];
       } else {
-        // the same chains, one row type at a time
-        auto chain = [&](const float4 w) {
-          f4 Y = mfma(xb[0], w.x, zf);
-          Y = mfma(xb[1], w.y, Y);
-          Y = mfma(xb[2], w.z, Y);
-          if (chunk3) Y = mfma(xb[3], w.w, Y);
-          return Y;
-        };
-        if (comp & 1u) Y0 = chain(wt[0]);
-        if (comp & 2u) Y1 = chain(wt[64]);
-        if (comp & 4u) Y2 = chain(wt[128]);
-      }
-      const int t = 16 * tb + ti;
-      uint32_t nok = 0;
-#pragma unroll
-      for (int i = 0; i < NI; ++i) {
-        ok[i] = (t < K) && ((4 * q) / AS + i < nsw);
-        nok += static_cast<uint32_t>(__builtin_popcountll(wballot(ok[i])));
-#pragma unroll
-        for (int x = 0; x < DIMS; ++x) {
-          p[i][x] = Y0[AS * i + x];
-          v[i][x] = Y1[AS * i + x];
-          ac[i][x] = Y2[AS * i + x];
-        }
-      }
-      const float tmid = a.dt * (static_cast<float>(16 * tb) + 7.5f);
-      return wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
-                                             comp, test, ok, p, v, ac, a.vmax, a.amax, a.box, S,
-                                             dv, da, r2, lane, cwords + tb * cstride, ncand, nok,
-                                             pairs, wwv, wwa, pm, lcl);
-    };
-
-    // ---- projection iterations ---------------------------------------------------
-    for (int k = 0; k < a.n_iter; ++k) {
-      const bool lowp = BF16 && (k < a.bf16_iters);
-      // right-hand side: the nonzero block partials added to +0 in time-block
-      // order, the sum of the time-split shape (an all-zero partial leaves it
-      // unchanged)
-      f4 g = zf;
-      // (the blocks with a row type to evaluate, in ascending order; the
-      // others add nothing)
-      uint32_t todo = a.box.on ? blocks : (mP | mV | mA);
-      while (todo) {
-        const int tb = __builtin_ctz(todo);
-        todo &= todo - 1u;
-        const uint32_t bit = 1u << tb;
-        uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
-        const bool test = (mP & bit) != 0u;
-        uint32_t comp = ((mV & bit) ? 2u : 0u) | ((mA & bit) ? 4u : 0u);
-        // (while the position budget lasts, every valid item is inside its
-        // grown box and clear of every candidate: no obstacle can push)
-        if (test || a.box.on) comp |= 1u;
-        if (comp) {
-          float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-          bool ok[NI];
-          float wwv = 0.0f, wwa = 0.0f, pm = 0.0f, lcl = INFINITY;
-          const uint32_t nz = block_items(tb, comp, test, ncand, std::false_type{}, p, v, ac, S, dv,
-                                          da, r2, ok, wwv, wwa, pm, lcl);
-          // new budgets of the row types evaluated here; the position budget
-          // is the smaller of the grown-box margin (per axis) and the
-          // candidates' clearance (Euclidean, over sqrt(dims)), or none while
-          // some position push-out is nonzero
-          if (test) {
-            float bp = -1.0f;
-            if (!(nz & 1u)) {
-              // (one reduction of both: rounding is monotone, so the smallest
-              // scaled clearance is the smallest clearance scaled)
-              float lm = pm;
-              if (ncand) {
-                const float c = fmaxf(lcl, 0.0f) * (DIMS == 3 ? 0.57735026f : 0.70710678f);
-                lm = fminf(lm, __uint_as_float(__float_as_uint(c) & 0x7fffffffu));
-              }
-              const float m = wave_reduce_nn<false>(lm);
-              if (m > 0.0f) bp = budget(m * a.bscale[0]);
-            }
-            Bp = lane == tb ? bp : Bp;
-            ncl = lane == tb ? ncand : ncl;
-          }
-          if (comp & 2u) {
-            const float bv = (nz & 2u) ? -1.0f : bound_budget(a.vmax, wwv, a.bscale[1]);
-            Bv = lane == tb ? bv : Bv;
-          }
-          if (comp & 4u) {
-            const float ba = (nz & 4u) ? -1.0f : bound_budget(a.amax, wwa, a.bscale[2]);
-            Ba = lane == tb ? ba : Ba;
-          }
-          // Right-hand side of the row types with a nonzero push-out.  The
-          // products of an all-zero row type are exact zeros, and an
-          // accumulator that starts at +0 is unchanged by adding them, so
-          // skipping them leaves the partial bit for bit as in the full chains.
-          if (nz) {
-            f4 part;
-            const float (*src[3])[DIMS] = {S, dv, da};
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-              if (nz & (1u << d)) {
-#pragma unroll
-                for (int i = 0; i < NI; ++i)
-#pragma unroll
-                  for (int x = 0; x < DIMS; ++x) wr[(d * 4 + AS * i + x) * kPlane + lane] = src[d][i][x];
-              }
-            wave_lds_sync();
-            f4 B[3];
-            float4 wa[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-              if (nz & (1u << d)) {
-                B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
-                wa[d] = wtab[(tb * kWtabV4 + 3 + d) * 64 + lane];
-              }
-            wave_lds_sync();
-            if (lowp) {
-              f4 gg = zf;
-#pragma unroll
-              for (int d = 0; d < 3; ++d)
-                if (nz & (1u << d)) {
-                  const float4 A4 = wa[d];
-                  gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
-                                 pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
-                }
-              part = gg;
-            } else {
-              // the two accumulation chains of the time-split shape
-              f4 acc0 = zf, acc1 = zf;
-#pragma unroll
-              for (int d = 0; d < 3; ++d)
-                if (nz & (1u << d)) {
-                  const float4 A4 = wa[d];
-                  acc0 = mfma(A4.x, B[d][0], acc0);
-                  acc1 = mfma(A4.y, B[d][1], acc1);
-                  acc0 = mfma(A4.z, B[d][2], acc0);
-                  acc1 = mfma(A4.w, B[d][3], acc1);
-                }
-              part = acc0 + acc1;
-            }
-            g = g + part;
-          }
-        }
-      }
-      lam += rho * g;
-      const f4 xold = xb;
-      if (k == 0) {
-        // Pi and c0 = M12 b enter the first step only
-        float Ap[4];
-        f4 c0v;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int c = coef_of(q, r);
-          Ap[r] = (crow < nv && c < nv) ? a.Pi[crow * nv + c] : 0.0f;
-          float sacc = 0.0f;
-          if (colok && c < nv)
-            for (int i = 0; i < 6; ++i) sacc = fmaf(a.M12[c * 6 + i], bc[cx * 6 + i], sacc);
-          c0v[r] = sacc;
-        }
-        const f4 u = lam + rho * g;
-        const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
-        f4 h1 = mfma(Ap[2], xi[2], zf);
-        const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], zf));
-        f4 h3 = mfma(Am[2], u[2], zf);
-        if (chunk3) {
-          h1 = mfma(Ap[3], xi[3], h1);
-          h3 = mfma(Am[3], u[3], h3);
-        }
-        xb = (h0 + h1) + (h2 + h3);
-      } else if (lowp) {
-        const f4 u = (xi - xb) + lam + rho * g;
-        const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
-        const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
-                                u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
-        xb = xb + mfma_bf16(Mhi, uh, mfma_bf16(Mlo, uh, mfma_bf16(Mhi, ul, zf)));
-      } else {
-        const f4 u = (xi - xb) + lam + rho * g;
-        xb = mfma(Am[2], u[2], mfma(Am[1], u[1], mfma(Am[0], u[0], xb)));
-        if (chunk3) xb = mfma(Am[3], u[3], xb);
-      }
-      // every block's budgets shrink by the largest coefficient change of
-      // the wave's valid columns (rounded up)
-      {
-        float m = 0.0f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(xb[r] - xold[r]));
-        const float dl = wave_reduce_nn<true>(colok ? m : 0.0f) * 1.000002f;
-        X += dl;
-        Bp -= dl;
-        Bv -= dl;
-        Ba -= dl;
-        const bool inb = lane < NB;
-        mP = static_cast<uint32_t>(wballot(inb && !(Bp >= 0.0f)));
-        mV = static_cast<uint32_t>(wballot(inb && !(Bv >= 0.0f)));
-        mA = static_cast<uint32_t>(wballot(inb && !(Ba >= 0.0f)));
-      }
-    }
-
-    // ---- residual and cost of the returned iterate, summed in t order --------------
-    float sg[DIMS], ug[DIMS], iuu = 0.0f;
-    if (a.cost.kind != 0) {
-      float uu = 0.0f;
-#pragma unroll
-      for (int x = 0; x < DIMS; ++x) {
-        sg[x] = bc[x * 6 + 0];
-        ug[x] = bc[x * 6 + 3] - sg[x];
-        uu = fmaf(ug[x], ug[x], uu);
-      }
-      iuu = uu > 0.0f ? 1.0f / uu : 0.0f;
-    }
-    float racc = 0.0f, cacc = 0.0f;
-    for (int tb = 0; tb < NB; ++tb) {
-      float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
-      bool ok[NI];
-      uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
-      float wwv = 0.0f, wwa = 0.0f, pm = 0.0f, lcl = INFINITY;
-      block_items(tb, 7u, (mP >> tb) & 1u, ncand, std::true_type{}, p, v, ac, S, dv, da, r2, ok, wwv,
-                  wwa, pm, lcl);
-      // per-(t, sample) residual^2 and cost through this wave's planes
-#pragma unroll
-      for (int i = 0; i < NI; ++i) {
-        float cc = 0.0f;
-        if (a.cost.kind == 0) {
-#pragma unroll
-          for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[i][x], ac[i][x], cc);
+        float* sZ = xs + SPW * D4;
+        if (a.mode == kFromNoise) {
+          const float* z = a.noise + prob * a.noise_stride + static_cast<int64_t>(gs0) * D;
+          for (int i = lane; i < nsw * D; i += 64) sZ[(i / D) * D4 + i % D] = z[i];
         } else {
-          cc = weighted_cost<DIMS>(p[i], v[i], ac[i], a.cost, sg, ug, iuu);
+          const int nq = D4 / 4;
+          const uint32_t stream_id = a.stream_base + static_cast<uint32_t>(prob);
+          for (int i = lane; i < nsw * nq; i += 64) {
+            const int s = i / nq, qq = i - s * nq;
+            float z[4];
+            philox_normals4(a.seed, static_cast<uint32_t>(gs0 + s), static_cast<uint32_t>(qq),
+                            static_cast<uint32_t>(a.iter), stream_id, z);
+            *reinterpret_cast<float4*>(sZ + s * D4 + 4 * qq) = make_float4(z[0], z[1], z[2], z[3]);
+          }
         }
-        float* f = wr + 2 * (ti * SPW + (4 * q) / AS + i);
-        f[0] = ok[i] ? r2[i] : 0.0f;
-        f[1] = ok[i] ? cc : 0.0f;
+        wave_lds_sync();
+        for (int i = lane; i < nsw * D; i += 64) {
+          const int s = i / D, d = i - s * D;
+          const float* zz = sZ + s * D4;
+          const float* Lr = sL + d * D;
+          float x = sMu[d];
+          for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
+          xs[s * D4 + d] = x;
+        }
+        wave_lds_sync();
+        if (a.xi_src) {
+          float* dst = a.xi_src + prob * a.xi_src_stride + static_cast<int64_t>(gs0) * D;
+          for (int i = lane; i < nsw * D; i += 64) dst[i] = xs[(i / D) * D4 + i % D];
+        }
       }
       wave_lds_sync();
-      if (lane < nsw) {
-        const int nt = min(16, K - 16 * tb);
-        for (int t = 0; t < nt; ++t) {
-          const float* f = wr + 2 * (t * SPW + lane);
-          racc += f[0];
-          cacc += f[1];
-        }
-      }
-      wave_lds_sync();
-    }
-    if (lane < nsw) {
-      const int s = s0 + sw0 + lane;
-      const float r = sqrtf(racc);
-      const int64_t nb = prob * a.n_stride + s;
-      const int64_t dense = static_cast<int64_t>(prob) * a.N + s;
-      if (a.resid) a.resid[nb] = r;
-      if (a.c1) a.c1[nb] = cacc;
-      if (a.resid2) a.resid2[dense] = r;
-      if (a.c12) a.c12[dense] = cacc;
-    }
-    if (a.pair_count && lane == 0) atomicAdd(a.pair_count, static_cast<unsigned long long>(pairs));
-    if (colok) {
-      float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(s0 + sw0 + cs) * D + cx * nv;
-      float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + s0 + sw0 + cs) * D + cx * nv
-                              : nullptr;
+      const bool colok = (cx < DIMS) && (cs < nsw);
+      f4 xi;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int c = coef_of(q, r);
-        if (c < nv) {
-          dst[c] = xb[r];
+        xi[r] = (colok && c < nv) ? xs[cs * D4 + cx * nv + c] : 0.0f;
+      }
+      // (the samples are read: the planes become transpose buffers)
+      wave_lds_sync();
+
+      // planes of padding columns (axis slots >= DIMS) are read as zeros; no
+      // time block has a candidate cache yet
+      if constexpr (AS == 4) {
+#pragma unroll
+        for (int x = DIMS; x < 4; ++x)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) wr[(d * 4 + x) * kPlane + lane] = 0.0f;
+      }
+      wave_lds_sync();
+      // reuse slack of the candidate masks: the smallest cull radius of the scene
+      float slack = INFINITY;
+      for (int j = lane; j < M; j += 64) slack = fminf(slack, rec[j].w);
+      slack = M > 0 ? wave_min(slack) : 1.0f;
+
+      f4 xb = xi;
+      f4 lam = {0.0f, 0.0f, 0.0f, 0.0f};
+      uint32_t pairs = 0;
+
+      // Displacement budgets.  Lane tb < NB holds, for time block tb, how much
+      // more the coefficients may move (summed max |change| over this wave's
+      // valid columns) before its positions may leave the grown boxes of its
+      // candidate cache (Bp) or its velocities / accelerations may exceed
+      // their bounds (Bv, Ba), and the block's candidate count (ncl).  A row
+      // type whose budget is left is not evaluated: its push-outs are zero on
+      // every valid item; with no budget left the positions are tested against
+      // the grown boxes and the cache is rebuilt only if an item is outside.
+      // The budgets come from the last evaluation: a change
+      // Delta moves row type d by at most S_d max|Delta| (bscale), and the
+      // MFMA rounding of the two evaluations, at most 3e-6 S_d X with X a bound
+      // on max |xi_bar|, is taken off with margin (1e-5 X); the factor 0.99899
+      // covers the rounding of the budget arithmetic.
+      float Bp = -1.0f, Bv = -1.0f, Ba = -1.0f;
+      uint32_t ncl = ~0u;  // no cache yet
+      const uint32_t blocks = (1u << NB) - 1u;
+      uint32_t mP = blocks, mV = blocks, mA = blocks;  // blocks to evaluate
+      float X;
+      {
+        float m = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(xi[r]));
+        X = wave_reduce_nn<true>(colok ? m : 0.0f) * 1.000002f;
+      }
+      auto budget = [&](float A) { return fmaf(A, 0.99899f, -1.0e-5f * X); };
+      auto bound_budget = [&](float wmax, float wwm, float scale) {
+        // (v_sqrt_f32 is within 1 ulp)
+        return budget((wmax * 0.999999f - __builtin_amdgcn_sqrtf(wwm) * 1.000001f) * scale);
+      };
+
+      // One time block: forward rows of the row types in `comp` (bit 0:
+      // positions, 1: velocities, 2: accelerations) of columns 4 q + 0..3 at
+      // step 16 tb + ti (item layout), then the push-outs of this lane's items.
+      auto block_items = [&](int tb, uint32_t comp, bool test, uint32_t& ncand, auto last_tag,
+                             float p[NI][DIMS], float v[NI][DIMS], float ac[NI][DIMS],
+                             float S[NI][DIMS], float dv[NI][DIMS], float da[NI][DIMS], float r2[NI],
+                             bool ok[NI], float& wwv, float& wwa, float& pm, float& lcl) {
+        constexpr bool LAST = decltype(last_tag)::value;
+        const float4* wt = wtab + tb * kWtabV4 * 64 + lane;
+        f4 Y0 = zf, Y1 = zf, Y2 = zf;
+        if (comp == 7u) {
+          const float4 w0 = wt[0], w1 = wt[64], w2 = wt[128];
+          Y0 = mfma(xb[0], w0.x, zf);
+          Y1 = mfma(xb[0], w1.x, zf);
+          Y2 = mfma(xb[0], w2.x, zf);
+          Y0 = mfma(xb[1], w0.y, Y0);
+          Y1 = mfma(xb[1], w1.y, Y1);
+          Y2 = mfma(xb[1], w2.y, Y2);
+          Y0 = mfma(xb[2], w0.z, Y0);
+          Y1 = mfma(xb[2], w1.z, Y1);
+          Y2 = mfma(xb[2], w2.z, Y2);
+          if (chunk3) {
+            Y0 = mfma(xb[3], w0.w, Y0);
+            Y1 = mfma(xb[3], w1.w, Y1);
+            Y2 = mfma(xb[3], w2.w, Y2);
+          }
+        } else {
+          // the same chains, one row type at a time
+          auto chain = [&](const float4 w) {
+            f4 Y = mfma(xb[0], w.x, zf);
+            Y = mfma(xb[1], w.y, Y);
+            Y = mfma(xb[2], w.z, Y);
+            if (chunk3) Y = mfma(xb[3], w.w, Y);
+            return Y;
+          };
+          if (comp & 1u) Y0 = chain(wt[0]);
+          if (comp & 2u) Y1 = chain(wt[64]);
+          if (comp & 4u) Y2 = chain(wt[128]);
+        }
+        const int t = 16 * tb + ti;
+        uint32_t nok = 0;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          ok[i] = (t < K) && ((4 * q) / AS + i < nsw);
+          nok += static_cast<uint32_t>(__builtin_popcountll(wballot(ok[i])));
+#pragma unroll
+          for (int x = 0; x < DIMS; ++x) {
+            p[i][x] = Y0[AS * i + x];
+            v[i][x] = Y1[AS * i + x];
+            ac[i][x] = Y2[AS * i + x];
+          }
+        }
+        const float tmid = a.dt * (static_cast<float>(16 * tb) + 7.5f);
+        return wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
+                                               comp, test, ok, p, v, ac, a.vmax, a.amax, a.box, S,
+                                               dv, da, r2, lane, cwords + tb * cstride, ncand, nok,
+                                               pairs, wwv, wwa, pm, lcl);
+      };
+
+      // ---- projection iterations ---------------------------------------------------
+      for (int k = 0; k < a.n_iter; ++k) {
+        const bool lowp = BF16 && (k < a.bf16_iters);
+        // right-hand side: the nonzero block partials added to +0 in time-block
+        // order, the sum of the time-split shape (an all-zero partial leaves it
+        // unchanged)
+        f4 g = zf;
+        // (the blocks with a row type to evaluate, in ascending order; the
+        // others add nothing)
+        uint32_t todo = a.box.on ? blocks : (mP | mV | mA);
+        while (todo) {
+          const int tb = __builtin_ctz(todo);
+          todo &= todo - 1u;
+          const uint32_t bit = 1u << tb;
+          uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
+          const bool test = (mP & bit) != 0u;
+          uint32_t comp = ((mV & bit) ? 2u : 0u) | ((mA & bit) ? 4u : 0u);
+          // (while the position budget lasts, every valid item is inside its
+          // grown box and clear of every candidate: no obstacle can push)
+          if (test || a.box.on) comp |= 1u;
+          if (comp) {
+            float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+            bool ok[NI];
+            float wwv = 0.0f, wwa = 0.0f, pm = 0.0f, lcl = INFINITY;
+            const uint32_t nz = block_items(tb, comp, test, ncand, std::false_type{}, p, v, ac, S, dv,
+                                            da, r2, ok, wwv, wwa, pm, lcl);
+            // new budgets of the row types evaluated here; the position budget
+            // is the smaller of the grown-box margin (per axis) and the
+            // candidates' clearance (Euclidean, over sqrt(dims)), or none while
+            // some position push-out is nonzero
+            if (test) {
+              float bp = -1.0f;
+              if (!(nz & 1u)) {
+                // (one reduction of both: rounding is monotone, so the smallest
+                // scaled clearance is the smallest clearance scaled)
+                float lm = pm;
+                if (ncand) {
+                  const float c = fmaxf(lcl, 0.0f) * (DIMS == 3 ? 0.57735026f : 0.70710678f);
+                  lm = fminf(lm, __uint_as_float(__float_as_uint(c) & 0x7fffffffu));
+                }
+                const float m = wave_reduce_nn<false>(lm);
+                if (m > 0.0f) bp = budget(m * a.bscale[0]);
+              }
+              Bp = lane == tb ? bp : Bp;
+              ncl = lane == tb ? ncand : ncl;
+            }
+            if (comp & 2u) {
+              const float bv = (nz & 2u) ? -1.0f : bound_budget(a.vmax, wwv, a.bscale[1]);
+              Bv = lane == tb ? bv : Bv;
+            }
+            if (comp & 4u) {
+              const float ba = (nz & 4u) ? -1.0f : bound_budget(a.amax, wwa, a.bscale[2]);
+              Ba = lane == tb ? ba : Ba;
+            }
+            // Right-hand side of the row types with a nonzero push-out.  The
+            // products of an all-zero row type are exact zeros, and an
+            // accumulator that starts at +0 is unchanged by adding them, so
+            // skipping them leaves the partial bit for bit as in the full chains.
+            if (nz) {
+              f4 part;
+              const float (*src[3])[DIMS] = {S, dv, da};
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if (nz & (1u << d)) {
+#pragma unroll
+                  for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int x = 0; x < DIMS; ++x) wr[(d * 4 + AS * i + x) * kPlane + lane] = src[d][i][x];
+                }
+              wave_lds_sync();
+              f4 B[3];
+              float4 wa[3];
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if (nz & (1u << d)) {
+                  B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
+                  wa[d] = wtab[(tb * kWtabV4 + 3 + d) * 64 + lane];
+                }
+              wave_lds_sync();
+              if (lowp) {
+                f4 gg = zf;
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                  if (nz & (1u << d)) {
+                    const float4 A4 = wa[d];
+                    gg = mfma_bf16(pack_bf16(A4.x, A4.y, A4.z, A4.w),
+                                   pack_bf16(B[d][0], B[d][1], B[d][2], B[d][3]), gg);
+                  }
+                part = gg;
+              } else {
+                // the two accumulation chains of the time-split shape
+                f4 acc0 = zf, acc1 = zf;
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                  if (nz & (1u << d)) {
+                    const float4 A4 = wa[d];
+                    acc0 = mfma(A4.x, B[d][0], acc0);
+                    acc1 = mfma(A4.y, B[d][1], acc1);
+                    acc0 = mfma(A4.z, B[d][2], acc0);
+                    acc1 = mfma(A4.w, B[d][3], acc1);
+                  }
+                part = acc0 + acc1;
+              }
+              g = g + part;
+            }
+          }
+        }
+        lam += rho * g;
+        const f4 xold = xb;
+        if (k == 0) {
+          // Pi and c0 = M12 b enter the first step only
+          float Ap[4];
+          f4 c0v;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = coef_of(q, r);
+            Ap[r] = (crow < nv && c < nv) ? a.Pi[crow * nv + c] : 0.0f;
+            float sacc = 0.0f;
+            if (colok && c < nv)
+              for (int i = 0; i < 6; ++i) sacc = fmaf(a.M12[c * 6 + i], bc[cx * 6 + i], sacc);
+            c0v[r] = sacc;
+          }
+          const f4 u = lam + rho * g;
+          const f4 h0 = mfma(Ap[1], xi[1], mfma(Ap[0], xi[0], c0v));
+          f4 h1 = mfma(Ap[2], xi[2], zf);
+          const f4 h2 = mfma(Am[1], u[1], mfma(Am[0], u[0], zf));
+          f4 h3 = mfma(Am[2], u[2], zf);
+          if (chunk3) {
+            h1 = mfma(Ap[3], xi[3], h1);
+            h3 = mfma(Am[3], u[3], h3);
+          }
+          xb = (h0 + h1) + (h2 + h3);
+        } else if (lowp) {
+          const f4 u = (xi - xb) + lam + rho * g;
+          const s4 uh = pack_bf16(u[0], u[1], u[2], u[3]);
+          const s4 ul = pack_bf16(u[0] - from_bf16(uh[0]), u[1] - from_bf16(uh[1]),
+                                  u[2] - from_bf16(uh[2]), u[3] - from_bf16(uh[3]));
+          xb = xb + mfma_bf16(Mhi, uh, mfma_bf16(Mlo, uh, mfma_bf16(Mhi, ul, zf)));
+        } else {
+          const f4 u = (xi - xb) + lam + rho * g;
+          xb = mfma(Am[2], u[2], mfma(Am[1], u[1], mfma(Am[0], u[0], xb)));
+          if (chunk3) xb = mfma(Am[3], u[3], xb);
+        }
+        // every block's budgets shrink by the largest coefficient change of
+        // the wave's valid columns (rounded up)
+        {
+          float m = 0.0f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(xb[r] - xold[r]));
+          const float dl = wave_reduce_nn<true>(colok ? m : 0.0f) * 1.000002f;
+          X += dl;
+          Bp -= dl;
+          Bv -= dl;
+          Ba -= dl;
+          const bool inb = lane < NB;
+          mP = static_cast<uint32_t>(wballot(inb && !(Bp >= 0.0f)));
+          mV = static_cast<uint32_t>(wballot(inb && !(Bv >= 0.0f)));
+          mA = static_cast<uint32_t>(wballot(inb && !(Ba >= 0.0f)));
+        }
+      }
+
+      // ---- residual and cost of the returned iterate, summed in t order --------------
+      float sg[DIMS], ug[DIMS], iuu = 0.0f;
+      if (a.cost.kind != 0) {
+        float uu = 0.0f;
+#pragma unroll
+        for (int x = 0; x < DIMS; ++x) {
+          sg[x] = bc[x * 6 + 0];
+          ug[x] = bc[x * 6 + 3] - sg[x];
+          uu = fmaf(ug[x], ug[x], uu);
+        }
+        iuu = uu > 0.0f ? 1.0f / uu : 0.0f;
+      }
+      float racc = 0.0f, cacc = 0.0f;
+      for (int tb = 0; tb < NB; ++tb) {
+        float p[NI][DIMS], v[NI][DIMS], ac[NI][DIMS], S[NI][DIMS], dv[NI][DIMS], da[NI][DIMS], r2[NI];
+        bool ok[NI];
+        uint32_t ncand = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ncl), tb));
+        float wwv = 0.0f, wwa = 0.0f, pm = 0.0f, lcl = INFINITY;
+        block_items(tb, 7u, (mP >> tb) & 1u, ncand, std::true_type{}, p, v, ac, S, dv, da, r2, ok, wwv,
+                    wwa, pm, lcl);
+        // per-(t, sample) residual^2 and cost through this wave's planes
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          float cc = 0.0f;
+          if (a.cost.kind == 0) {
+#pragma unroll
+            for (int x = 0; x < DIMS; ++x) cc = fmaf(ac[i][x], ac[i][x], cc);
+          } else {
+            cc = weighted_cost<DIMS>(p[i], v[i], ac[i], a.cost, sg, ug, iuu);
+          }
+          float* f = wr + 2 * (ti * SPW + (4 * q) / AS + i);
+          f[0] = ok[i] ? r2[i] : 0.0f;
+          f[1] = ok[i] ? cc : 0.0f;
+        }
+        wave_lds_sync();
+        if (lane < nsw) {
+          const int nt = min(16, K - 16 * tb);
+          for (int t = 0; t < nt; ++t) {
+            const float* f = wr + 2 * (t * SPW + lane);
+            racc += f[0];
+            cacc += f[1];
+          }
+        }
+        wave_lds_sync();
+      }
+      if (lane < nsw) {
+        const int s = gs0 + lane;
+        const float r = sqrtf(racc);
+        const int64_t nb = prob * a.n_stride + s;
+        const int64_t dense = static_cast<int64_t>(prob) * a.N + s;
+        if (a.resid) a.resid[nb] = r;
+        if (a.c1) a.c1[nb] = cacc;
+        if (a.resid2) a.resid2[dense] = r;
+        if (a.c12) a.c12[dense] = cacc;
+      }
+      if (a.pair_count && lane == 0) atomicAdd(a.pair_count, static_cast<unsigned long long>(pairs));
+      if (colok) {
+        float* dst = a.xi_out + prob * a.xi_out_stride + static_cast<int64_t>(gs0 + cs) * D + cx * nv;
+        float* dst2 = a.xi_out2 ? a.xi_out2 + (static_cast<int64_t>(prob) * a.N + gs0 + cs) * D + cx * nv
+                                : nullptr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = coef_of(q, r);
+          if (c < nv) {
+            dst[c] = xb[r];
           if (dst2) dst2[c] = xb[r];
         }
       }
+    }
     }
   }
 }
@@ -2268,13 +2288,7 @@ hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, h
 template <int DIMS, int AS, bool BF16>
 hipError_t launch_wave_shape(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s,
                              KEvents ev) {
-  if (a.persistent) {
-    const void* fn = reinterpret_cast<const void*>(&project_wave_kernel<DIMS, AS, BF16>);
-    const int grid = std::min(total, resident_blocks(fn, threads, lds));
-    launch_k(project_wave_kernel<DIMS, AS, BF16>, dim3(grid), dim3(threads), lds, s, ev, a, total);
-  } else {
-    launch_k(project_wave_kernel<DIMS, AS, BF16>, dim3(total), dim3(threads), lds, s, ev, a, total);
-  }
+  launch_k(project_wave_kernel<DIMS, AS, BF16>, dim3(total), dim3(threads), lds, s, ev, a, total);
   return hipGetLastError();
 }
 
@@ -2356,8 +2370,14 @@ int wave_block_waves(const ProjArgs& a) {
   return 4;
 }
 
+// Whole-horizon shape: a block covers one group of 16 / axis_slots samples
+// per wave, or kWaveGroups groups per wave that its waves draw from a
+// counter (the third tiling field).
+constexpr int kWaveGroups = 4;
+
 int samples_per_block(const ProjArgs& a) {
-  return (a.row_tiles == 0 ? wave_block_waves(a) : 1) * (16 / a.axis_slots);
+  if (a.row_tiles == 0) return wave_block_waves(a) * (16 / a.axis_slots) * (a.persistent ? kWaveGroups : 1);
+  return 16 / a.axis_slots;
 }
 
 int project_threads(int K, int row_tiles) { return 64 * waves_for(K, row_tiles); }
@@ -2386,8 +2406,7 @@ hipError_t launch_project(const ProjArgs& a, int n_problems, hipStream_t s, hipE
     return hipErrorInvalidValue;
   if (a.resid_hist && n_problems != 1) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(a);
-  const int threads = a.row_tiles == 0 ? 64 * (a.S / (16 / a.axis_slots))
-                                       : project_threads(a.K, a.row_tiles);
+  const int threads = a.row_tiles == 0 ? 64 * wave_block_waves(a) : project_threads(a.K, a.row_tiles);
   const int total = n_problems * a.blocks_per_problem;
   if (total <= 0) return hipSuccess;
   const bool bf = a.bf16_iters > 0;
