@@ -152,6 +152,32 @@ def test_plan_batch_identical_across_tilings_and_graphs(P):
     prob.close()
 
 
+def test_plan_with_noise_identical_across_tilings(P):
+    """Supplied normals (the sampler's other input), 3D, a ragged last group
+    of samples: every shape, including the whole-horizon ones whose waves
+    draw and stage their own sample groups, gives the same plan bit for bit."""
+    say("tilings: 3D plan with supplied normals under every shape")
+    w = W.with_changes(W.C3, n_obs=24, n_steps=50, n_samples=150, n_proj=W.default_n_proj(150),
+                       n_elite=20, n_proj_iters=12, n_cem=2)
+    prob = P.Problem.from_workload(w)
+    bc, obs = W.scene(w, 0)
+    noise = t32(W.standard_normals(17, (w.n_cem, w.n_samples, w.D)))
+    cem = P.Cem(w.n_samples, w.n_cem, w.n_proj_iters, w.n_proj, w.n_elite)
+    results = {}
+    for c in prob.tiling_candidates():
+        prob.set_tiling(c)
+        mu, cov = t32(W.initial_mean(w)), t32(W.initial_cov(w))
+        out = prob.plan(t32(bc), t32(obs), cem, mu, cov, noise=noise)
+        torch.cuda.synchronize()
+        results[c] = (out["best_xi"].cpu().numpy(), out["xi_bar"].cpu().numpy(),
+                      mu.cpu().numpy(), cov.cpu().numpy())
+    ref = results[(4, 1, 0)]
+    for c, val in results.items():
+        for got, want in zip(val, ref):
+            np.testing.assert_array_equal(got, want, err_msg=f"tiling {c}")
+    prob.close()
+
+
 def test_autotuner_picks_a_candidate_and_keeps_results(P):
     say("tilings: autotuned projection equals the default shape")
     w = W.C2
