@@ -113,8 +113,8 @@ def measured_execution(kernel_ms):
     from the rocprofv3 SQ counter summary in profiles/ (null when the kernel
     sources changed since): MFMA instructions and their flops (2048 per
     16x16x4 FP32 MFMA), VALU instructions, the MFMA busy share of SIMD
-    cycles, and the VALU lane operations per second against one FP32 op per
-    lane and cycle."""
+    cycles, the VALU lane operations per second against one FP32 op per
+    lane and cycle, and the mean resident waves per CU (of 16)."""
     vals = profile_values(COUNTER_FILE)
     if not vals:
         return None
@@ -125,7 +125,12 @@ def measured_execution(kernel_ms):
     except (KeyError, ValueError):
         return None
     t = kernel_ms * 1e-3
+    try:
+        waves = float(vals["mean_waves_per_cu"])
+    except (KeyError, ValueError):
+        waves = None
     return {"mfma_instructions_per_launch": mfma, "mfma_flops_per_launch": mfma * 2048,
+            "mean_waves_per_cu": waves,
             "mfma_tflops": round(mfma * 2048 / t / 1e12, 3),
             "mfma_frac": round(mfma * 2048 / t / 1e12 / PEAK_FP32_TFLOPS, 4),
             "mfma_busy_frac": busy, "valu_instructions_per_launch": valu,
@@ -256,6 +261,9 @@ def roofline_entry(wl, n_samples_per_launch, avg_ms, launches, tiling, note, pai
             "dense_rows_frac": round(mfma / PEAK_FP32_TFLOPS, 4),
             "work": "algorithmic: dense AM-iteration flops per sample-iteration (evaluated or "
                     "proven zero) + evaluated obstacle pairs",
+            "frac_note": "the algorithmic work counts the rows the kernel proves zero and does not "
+                         "execute, so achieved can pass the peak; what the hardware executed, "
+                         "against its own peaks, is in `executed`",
             "timing": note}
 
 
