@@ -33,11 +33,12 @@
 // After the last iteration one more forward + push-out pass evaluates
 // r(xi_bar) and c1 = sum_t |a_t|^2, summed per sample in fixed t order.
 //
-// Tile shapes (AS, RT) and the persistent grid change only which lanes and
-// blocks do the work: every sample goes through the same operations in the
-// same order (per-column MFMA, per-16-step partials added in time-block order,
-// culled obstacles contribute exact zeros), so every shape gives bit-identical
-// results and the autotuner may pick any of them.
+// Tile shapes (AS, RT), the persistent grid and the groups a wave draws
+// change only which lanes, waves and blocks do the work: every sample goes
+// through the same operations in the same order (per-column MFMA,
+// per-16-step partials added in time-block order, culled obstacles
+// contribute exact zeros), so every shape gives bit-identical results and the
+// autotuner may pick any of them.
 #include "priest_internal.h"
 
 #include <hip/hip_ext.h>
@@ -2128,10 +2129,10 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   }
 }
 
-// Whole-horizon shape: one block of blockDim / 64 waves per tile of
-// (blockDim / 64) * 16 / AS samples of one problem; with a grid smaller
-// than `total` (persistent launch) blocks loop over tiles.  XCD-aware block
-// order as project_kernel.
+// Whole-horizon shape: one block of blockDim / 64 waves per tile of a.S
+// samples of one problem (one or four groups of 16 / AS samples per wave,
+// drawn by the waves from the tile's counter).  XCD-aware block order as
+// project_kernel.
 template <int DIMS, int AS, bool BF16>
 __global__ __launch_bounds__(1024) void project_wave_kernel(ProjArgs a, int total) {
   const int G = gridDim.x;
