@@ -1321,7 +1321,7 @@ __global__ __launch_bounds__(MAXT) void project_task_kernel(const ProjArgs* task
 // ---------------------------------------------------------------------------
 constexpr int kWaveMaxBlocks = 8;  // 16-step time blocks (n_steps <= 128)
 constexpr int kPlane = 68;         // floats per transpose plane: 64 lanes + 4 (conflict-free reads)
-constexpr int kWtabV4 = 6;         // float4 per lane and time block in the W table
+constexpr int kWtabV4 = 3;         // float4 per lane and time block in the W table
 
 struct WaveLayout {  // offsets into dynamic LDS, in floats
   int rec, wtab, wave, wave_floats, cache, cstride, mul, ctr, total;
@@ -1662,31 +1662,28 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   uint32_t* cwords = reinterpret_cast<uint32_t*>(wr + l.cache);
   const int cstride = l.cstride;  // cache words per time block
 
-  // W operands of every time block, once per block
+  // forward B operands of every time block, once per block: lane ll, row
+  // type d, coefficient chunk h -> W[16 tb + ll % 16][d][coefficient of
+  // chunk h, row ll / 16] (zero past the horizon and the coefficients)
   {
     float4* wt = reinterpret_cast<float4*>(sm + l.wtab);
     for (int e = tid; e < NB * kWtabV4 * 64; e += blockDim.x) {
-      const int ll = e & 63, i = (e >> 6) % kWtabV4, tb = (e >> 6) / kWtabV4;
+      const int ll = e & 63, d = (e >> 6) % kWtabV4, tb = (e >> 6) / kWtabV4;
+      const int t = 16 * tb + (ll & 15);
       float v[4];
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const int j = 4 * i + h;
-        int t, d, c;
-        if (j < 12) {  // forward B operand: W[t][d][coefficient of chunk j % 4, row ll / 16]
-          d = j >> 2;
-          t = 16 * tb + (ll & 15);
-          c = coef_of(ll >> 4, j & 3);
-        } else {       // right-hand-side A operand: W[t][d][coefficient of column ll % 16]
-          const int jj = j - 12;
-          d = jj >> 2;
-          t = 16 * tb + 4 * (ll >> 4) + (jj & 3);
-          c = coef_of((ll & 15) >> 2, ll & 3);
-        }
+        const int c = coef_of(ll >> 4, h);
         v[h] = (t < K && c < nv) ? a.W[(t * 3 + d) * nv + c] : 0.0f;
       }
       wt[e] = make_float4(v[0], v[1], v[2], v[3]);
     }
   }
+  // the right-hand-side A operand of this lane (time rows 4 q + 0..3 of a
+  // block, coefficient row of column `col`) is the forward operand of lane
+  // 16 (col / 4) + 4 q + jj, chunk col % 4: its float offsets in a table row
+  const float* wtf = reinterpret_cast<const float*>(wtab);
+  const int rhs_off = (16 * (col >> 2) + 4 * q) * 4 + (col & 3);
   float Am[4];
   const int crow = coef_of(col >> 2, col & 3);
 #pragma unroll
@@ -1971,7 +1968,8 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
               for (int d = 0; d < 3; ++d)
                 if (nz & (1u << d)) {
                   B[d] = *reinterpret_cast<const f4*>(wr + (d * 4 + (col & 3)) * kPlane + 16 * (col >> 2) + 4 * q);
-                  wa[d] = wtab[(tb * kWtabV4 + 3 + d) * 64 + lane];
+                  const float* wr0 = wtf + (tb * kWtabV4 + d) * 256 + rhs_off;
+                  wa[d] = make_float4(wr0[0], wr0[4], wr0[8], wr0[12]);
                 }
               wave_lds_sync();
               if (lowp) {
@@ -2366,7 +2364,7 @@ size_t wave_lds_bytes(const ProjArgs& a, int wpb) {
 // whose LDS (the block's W table and records, a region per wave) fits.
 int wave_block_waves(const ProjArgs& a) {
   const size_t limit = device_lds_limit();
-  for (int wpb : {16, 12, 8}) 
+  for (int wpb : {16, 12, 8})
     if (wave_lds_bytes(a, wpb) <= limit) return wpb;
   return 4;
 }
