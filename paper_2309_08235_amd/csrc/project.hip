@@ -1328,8 +1328,8 @@ struct WaveLayout {  // offsets into dynamic LDS, in floats
 };
 
 // rec: obstacle records; wtab: per time block and lane the 12 forward-row B
-// operands (rows P, Pdot, Pddot x 4 coefficient chunks) and the 12
-// right-hand-side A operands (row types x 4 time chunks); wave: per wave 12
+// operands (rows P, Pdot, Pddot x 4 coefficient chunks; the right-hand side
+// reads its A operands from them); wave: per wave 12
 // transpose planes (3 quantities x 4 column residues), which also stage the
 // wave's samples before it iterates (2 SPW D4 <= 768 floats), then per time
 // block its candidate cache: words 0..31 the box of each row of 16 lanes grown
