@@ -2119,10 +2119,10 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
           const int c = coef_of(q, r);
           if (c < nv) {
             dst[c] = xb[r];
-          if (dst2) dst2[c] = xb[r];
+            if (dst2) dst2[c] = xb[r];
+          }
         }
       }
-    }
     }
   }
 }
