@@ -264,31 +264,30 @@ __device__ __forceinline__ void uf_row_step(const float g[kMaxNV], int s, int ax
   if (first)
 #pragma unroll
     for (int e = 0; e < 6; ++e) bcv[e] = bc[ax * 6 + e];
+  // (guarded bodies rather than breaks, so that the loops unroll: xo and l
+  // stay in registers)
 #pragma unroll
   for (int r = 0; r < kMaxNV; ++r) {
-    if (r >= nv) break;
-    float acc = 0.0f;
+    if (r < nv) {
+      float acc = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kMaxNV; ++c) {
-      if (c >= nv) break;
-      acc = fmaf(M11[r * nv + c], u[c], acc);
-    }
-    float nx;
-    if (first) {
-      float h = 0.0f, c0 = 0.0f;
+      for (int c = 0; c < kMaxNV; ++c)
+        if (c < nv) acc = fmaf(M11[r * nv + c], u[c], acc);
+      float nx;
+      if (first) {
+        float h = 0.0f, c0 = 0.0f;
 #pragma unroll
-      for (int c = 0; c < kMaxNV; ++c) {
-        if (c >= nv) break;
-        h = fmaf(Pi[r * nv + c], x0[c], h);
+        for (int c = 0; c < kMaxNV; ++c)
+          if (c < nv) h = fmaf(Pi[r * nv + c], x0[c], h);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) c0 = fmaf(M12[r * 6 + e], bcv[e], c0);
+        nx = (h + c0) + acc;
+      } else {
+        nx = xo[r] + acc;
       }
-#pragma unroll
-      for (int e = 0; e < 6; ++e) c0 = fmaf(M12[r * 6 + e], bcv[e], c0);
-      nx = (h + c0) + acc;
-    } else {
-      nx = xo[r] + acc;
+      lam[base + r] = l[r];
+      xb[base + r] = nx;
     }
-    lam[base + r] = l[r];
-    xb[base + r] = nx;
   }
 }
 
