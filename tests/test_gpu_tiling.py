@@ -1,5 +1,6 @@
 """Every tile shape of the projection kernel (MFMA column packing, time blocks
-per wave, persistent grid) computes the same arithmetic per sample, so results
+per wave, persistent grid or sample groups drawn per wave) computes the same
+arithmetic per sample, so results
 must be bit-identical across shapes; the autotuner's pick is one of them.
 The default shape is pinned to the oracle by test_gpu_parity.py; one shape
 is also compared with the oracle here."""
@@ -40,6 +41,8 @@ CASES = [
     ("2d k200 m20", W.C2, dict(n_steps=200, n_obs=20, horizon=20.0), 45),
     ("2d k10 m4", W.C1, dict(n_steps=10), 19),
     ("3d k100 m128", W.C3, {}, 101),
+    ("3d k40 m0", W.C3, dict(n_steps=40, n_obs=0), 13),
+    ("2d k50 m8 n1", W.C1, dict(n_obs=8), 1),
 ]
 
 
