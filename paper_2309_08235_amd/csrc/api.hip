@@ -261,11 +261,15 @@ int32_t check_lds(const priest_problem* p, const ProjArgs& a) {
   return PRIEST_OK;
 }
 
+// Per problem: projected samples, residuals, costs, Cholesky factor, CMA
+// evolution path, status, the obstacle records of a projection launch whose
+// waves draw (problem, group) pairs (3 float4 per obstacle) and that
+// launch's counter (used in problem 0's block only).
 struct PlanLayout {
-  size_t xb, resid, c1, L, pc, status, per_problem;
+  size_t xb, resid, c1, L, pc, status, grec, gq, per_problem;
 };
 
-PlanLayout plan_layout(int D, int N) {
+PlanLayout plan_layout(int D, int N, int M) {
   PlanLayout l{};
   size_t o = 0;
   l.xb = o;     o += align256(sizeof(float) * static_cast<size_t>(N) * D);
@@ -274,6 +278,8 @@ PlanLayout plan_layout(int D, int N) {
   l.L = o;      o += align256(sizeof(float) * D * D);
   l.pc = o;     o += align256(sizeof(float) * D);
   l.status = o; o += align256(sizeof(int32_t));
+  l.grec = o;   o += align256(sizeof(float) * 12 * static_cast<size_t>(M));
+  l.gq = o;     o += align256(sizeof(int32_t));
   l.per_problem = o;
   return l;
 }
@@ -333,7 +339,7 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
                    uint32_t stream_base, const float* noise, const priest_plan_out* out, char* ws) {
   (void)P;
   const int D = p->D, N = c->n_samples;
-  const PlanLayout pl = plan_layout(D, N);
+  const PlanLayout pl = plan_layout(D, N, p->desc.n_obs);
   // per-problem workspace blocks are laid out [problem][...]: strides in floats
   const int64_t wstride = static_cast<int64_t>(pl.per_problem / sizeof(float));
   float* wxb = reinterpret_cast<float*>(ws + pl.xb);
@@ -396,6 +402,9 @@ PlanArgs plan_args(priest_problem* p, int32_t P, const float* bc, const float* o
   a.c1 = wc;
   a.n_stride = wstride;
   a.xi_src_stride = static_cast<int64_t>(N) * D;
+  a.grec = reinterpret_cast<float*>(ws + pl.grec);
+  a.grec_stride = wstride;
+  a.gq = reinterpret_cast<int32_t*>(ws + pl.gq);
   a.cost = CostArgs{c->cost.kind, c->cost.w_acc, c->cost.w_curv, c->cost.w_path,
                     c->cost.w_steer, c->cost.wheelbase, c->cost.eps};
   apply_tiling(a, tile_candidates(a.dims, a.K)[0]);
@@ -847,7 +856,7 @@ int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_par
   const int32_t st = validate_cem(c, p->desc.dims);
   if (st != PRIEST_OK) return st;
   if (n_problems < 1) return fail(PRIEST_ERR_INVALID, "n_problems must be >= 1");
-  *bytes = plan_layout(p->D, c->n_samples).per_problem * static_cast<size_t>(n_problems);
+  *bytes = plan_layout(p->D, c->n_samples, p->desc.n_obs).per_problem * static_cast<size_t>(n_problems);
   return PRIEST_OK;
 }
 

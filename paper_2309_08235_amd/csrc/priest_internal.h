@@ -81,6 +81,13 @@ struct ProjArgs {
   // per-iteration residual history [n_iter][N] (nullable; default shape, one
   // problem)
   float* resid_hist;
+  // whole-horizon shape drawing sample groups (persistent = 1): with these
+  // set, the launch first writes every problem's obstacle records to `grec`
+  // (3 M float4 per problem, stride in floats) and clears the group counter
+  // `gq`, and the waves of a grid of resident blocks draw (problem, group)
+  // pairs from it; nullable (then each block draws from a counter in LDS)
+  float* grec; int64_t grec_stride;
+  int32_t* gq;
 };
 
 // Arguments of the selection / refit / Cholesky kernel (one block per problem).

@@ -1642,7 +1642,7 @@ __device__ __forceinline__ uint32_t wave_block_push(const float4* rec, int M, fl
   return nz;
 }
 
-template <int DIMS, int AS, bool BF16>
+template <int DIMS, int AS, bool BF16, bool GQ>
 __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first, int stride, int total) {
   static_assert(AS == 4 || (AS == 2 && DIMS == 2), "2 axis slots only hold 2D samples");
   constexpr int SPW = 16 / AS;  // samples per wave
@@ -1705,37 +1705,59 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
 
   // The tile's groups of SPW samples are drawn by the block's waves from a
   // counter in LDS: a wave that finishes a group early takes the next one
-  // instead of idling until the slowest wave of the block is done.
+  // instead of idling until the slowest wave of the block is done.  With GQ
+  // the waves of every block draw (problem, group) pairs from one counter in
+  // global memory for the whole launch (total = the number of pairs), with
+  // the problems' obstacle records in global memory too, so no block waits
+  // for its waves before the end of the launch.
   int* ctr = reinterpret_cast<int*>(sm + l.ctr);
   float* sMu = sm + l.mul;
   float* sL = sMu + D4;
+  const int gpp = (a.N + SPW - 1) / SPW;  // groups per problem
+  // (the W table is complete before any wave reads it; without GQ the first
+  // barrier of the tile loop does this)
+  if constexpr (GQ) __syncthreads();
   int cur_prob = -1;
-  for (int tile = first; tile < total; tile += stride) {
-    const int prob = tile / a.blocks_per_problem;
-    const int s0 = (tile - prob * a.blocks_per_problem) * SPB;
-    const int ns = min(SPB, a.N - s0);
-    const int ngroups = (ns + SPW - 1) / SPW;
-    // (every wave is done with the previous tile: records, mean, factor and
-    // counter may change)
-    __syncthreads();
-    if (prob != cur_prob) {
-      build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
-      if (a.mode != kFromInput) {
-        const float* mu = a.mu + prob * a.mu_stride;
-        const float* Lm = a.L + prob * a.L_stride;
-        for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
-        for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
+  for (int tile = first; GQ ? tile == first : tile < total; tile += stride) {
+    int prob = 0, s0 = 0, ns = a.N, ngroups = 0;
+    if constexpr (!GQ) {
+      prob = tile / a.blocks_per_problem;
+      s0 = (tile - prob * a.blocks_per_problem) * SPB;
+      ns = min(SPB, a.N - s0);
+      ngroups = (ns + SPW - 1) / SPW;
+      // (every wave is done with the previous tile: records, mean, factor and
+      // counter may change)
+      __syncthreads();
+      if (prob != cur_prob) {
+        build_records<DIMS>(a.obs + prob * a.obs_stride, M, tid, blockDim.x, rec);
+        if (a.mode != kFromInput) {
+          const float* mu = a.mu + prob * a.mu_stride;
+          const float* Lm = a.L + prob * a.L_stride;
+          for (int i = tid; i < D; i += blockDim.x) sMu[i] = mu[i];
+          for (int i = tid; i < D * D; i += blockDim.x) sL[i] = Lm[i];
+        }
       }
+      cur_prob = prob;
+      if (tid == 0) *ctr = 0;
+      __syncthreads();
     }
-    cur_prob = prob;
-    if (tid == 0) *ctr = 0;
-    __syncthreads();
-    const float* bc = a.bc + prob * a.bc_stride;
+    (void)cur_prob;
     for (;;) {
       int gi = 0;
-      if (lane == 0) gi = atomicAdd(ctr, 1);
+      if (lane == 0) gi = atomicAdd(GQ ? a.gq : ctr, 1);
       gi = __builtin_amdgcn_readfirstlane(gi);
-      if (gi >= ngroups) break;
+      if constexpr (GQ) {
+        if (gi >= total) break;
+        prob = gi / gpp;
+        gi -= prob * gpp;
+      } else {
+        if (gi >= ngroups) break;
+      }
+      // this problem's obstacle records, mean and factor
+      const float4* recp = GQ ? reinterpret_cast<const float4*>(a.grec + prob * a.grec_stride) : rec;
+      const float* muP = GQ ? a.mu + prob * a.mu_stride : sMu;
+      const float* LP = GQ ? a.L + prob * a.L_stride : sL;
+      const float* bc = a.bc + prob * a.bc_stride;
       const int gs0 = s0 + gi * SPW;  // the group's first sample
       const int nsw = min(SPW, ns - gi * SPW);
       // the group's samples, staged in this wave's planes
@@ -1763,8 +1785,8 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
         for (int i = lane; i < nsw * D; i += 64) {
           const int s = i / D, d = i - s * D;
           const float* zz = sZ + s * D4;
-          const float* Lr = sL + d * D;
-          float x = sMu[d];
+          const float* Lr = LP + d * D;
+          float x = muP[d];
           for (int e = 0; e <= d; ++e) x = fmaf(Lr[e], zz[e], x);
           xs[s * D4 + d] = x;
         }
@@ -1796,7 +1818,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
       wave_lds_sync();
       // reuse slack of the candidate masks: the smallest cull radius of the scene
       float slack = INFINITY;
-      for (int j = lane; j < M; j += 64) slack = fminf(slack, rec[j].w);
+      for (int j = lane; j < M; j += 64) slack = fminf(slack, recp[j].w);
       slack = M > 0 ? wave_min(slack) : 1.0f;
 
       f4 xb = xi;
@@ -1886,7 +1908,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
           }
         }
         const float tmid = a.dt * (static_cast<float>(16 * tb) + 7.5f);
-        return wave_block_push<DIMS, LAST, NI>(rec, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
+        return wave_block_push<DIMS, LAST, NI>(recp, M, a.dt * static_cast<float>(t), tmid, thalf, slack,
                                                comp, test, ok, p, v, ac, a.vmax, a.amax, a.box, S,
                                                dv, da, r2, lane, cwords + tb * cstride, ncand, nok,
                                                pairs, wwv, wwa, pm, lcl);
@@ -2131,12 +2153,23 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
 // samples of one problem (one or four groups of 16 / AS samples per wave,
 // drawn by the waves from the tile's counter).  XCD-aware block order as
 // project_kernel.
-template <int DIMS, int AS, bool BF16>
+template <int DIMS, int AS, bool BF16, bool GQ>
 __global__ __launch_bounds__(1024) void project_wave_kernel(ProjArgs a, int total) {
   const int G = gridDim.x;
   int lb = blockIdx.x;
   if ((G & 7) == 0) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  project_wave_block<DIMS, AS, BF16>(a, lb, G, total);
+  project_wave_block<DIMS, AS, BF16, GQ>(a, lb, G, total);
+}
+
+// Before a launch that draws (problem, group) pairs from global memory: each
+// problem's obstacle records (one block per problem), and the counter set to
+// zero.
+template <int DIMS>
+__global__ void wave_records_kernel(ProjArgs a) {
+  const int prob = blockIdx.x;
+  build_records<DIMS>(a.obs + prob * a.obs_stride, a.M, threadIdx.x, blockDim.x,
+                      reinterpret_cast<float4*>(a.grec + prob * a.grec_stride));
+  if (prob == 0 && threadIdx.x == 0) *a.gq = 0;
 }
 
 // Per-row push-outs e(xi) - F xi, [N][M + 2][K][dims] (parity hook): one
@@ -2287,7 +2320,21 @@ hipError_t launch_shape(const ProjArgs& a, int total, int threads, size_t lds, h
 template <int DIMS, int AS, bool BF16>
 hipError_t launch_wave_shape(const ProjArgs& a, int total, int threads, size_t lds, hipStream_t s,
                              KEvents ev) {
-  launch_k(project_wave_kernel<DIMS, AS, BF16>, dim3(total), dim3(threads), lds, s, ev, a, total);
+  if (a.persistent && a.gq && a.grec && !a.traj) {
+    // one counter over every (problem, group) pair of the launch, drawn by
+    // the waves of a grid of resident blocks
+    const int P = total / a.blocks_per_problem;
+    const int pairs = P * ((a.N + 16 / AS - 1) / (16 / AS));
+    hipLaunchKernelGGL(wave_records_kernel<DIMS>, dim3(P), dim3(256), 0, s, a);
+    const void* fn = reinterpret_cast<const void*>(&project_wave_kernel<DIMS, AS, BF16, true>);
+    const int wpb = threads / 64;
+    const int grid = std::max(1, std::min((pairs + wpb - 1) / wpb, resident_blocks(fn, threads, lds)));
+    launch_k(project_wave_kernel<DIMS, AS, BF16, true>, dim3(grid), dim3(threads), lds, s, ev, a,
+             pairs);
+  } else {
+    launch_k(project_wave_kernel<DIMS, AS, BF16, false>, dim3(total), dim3(threads), lds, s, ev, a,
+             total);
+  }
   return hipGetLastError();
 }
 
