@@ -233,7 +233,9 @@ int32_t priest_project_unfused(priest_problem* p, const float* bc, const float* 
                                void* stream);
 
 /* Bytes of device workspace priest_plan / priest_plan_batch need for
- * n_problems problems with settings `c` (host call). */
+ * n_problems problems with settings `c` (host call): per problem the
+ * projected samples, residuals, costs, Cholesky factor, CMA path, status and
+ * 48 bytes per obstacle of precomputed obstacle records. */
 int32_t priest_plan_workspace_size(const priest_problem* p, const priest_cem_params* c,
                                    int32_t n_problems, size_t* bytes);
 
@@ -298,9 +300,12 @@ int32_t priest_plan_batch(priest_problem* p, int32_t n_problems, const float* bc
  * per wave, or every time block of the horizon in one wave (blocks of 16
  * waves, each with its own samples); one block per tile or a persistent grid
  * of resident blocks that loop over tiles (for the whole-horizon shape: one
- * group of samples per wave, or four per wave that the block's waves draw
- * from a shared counter, so that waves whose samples need fewer evaluations
- * take more of them).  Every shape gives bit-identical results.  By default the
+ * group of samples per wave, or groups that the waves draw from a counter, so
+ * that waves whose samples need fewer evaluations take more of them - four
+ * per wave from a counter per block, or, in the plan calls, whose workspace
+ * then also holds the obstacle records of every problem, from one counter
+ * over all (problem, group) pairs of the launch for a grid of resident
+ * blocks).  Every shape gives bit-identical results.  By default the
  * library times every candidate the first time a problem handle meets a new
  * (N, n_problems, sampling mode, precision) - one warm-up and two timed
  * launches of a shortened (<= 8 iteration) copy of the real launch, outputs
@@ -318,8 +323,9 @@ typedef struct priest_tiling {
                          or 2 in 2D; n_steps <= 128), no block barrier per iteration: for
                          batches large enough to fill the chip */
   int32_t persistent; /* 1: grid of resident blocks looping over tiles; with row_tiles 0:
-                         blocks of 4 sample groups per wave, drawn by the waves from a
-                         counter (one group per wave with 0) */
+                         sample groups drawn by the waves from a counter (4 per wave and
+                         block; in the plan calls one counter for the whole launch), one
+                         group per wave with 0 */
   int32_t reserved;   /* must be 0 */
 } priest_tiling;
 
