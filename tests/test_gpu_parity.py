@@ -252,6 +252,46 @@ def test_project_c3_full_batch_100_iterations(priest):
     gp.close()
 
 
+def test_plan_batch_c3_shared_counter_against_oracle(priest):
+    """The benchmark's batched plans at their configured size (64 problems x
+    2000 samples, M = 128, K = 100, 100 projection iterations), one CEM
+    iteration through priest_plan_batch with the whole-horizon shape whose
+    waves draw (problem, group) pairs from one counter for the whole launch
+    (obstacle records read from the plan workspace): the oracle projects 16
+    of the drawn samples of each of 4 problems, and the plan's projected
+    samples, residuals and costs must match them."""
+    wl = W.C3
+    P_, N = wl.n_problems, wl.n_samples
+    say(f"plan_batch c3 {P_} x {N}, shared counter, oracle on 4 x 16 samples")
+    gp, op = make(priest, wl)
+    gp.set_tiling((4, 0, 1))
+    scenes = [W.scene(wl, q) for q in range(P_)]
+    bc = np.stack([s[0] for s in scenes])
+    obs = np.stack([s[1] for s in scenes])
+    cem = priest.Cem(n_samples=N, n_cem=1, n_proj_iters=wl.n_proj_iters, n_proj=wl.n_proj,
+                     n_elite=wl.n_elite, sigma=wl.sigma, gamma=wl.gamma, cov_jitter=wl.cov_jitter)
+    mu = t32(np.stack([W.initial_mean(wl)] * P_))
+    cov = t32(np.stack([W.initial_cov(wl)] * P_))
+    out = gp.plan_batch(P_, t32(bc), t32(obs), cem, mu, cov, seed=11,
+                        out=gp.plan_outputs(cem, P_, full=True))
+    torch.cuda.synchronize()
+    assert gp.last_tiling()[0] == (4, 0, 1)
+    xi, got, gr, gc = (np64(out[k]) for k in ("xi", "xi_bar", "resid", "c1"))
+    counts = {}
+    rng = np.random.default_rng(4)
+    for q in (0, 21, 42, 63):
+        idx = rng.choice(N, 16, replace=False)
+        pr = O.project(op, bc[q], obs[q], xi[q, idx], wl.n_proj_iters)
+        err = check_projection(op, bc[q], obs[q], xi[q, idx].astype(np.float32), got[q, idx],
+                               pr.xi_bar, wl.n_proj_iters, label=f"c3 plan problem {q}",
+                               counts=counts)
+        assert np.median(err) < 1e-4, (q, np.median(err))
+        np.testing.assert_allclose(gr[q, idx], pr.resid, atol=2e-3 * max(1, pr.resid.max()))
+        np.testing.assert_allclose(gc[q, idx], O.smoothness_cost(op, pr.xi_bar), rtol=2e-3,
+                                   atol=1e-3)
+    gp.close()
+
+
 @pytest.mark.parametrize("n", [1, 3, 37])
 def test_project_ragged_batches(priest, n):
     say(f"project ragged N={n}")
