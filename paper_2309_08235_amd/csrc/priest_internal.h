@@ -162,7 +162,7 @@ int pick_tiling(const std::vector<float>& ms);
 
 // Unfused projection (unfused.hip): workspace layout in bytes and launcher.
 struct UnfusedLayout {
-  size_t pva, delta, r2, xb, lam, w16, cen, total;
+  size_t pva, delta, r2, xb, lam, w16, cen, g, total;
 };
 UnfusedLayout unfused_layout(int N, int K, int dims, int nv, int M);
 hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, float* resid,

@@ -305,10 +305,8 @@ constexpr int kUpdParts = 4;
 
 template <int NVP>
 __global__ __launch_bounds__(1024) void uf_update_tile(
-    const float4* __restrict__ w16, const float* __restrict__ M11, const float* __restrict__ Pi,
-    const float* __restrict__ M12, const float* __restrict__ bc, const float* __restrict__ delta,
-    const float* __restrict__ xi, float* __restrict__ xb, float* __restrict__ lam, int N, int K,
-    int nv, int dims, float rho, int first, int tiles) {
+    const float4* __restrict__ w16, const float* __restrict__ delta, float* __restrict__ gout,
+    int N, int K, int dims, int tiles) {
   extern __shared__ float4 swe[];  // [3K][16] W rows, then the partials [parts - 1][block rows][16]
   const int E = 3 * K, trows = kUfTile * dims, rows = tiles * trows;
   for (int j = threadIdx.x; j < E * 4; j += blockDim.x) swe[j] = w16[j];
@@ -357,11 +355,58 @@ __global__ __launch_bounds__(1024) void uf_update_tile(
     for (int c = 0; c < NVP; ++c) g[c] += red[((q - 1) * rows + rl) * NVP + c];
   const int r = tile * trows + rt;
   if (r >= N * dims) return;
-  float gg[kMaxNV];
+  float4* gr = reinterpret_cast<float4*>(gout + static_cast<int64_t>(r) * kMaxNV);
 #pragma unroll
-  for (int c = 0; c < kMaxNV; ++c) gg[c] = c < NVP ? g[c] : 0.0f;
-  uf_row_step(gg, r / dims, r - (r / dims) * dims, nv, dims, rho, first, M11, Pi, M12, bc, xi, xb,
-              lam);
+  for (int c4 = 0; c4 < NVP / 4; ++c4)
+    gr[c4] = make_float4(g[4 * c4], g[4 * c4 + 1], g[4 * c4 + 2], g[4 * c4 + 3]);
+}
+
+// The QP step of every (sample, axis) row from the g the streaming pass wrote:
+// 16 lanes per row, lane c forming entry c of the multiplier, of u and of the
+// new xi_bar (the same operations, in the same order, as uf_row_step), the
+// row's u shared through LDS.  Every old xi_bar and multiplier entry of a
+// row is read before the barrier, every new one written after it.
+__global__ __launch_bounds__(256) void uf_qp(const float* __restrict__ gin,
+                                             const float* __restrict__ M11,
+                                             const float* __restrict__ Pi,
+                                             const float* __restrict__ M12,
+                                             const float* __restrict__ bc,
+                                             const float* __restrict__ xi, float* __restrict__ xb,
+                                             float* __restrict__ lam, int N, int nv, int dims,
+                                             float rho, int first) {
+  __shared__ float su[256];  // u of the block's 16 rows
+  __shared__ float sm11[kMaxNV * kMaxNV];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x < nv * nv) sm11[threadIdx.x] = M11[threadIdx.x];
+  const int r = t >> 4, c = t & 15;
+  const bool live = r < N * dims && c < nv;
+  const int ax = r % dims;
+  const int64_t base = static_cast<int64_t>(r) * nv;  // row (sample r / dims, axis ax)
+  float l = 0.0f, u = 0.0f, xo = 0.0f;
+  if (live) {
+    const float gc = gin[static_cast<int64_t>(r) * kMaxNV + c];
+    l = lam[base + c] + rho * gc;
+    xo = xb[base + c];
+    u = first ? l + rho * gc : (xi[base + c] - xo) + l + rho * gc;
+  }
+  su[threadIdx.x] = u;
+  __syncthreads();
+  if (!live) return;
+  const float* ur = su + (threadIdx.x & ~15);
+  float acc = 0.0f;
+  for (int k = 0; k < nv; ++k) acc = fmaf(sm11[c * nv + k], ur[k], acc);
+  float nx;
+  if (first) {
+    float h = 0.0f, c0 = 0.0f;
+    for (int k = 0; k < nv; ++k) h = fmaf(Pi[c * nv + k], xi[base + k], h);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) c0 = fmaf(M12[c * 6 + e], bc[ax * 6 + e], c0);
+    nx = (h + c0) + acc;
+  } else {
+    nx = xo + acc;
+  }
+  lam[base + c] = l;
+  xb[base + c] = nx;
 }
 
 // Small batches: a group of `tpr` consecutive lanes (a power of two up to
@@ -462,6 +507,7 @@ UnfusedLayout unfused_layout(int N, int K, int dims, int nv, int M) {
   l.lam = o;   o += al(sizeof(float) * static_cast<size_t>(N) * dims * nv);
   l.w16 = o;   o += al(sizeof(float) * 3 * K * 16);
   l.cen = o;   o += al(sizeof(float) * 4 * (static_cast<size_t>(K) + 1) * M);
+  l.g = o;     o += al(sizeof(float) * kMaxNV * static_cast<size_t>(N) * dims);
   l.total = o;
   return l;
 }
@@ -477,6 +523,7 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
   float* lam = reinterpret_cast<float*>(ws + l.lam);
   float* w16 = reinterpret_cast<float*>(ws + l.w16);
   float4* cen = reinterpret_cast<float4*>(ws + l.cen);
+  float* gbuf = reinterpret_cast<float*>(ws + l.g);
   const int64_t nD = static_cast<int64_t>(N) * dims * nv;
   const int64_t items = static_cast<int64_t>((N + kUfTile - 1) / kUfTile) * kUfTile * K;
   const dim3 b256(256);
@@ -515,11 +562,15 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
   for (int k = 0; k < a.n_iter; ++k) {
     forward();
     push(false);
-    if (tpr == 1)
-      hipLaunchKernelGGL(nv <= 12 ? uf_update_tile<12> : uf_update_tile<16>, g_tiles, dim3(ut * kUfTile * dims * kUpdParts), lds_tile,
-                         s, reinterpret_cast<const float4*>(w16), a.M11, a.Pi, a.M12, a.bc, delta,
-                         xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, ut);
-    else
+    if (tpr == 1) {
+      // g = W^T delta per row, streamed; then the QP step per row
+      hipLaunchKernelGGL(nv <= 12 ? uf_update_tile<12> : uf_update_tile<16>, g_tiles,
+                         dim3(ut * kUfTile * dims * kUpdParts), lds_tile, s,
+                         reinterpret_cast<const float4*>(w16), delta, gbuf, N, K, dims, ut);
+      const dim3 g_rows(static_cast<unsigned>((static_cast<int64_t>(N) * dims * 16 + 255) / 256));
+      hipLaunchKernelGGL(uf_qp, g_rows, b256, 0, s, gbuf, a.M11, a.Pi, a.M12, a.bc, xi_in, xb,
+                         lam, N, nv, dims, a.rho, k == 0 ? 1 : 0);
+    } else
       hipLaunchKernelGGL(uf_update, g_upd, dim3(kUpdT), lds_upd, s,
                          reinterpret_cast<const float4*>(w16), a.M11, a.Pi, a.M12, a.bc, delta,
                          xi_in, xb, lam, N, K, nv, dims, a.rho, k == 0 ? 1 : 0, tpr);
