@@ -304,7 +304,7 @@ __device__ __forceinline__ void uf_row_step(const float g[kMaxNV], int s, int ax
 constexpr int kUpdParts = 4;
 
 template <int NVP>
-__global__ __launch_bounds__(1024) void uf_update_tile(
+__global__ __launch_bounds__(1024, 8) void uf_update_tile(
     const float4* __restrict__ w16, const float* __restrict__ delta, float* __restrict__ gout,
     int N, int K, int dims, int tiles) {
   extern __shared__ float4 swe[];  // [3K][16] W rows, then the partials [parts - 1][block rows][16]
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(1024) void uf_update_tile(
   // reads workspace and stores nothing)
   const float* dl = delta + static_cast<int64_t>(tile) * E * trows + part * trows + rt;
   const int64_t estride = static_cast<int64_t>(kUpdParts) * trows;
-  constexpr int kU = 16;  // loads in flight per lane
+  constexpr int kU = 8;  // loads in flight per lane (two blocks per CU)
   for (int i0 = 0; i0 < ne; i0 += kU) {
     float v[kU];
 #pragma unroll
