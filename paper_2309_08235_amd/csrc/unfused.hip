@@ -55,7 +55,7 @@ __device__ __forceinline__ int64_t soa(int d, int t, int s, int x, int K, int di
 // rows of 16 (zero-padded), are the same for every lane of a wave.
 constexpr int kFwdTC = 10;
 
-template <int DIMS>
+template <int DIMS, int NVP>
 __global__ __launch_bounds__(256) void uf_forward(const float* __restrict__ W,
                                                   const float* __restrict__ xb, int N, int K,
                                                   int nv, int n_chunk, float* __restrict__ pva) {
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void uf_forward(const float* __restrict__ W,
 #pragma unroll
       for (int ax = 0; ax < DIMS; ++ax) acc[ax] = 0.0f;
 #pragma unroll
-      for (int c4 = 0; c4 < 4; ++c4) {
+      for (int c4 = 0; c4 < NVP / 4; ++c4) {  // (NVP: coefficients rounded up to float4s)
         const float4 w = sw[(tl * 3 + d) * 4 + c4];
         const float wc[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -547,8 +547,13 @@ hipError_t launch_unfused(const ProjArgs& a, const float* xi_in, float* xi_out, 
                      a.dt, w16, cen);
   hipLaunchKernelGGL(uf_init, g_nD, b256, 0, s, xi_in, xb, lam, nD);
   auto forward = [&]() {
-    if (dims == 2) hipLaunchKernelGGL(uf_forward<2>, g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
-    else hipLaunchKernelGGL(uf_forward<3>, g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+    if (dims == 2) {
+      if (nv <= 12) hipLaunchKernelGGL((uf_forward<2, 12>), g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+      else hipLaunchKernelGGL((uf_forward<2, 16>), g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+    } else {
+      if (nv <= 12) hipLaunchKernelGGL((uf_forward<3, 12>), g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+      else hipLaunchKernelGGL((uf_forward<3, 16>), g_fwd, b256, 0, s, a.W, xb, N, K, nv, n_chunk, pva);
+    }
   };
   auto push = [&](bool last) {
     if (dims == 2) {
