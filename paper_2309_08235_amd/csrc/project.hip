@@ -1337,11 +1337,10 @@ struct WaveLayout {  // offsets into dynamic LDS, in floats
 // per obstacle group (static, moving; 64 bits each); mul: the problem's mean
 // and Cholesky factor (when the kernel draws the samples); ctr: the tile's
 // group counter.
-__host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int NB, int WPB, int SPW,
+__host__ __device__ inline WaveLayout wave_layout(int dims, int nv, int M, int NB, int WPB,
                                                   int mode) {
   WaveLayout l{};
   const int D = dims * nv, D4 = round4(D), G = (M + 63) / 64;
-  (void)SPW;
   int o = 0;
   l.rec = o;  o += 12 * M;
   l.wtab = o; o += NB * kWtabV4 * 64 * 4;
@@ -1652,7 +1651,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, WPB = blockDim.x >> 6;
   const int nv = a.nv, K = a.K, M = a.M, D = DIMS * nv, D4 = round4(D);
   const int NB = (K + 15) >> 4, SPB = a.S;  // samples per block: SPW per group, 1 or 4 groups per wave
-  const WaveLayout l = wave_layout(DIMS, nv, M, NB, WPB, SPW, a.mode);
+  const WaveLayout l = wave_layout(DIMS, nv, M, NB, WPB, a.mode);
   // column layout (MFMA state): col = AS * cs + cx, coefficient rows 4 q + r;
   // item layout (forward rows, push-outs): step ti of columns 4 q + 0..3
   const int q = lane >> 4, col = lane & 15, cs = col / AS, cx = col % AS, ti = lane & 15;
@@ -1717,7 +1716,7 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
   // (the W table is complete before any wave reads it; without GQ the first
   // barrier of the tile loop does this)
   if constexpr (GQ) __syncthreads();
-  int cur_prob = -1;
+  [[maybe_unused]] int cur_prob = -1;
   for (int tile = first; GQ ? tile == first : tile < total; tile += stride) {
     int prob = 0, s0 = 0, ns = a.N, ngroups = 0;
     if constexpr (!GQ) {
@@ -1741,7 +1740,6 @@ __device__ __forceinline__ void project_wave_block(const ProjArgs& a, int first,
       if (tid == 0) *ctr = 0;
       __syncthreads();
     }
-    (void)cur_prob;
     for (;;) {
       int gi = 0;
       if (lane == 0) gi = atomicAdd(GQ ? a.gq : ctr, 1);
@@ -2403,8 +2401,8 @@ size_t device_lds_limit() {
 }
 
 size_t wave_lds_bytes(const ProjArgs& a, int wpb) {
-  return sizeof(float) * static_cast<size_t>(wave_layout(a.dims, a.nv, a.M, (a.K + 15) / 16, wpb,
-                                                         16 / a.axis_slots, a.mode).total);
+  return sizeof(float) *
+         static_cast<size_t>(wave_layout(a.dims, a.nv, a.M, (a.K + 15) / 16, wpb, a.mode).total);
 }
 
 // Waves per block of the whole-horizon shape: the most (16, 12, 8 or 4)
